@@ -1,0 +1,139 @@
+"""FP64 CPU oracle of the MSFT forward model and its gradient -- test infrastructure.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may import
+this package.  The product library never loads it and shares no code with it.
+The arithmetic lives in ``msft_oracle.c`` (plain double-precision C written from
+Sec. 2 of the paper, Eqs. (1)-(9)); this module only marshals numpy arrays.
+
+Strength modes: 0 = MSFT (Eq. (9), incident field propagated by Eq. (8)),
+1 = BORN (undisturbed incident field, Eq. (1) with (5)), 2 = DENSITY (the two
+inputs are the real and imaginary parts of a scattering density, Eq. (1)).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+MSFT, BORN, DENSITY = 0, 1, 2
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "msft_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (FP64, no FMA contraction, OpenMP over pixels)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        d, i32, i64, p = ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+        lib.oracle_qmap.argtypes = [d, d, i32, p]
+        lib.oracle_grid.argtypes = [i32, d, p]
+        lib.oracle_strength.argtypes = [i32, i32, i32, i32, d, d, d, d, p, p, p]
+        lib.oracle_amplitude.argtypes = [i32, p, i64, i32, i32, i32, d, d, d, p, p]
+        lib.oracle_backward.argtypes = [i32, p, i64, p, p, i32, i32, i32, d, d, d, d,
+                                        p, p, p, i64, p, p]
+        for f in (lib.oracle_qmap, lib.oracle_grid, lib.oracle_strength,
+                  lib.oracle_amplitude, lib.oracle_backward):
+            f.restype = None
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def qmap(wavelength: float, theta_max_deg: float, n: int) -> np.ndarray:
+    """Transfer momentum of every pixel of a flat n x n detector, shape (n*n, 3)."""
+    out = np.empty((n * n, 3), np.float64)
+    _load().oracle_qmap(float(wavelength), float(theta_max_deg), int(n), _ptr(out))
+    return out
+
+
+def grid(n: int, d: float) -> np.ndarray:
+    """Voxel centres of n cells of pitch d, centred on the origin."""
+    out = np.empty(n, np.float64)
+    _load().oracle_grid(int(n), float(d), _ptr(out))
+    return out
+
+
+def strength(mode: int, delta, beta, pitch, wavelength: float) -> np.ndarray:
+    """Effective scattering strength w (complex128, same [x][y][z] shape as delta)."""
+    delta, beta = _f64(delta), _f64(beta)
+    nx, ny, nz = delta.shape
+    out = np.empty(delta.shape + (2,), np.float64)
+    dx, dy, dz = (float(v) for v in pitch)
+    _load().oracle_strength(int(mode), nx, ny, nz, dx, dy, dz, float(wavelength),
+                            _ptr(delta), _ptr(beta), _ptr(out))
+    return out[..., 0] + 1j * out[..., 1]
+
+
+def amplitude(q, w, pitch, method: int = 1) -> np.ndarray:
+    """A_p = sum_v w_v exp(-i q_p . r_v) for every row of q (complex128 vector)."""
+    q = _f64(q).reshape(-1, 3)
+    w = np.asarray(w)
+    nx, ny, nz = w.shape
+    wr = _f64(np.stack([w.real, w.imag], axis=-1))
+    out = np.empty((q.shape[0], 2), np.float64)
+    dx, dy, dz = (float(v) for v in pitch)
+    _load().oracle_amplitude(int(method), _ptr(q), q.shape[0], nx, ny, nz, dx, dy, dz,
+                             _ptr(wr), _ptr(out))
+    return out[:, 0] + 1j * out[:, 1]
+
+
+def backward(mode: int, q, g, A, delta, beta, pitch, wavelength: float, cols=None):
+    """dL/d delta and dL/d beta for a loss with dL/dI = g over the pixels q.
+
+    ``A`` are the oracle's own amplitudes of those pixels.  ``cols`` (flat a*ny+b
+    column indices) restricts the output to some columns; the result then has
+    shape (len(cols), nz), otherwise the shape of delta.
+    """
+    q = _f64(q).reshape(-1, 3)
+    g = _f64(g).reshape(-1)
+    A = np.asarray(A).reshape(-1)
+    Ar = _f64(np.stack([A.real, A.imag], axis=-1))
+    delta, beta = _f64(delta), _f64(beta)
+    nx, ny, nz = delta.shape
+    dx, dy, dz = (float(v) for v in pitch)
+    if cols is None:
+        colp, ncols, oshape = None, nx * ny, delta.shape
+    else:
+        cols = np.ascontiguousarray(cols, dtype=np.int64)
+        colp, ncols, oshape = _ptr(cols), cols.size, (cols.size, nz)
+    gd = np.empty(ncols * nz, np.float64)
+    gb = np.empty(ncols * nz, np.float64)
+    _load().oracle_backward(int(mode), _ptr(q), q.shape[0], _ptr(g), _ptr(Ar), nx, ny, nz,
+                            dx, dy, dz, float(wavelength), _ptr(delta), _ptr(beta),
+                            colp, ncols, _ptr(gd), _ptr(gb))
+    return gd.reshape(oshape), gb.reshape(oshape)
+
+
+def simulate(mode: int, wavelength: float, theta_max_deg: float, n: int, delta, beta,
+             pitch, pixels=None, method: int = 1):
+    """Intensity |A|^2 of the pixels ``pixels`` (flat j*n+i, default all) and A itself."""
+    q = qmap(wavelength, theta_max_deg, n)
+    if pixels is not None:
+        q = q[np.asarray(pixels, dtype=np.int64)]
+    w = strength(mode, delta, beta, pitch, wavelength)
+    A = amplitude(q, w, pitch, method)
+    return np.abs(A) ** 2, A

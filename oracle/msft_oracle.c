@@ -1,0 +1,314 @@
+/*
+ * FP64 reference oracle for the Multi-Slice Fourier Transform (MSFT) forward
+ * model and its gradient -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark may load this library.  The product path never calls it and shares
+ * no code, header or table with it.  Every routine is plain, slow, double
+ * precision C written from the paper's equations (Sec. 2 of "The Scatman",
+ * arXiv 2202.03411); OpenMP only splits independent pixels or columns over
+ * threads, it does not reorder any single sum.
+ *
+ * Equation numbers follow the paper: (1) first Born approximation, (2) slicing
+ * of the z integral, (3) Ewald-sphere q_z, (4) MSFT with the Ewald phase,
+ * (5)/(6) scattering strength from n^2 - 1, (7) n = 1 - delta + i beta,
+ * (8) projection-approximation propagation of the incident field,
+ * (9) main Scatman equation, I = |Psi|^2.
+ *
+ * Readings taken where the paper is silent (all listed in the design notes):
+ *  - Flat detector at unit distance, N x N pixels; tan(theta_max) is the outer
+ *    edge of the edge pixel, pixel centres at u_i = (2i + 1 - N) t / N.
+ *  - Exported transfer momentum q = k0 (khat_out - zhat); the amplitude is
+ *    A = sum_v w_v exp(-i q . r_v), which is the paper's exp(+i q_paper . r)
+ *    with q_paper = k_in - k_out (Fig. 3).
+ *  - The field reaching slice s is attenuated by slices 0..s-1 only
+ *    (E_{s=0} = E_0 in Eq. (9)): an exclusive prefix along +z.
+ *  - Proportionality constants are dropped: w = dV (n^2 - 1) T exactly.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_PI 3.14159265358979323846
+
+enum { ORACLE_MSFT = 0, ORACLE_BORN = 1, ORACLE_DENSITY = 2 };
+
+/* Wave number k0 = 2 pi / lambda. */
+static double oracle_k0(double wavelength) { return (2.0 * ORACLE_PI) / wavelength; }
+
+/*
+ * Pixel -> transfer momentum for a flat N x N detector (Sec. 3, Block 1; the
+ * Ewald relation of Eq. (3)).  Pixel p = j * N + i, i along detector x (u),
+ * j along detector y (v).  Output q[p][3] = (qx, qy, qz).  The direction of a
+ * pixel centre is (u, v, 1) / r with r = sqrt(u^2 + v^2 + 1); q = k0 (khat - zhat)
+ * so qz = k0 (1/r - 1), evaluated in the cancellation-free form -k0 s / (r (r + 1)).
+ */
+void oracle_qmap(double wavelength, double theta_max_deg, int32_t n, double* q)
+{
+    const double k0 = oracle_k0(wavelength);
+    const double t = tan((theta_max_deg * ORACLE_PI) / 180.0);
+    for (int32_t j = 0; j < n; ++j) {
+        const double v = ((double)(2 * j + 1 - n) * t) / (double)n;
+        for (int32_t i = 0; i < n; ++i) {
+            const double u = ((double)(2 * i + 1 - n) * t) / (double)n;
+            const double uu = u * u;
+            const double vv = v * v;
+            const double s = uu + vv;
+            const double r = sqrt(s + 1.0);
+            double* qp = q + 3 * ((int64_t)j * n + i);
+            qp[0] = (k0 * u) / r;
+            qp[1] = (k0 * v) / r;
+            qp[2] = -((k0 * s) / (r * (r + 1.0)));
+        }
+    }
+}
+
+/* Voxel centres of a grid of n cells with pitch d, centred on the origin. */
+void oracle_grid(int32_t n, double d, double* c)
+{
+    for (int32_t a = 0; a < n; ++a) c[a] = ((double)(2 * a + 1 - n) * d) / 2.0;
+}
+
+/*
+ * Effective scattering strength per voxel, w[(a*ny + b)*nz + c] as (re, im).
+ *   MSFT    : w = dV (n^2 - 1) E_s / (E_0 e^{i k0 s dz})  -- Eqs. (6)-(9).  With
+ *             Eq. (8) the ratio is prod_{s'<s} exp(-i k0 dz delta_s') exp(-k0 dz beta_s').
+ *   BORN    : w = dV (n^2 - 1), incident field undisturbed (Eq. (1) with (5)).
+ *   DENSITY : the two inputs are the real and imaginary parts of a scattering
+ *             density rho (Eq. (1)); w = dV rho.
+ * Inputs are [a][b][c] with c (z, the beam axis) fastest; the beam enters at c = 0.
+ */
+void oracle_strength(int32_t mode, int32_t nx, int32_t ny, int32_t nz,
+                     double dx, double dy, double dz, double wavelength,
+                     const double* delta, const double* beta, double* w)
+{
+    const double k0 = oracle_k0(wavelength);
+    const double dV = dx * dy * dz;
+    for (int32_t a = 0; a < nx; ++a) {
+        for (int32_t b = 0; b < ny; ++b) {
+            double sum_beta = 0.0, sum_delta = 0.0; /* over slices already passed */
+            for (int32_t c = 0; c < nz; ++c) {
+                const int64_t v = ((int64_t)a * ny + b) * nz + c;
+                const double d = delta[v], bt = beta[v];
+                double wr, wi;
+                if (mode == ORACLE_DENSITY) {
+                    wr = dV * d;
+                    wi = dV * bt;
+                } else {
+                    /* n = 1 - delta + i beta (Eq. (7)); chi = n^2 - 1. */
+                    const double nr = 1.0 - d, ni = bt;
+                    const double chi_r = (nr * nr - ni * ni) - 1.0;
+                    const double chi_i = 2.0 * nr * ni;
+                    double tr = 1.0, ti = 0.0;
+                    if (mode == ORACLE_MSFT) {
+                        const double mag = exp(-k0 * dz * sum_beta);
+                        const double ph = -k0 * dz * sum_delta;
+                        tr = mag * cos(ph);
+                        ti = mag * sin(ph);
+                    }
+                    wr = dV * (chi_r * tr - chi_i * ti);
+                    wi = dV * (chi_r * ti + chi_i * tr);
+                }
+                w[2 * v] = wr;
+                w[2 * v + 1] = wi;
+                sum_beta += bt;
+                sum_delta += d;
+            }
+        }
+    }
+}
+
+/*
+ * Scattered amplitude A_p = sum_v w_v exp(-i q_p . r_v) for an explicit list of
+ * npix momenta q[p][3]; A[p] as (re, im).  This is Eq. (9) with the 2D Fourier
+ * transform of every slice and the slice phase of Eq. (4) written as one sum.
+ *   method 0 (direct)    : one sin/cos of the full phase per voxel-pixel term.
+ *   method 1 (separable) : the same sum with exp(-i q.r) split exactly into
+ *                          exp(-i qx x) exp(-i qy y) exp(-i qz z) tables, summed
+ *                          z innermost, then y, then x.
+ */
+void oracle_amplitude(int32_t method, const double* q, int64_t npix,
+                      int32_t nx, int32_t ny, int32_t nz,
+                      double dx, double dy, double dz, const double* w, double* A)
+{
+    double* xs = (double*)malloc(sizeof(double) * (size_t)nx);
+    double* ys = (double*)malloc(sizeof(double) * (size_t)ny);
+    double* zs = (double*)malloc(sizeof(double) * (size_t)nz);
+    oracle_grid(nx, dx, xs);
+    oracle_grid(ny, dy, ys);
+    oracle_grid(nz, dz, zs);
+
+    #pragma omp parallel
+    {
+        double* ex = (double*)malloc(sizeof(double) * 2 * (size_t)nx);
+        double* ey = (double*)malloc(sizeof(double) * 2 * (size_t)ny);
+        double* ez = (double*)malloc(sizeof(double) * 2 * (size_t)nz);
+        #pragma omp for schedule(dynamic, 1)
+        for (int64_t p = 0; p < npix; ++p) {
+            const double qx = q[3 * p], qy = q[3 * p + 1], qz = q[3 * p + 2];
+            double ar = 0.0, ai = 0.0;
+            if (method == 0) {
+                for (int32_t a = 0; a < nx; ++a)
+                    for (int32_t b = 0; b < ny; ++b)
+                        for (int32_t c = 0; c < nz; ++c) {
+                            const int64_t v = ((int64_t)a * ny + b) * nz + c;
+                            const double ph = -(qx * xs[a] + qy * ys[b] + qz * zs[c]);
+                            const double kr = cos(ph), ki = sin(ph);
+                            ar += w[2 * v] * kr - w[2 * v + 1] * ki;
+                            ai += w[2 * v] * ki + w[2 * v + 1] * kr;
+                        }
+            } else {
+                for (int32_t a = 0; a < nx; ++a) { ex[2 * a] = cos(-qx * xs[a]); ex[2 * a + 1] = sin(-qx * xs[a]); }
+                for (int32_t b = 0; b < ny; ++b) { ey[2 * b] = cos(-qy * ys[b]); ey[2 * b + 1] = sin(-qy * ys[b]); }
+                for (int32_t c = 0; c < nz; ++c) { ez[2 * c] = cos(-qz * zs[c]); ez[2 * c + 1] = sin(-qz * zs[c]); }
+                for (int32_t a = 0; a < nx; ++a) {
+                    double sxr = 0.0, sxi = 0.0;
+                    for (int32_t b = 0; b < ny; ++b) {
+                        double syr = 0.0, syi = 0.0;
+                        const double* wc = w + 2 * (((int64_t)a * ny + b) * nz);
+                        for (int32_t c = 0; c < nz; ++c) {
+                            syr += wc[2 * c] * ez[2 * c] - wc[2 * c + 1] * ez[2 * c + 1];
+                            syi += wc[2 * c] * ez[2 * c + 1] + wc[2 * c + 1] * ez[2 * c];
+                        }
+                        sxr += syr * ey[2 * b] - syi * ey[2 * b + 1];
+                        sxi += syr * ey[2 * b + 1] + syi * ey[2 * b];
+                    }
+                    ar += sxr * ex[2 * a] - sxi * ex[2 * a + 1];
+                    ai += sxr * ex[2 * a + 1] + sxi * ex[2 * a];
+                }
+            }
+            A[2 * p] = ar;
+            A[2 * p + 1] = ai;
+        }
+        free(ex);
+        free(ey);
+        free(ez);
+    }
+    free(xs);
+    free(ys);
+    free(zs);
+}
+
+/*
+ * Gradient of a real loss L(I) with respect to the voxel delta and beta, given
+ * g[p] = dL/dI_p and the amplitudes A[p] of all npix pixels.
+ *
+ * Since I_p = |A_p|^2 and A_p is linear in w, dL = sum_v 2 Re(R_v dw_v) with
+ * R_v = sum_p g_p conj(A_p) exp(-i q_p . r_v).  The chain rule through Eq. (7)
+ * and the propagation of Eq. (8) then gives, for slice s of a column,
+ *   dL/d delta_s = 2 Re(R_s dV T_s dchi/ddelta) + 2 Re(-i k0 dz sum_{s'>s} R_s' w_s')
+ *   dL/d beta_s  = 2 Re(R_s dV T_s dchi/dbeta)  + 2 Re(  -k0 dz sum_{s'>s} R_s' w_s')
+ * with dchi/ddelta = -2 n and dchi/dbeta = 2 i n (n = 1 - delta + i beta).  The
+ * second terms are absent in the BORN and DENSITY modes; DENSITY has
+ * dw/ddelta = dV and dw/dbeta = i dV.
+ *
+ * cols[k] = a * ny + b selects the columns to differentiate (ncols of them);
+ * cols == NULL means every column.  Outputs gdelta/gbeta hold [k][c] for the
+ * selected columns, nz values each.
+ */
+void oracle_backward(int32_t mode, const double* q, int64_t npix,
+                     const double* g, const double* A,
+                     int32_t nx, int32_t ny, int32_t nz,
+                     double dx, double dy, double dz, double wavelength,
+                     const double* delta, const double* beta,
+                     const int64_t* cols, int64_t ncols,
+                     double* gdelta, double* gbeta)
+{
+    const double k0 = oracle_k0(wavelength);
+    const double dV = dx * dy * dz;
+    double* xs = (double*)malloc(sizeof(double) * (size_t)nx);
+    double* ys = (double*)malloc(sizeof(double) * (size_t)ny);
+    double* zs = (double*)malloc(sizeof(double) * (size_t)nz);
+    oracle_grid(nx, dx, xs);
+    oracle_grid(ny, dy, ys);
+    oracle_grid(nz, dz, zs);
+    const int64_t ncol_all = (int64_t)nx * ny;
+    const int64_t nsel = cols ? ncols : ncol_all;
+
+    #pragma omp parallel
+    {
+        double* R = (double*)malloc(sizeof(double) * 2 * (size_t)nz);
+        double* T = (double*)malloc(sizeof(double) * 2 * (size_t)nz);
+        double* wcol = (double*)malloc(sizeof(double) * 2 * (size_t)nz);
+        #pragma omp for schedule(dynamic, 1)
+        for (int64_t k = 0; k < nsel; ++k) {
+            const int64_t col = cols ? cols[k] : k;
+            const int32_t a = (int32_t)(col / ny), b = (int32_t)(col % ny);
+            const double* dcol = delta + col * nz;
+            const double* bcol = beta + col * nz;
+
+            /* incident-field ratio T_s and strength w_s along the column */
+            double sum_beta = 0.0, sum_delta = 0.0;
+            for (int32_t c = 0; c < nz; ++c) {
+                double tr = 1.0, ti = 0.0;
+                if (mode == ORACLE_MSFT) {
+                    const double mag = exp(-k0 * dz * sum_beta);
+                    const double ph = -k0 * dz * sum_delta;
+                    tr = mag * cos(ph);
+                    ti = mag * sin(ph);
+                }
+                T[2 * c] = tr;
+                T[2 * c + 1] = ti;
+                const double nr = 1.0 - dcol[c], ni = bcol[c];
+                const double chi_r = (nr * nr - ni * ni) - 1.0, chi_i = 2.0 * nr * ni;
+                wcol[2 * c] = dV * (chi_r * tr - chi_i * ti);
+                wcol[2 * c + 1] = dV * (chi_r * ti + chi_i * tr);
+                sum_beta += bcol[c];
+                sum_delta += dcol[c];
+            }
+
+            /* R_v = sum_p g_p conj(A_p) exp(-i q_p . r_v) */
+            for (int32_t c = 0; c < nz; ++c) {
+                double rr = 0.0, ri = 0.0;
+                for (int64_t p = 0; p < npix; ++p) {
+                    const double ph = -(q[3 * p] * xs[a] + q[3 * p + 1] * ys[b] + q[3 * p + 2] * zs[c]);
+                    const double kr = cos(ph), ki = sin(ph);
+                    const double hr = g[p] * A[2 * p], hi = -g[p] * A[2 * p + 1];
+                    rr += hr * kr - hi * ki;
+                    ri += hr * ki + hi * kr;
+                }
+                R[2 * c] = rr;
+                R[2 * c + 1] = ri;
+            }
+
+            for (int32_t c = 0; c < nz; ++c) {
+                const double rr = R[2 * c], ri = R[2 * c + 1];
+                double gd, gb;
+                if (mode == ORACLE_DENSITY) {
+                    gd = 2.0 * (rr * dV);
+                    gb = 2.0 * (-ri * dV);
+                } else {
+                    const double nr = 1.0 - dcol[c], ni = bcol[c];
+                    /* dw/ddelta (own) = dV T (-2 n), dw/dbeta (own) = dV T (2 i n) */
+                    const double tr = T[2 * c], ti = T[2 * c + 1];
+                    const double dd_r = dV * (tr * (-2.0 * nr) - ti * (-2.0 * ni));
+                    const double dd_i = dV * (tr * (-2.0 * ni) + ti * (-2.0 * nr));
+                    const double db_r = dV * (tr * (-2.0 * ni) - ti * (2.0 * nr));
+                    const double db_i = dV * (tr * (2.0 * nr) + ti * (-2.0 * ni));
+                    gd = 2.0 * (rr * dd_r - ri * dd_i);
+                    gb = 2.0 * (rr * db_r - ri * db_i);
+                    if (mode == ORACLE_MSFT) {
+                        /* later slices see this voxel through T */
+                        double sr = 0.0, si = 0.0;
+                        for (int32_t c2 = c + 1; c2 < nz; ++c2) {
+                            sr += R[2 * c2] * wcol[2 * c2] - R[2 * c2 + 1] * wcol[2 * c2 + 1];
+                            si += R[2 * c2] * wcol[2 * c2 + 1] + R[2 * c2 + 1] * wcol[2 * c2];
+                        }
+                        /* Re(-i k0 dz S) = k0 dz Im S ; Re(-k0 dz S) = -k0 dz Re S */
+                        gd += 2.0 * (k0 * dz * si);
+                        gb += 2.0 * (-k0 * dz * sr);
+                    }
+                }
+                gdelta[k * nz + c] = gd;
+                gbeta[k * nz + c] = gb;
+            }
+        }
+        free(R);
+        free(T);
+        free(wcol);
+    }
+    free(xs);
+    free(ys);
+    free(zs);
+}

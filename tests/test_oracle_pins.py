@@ -1,0 +1,398 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself.
+
+Each test checks the oracle against a closed form, an invariant, a special case
+that reduces to a library routine, or central finite differences, chosen so that
+a plausible slip in the oracle (a dropped factor, a wrong sign or index, an
+inclusive instead of an exclusive scan, transposed axes) fails at least one.
+Paper references are to "The Scatman" (arXiv 2202.03411).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2202_03411_amd import inputs
+
+LAM = 45.0
+K0 = 2.0 * math.pi / LAM
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+# ---------------------------------------------------------------------------
+# pixel -> q map (Eq. (3); flat detector reading)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,theta", [(16, 30.0), (17, 60.0), (64, 80.0), (5, 10.0)])
+def test_qmap_on_ewald_sphere(n, theta):
+    # elastic scattering: |k_out| = k0, i.e. |q + k0 zhat| = k0 (Eq. (3), Fig. 3)
+    q = oracle.qmap(LAM, theta, n)
+    kout = q + np.array([0.0, 0.0, K0])
+    assert np.allclose(np.linalg.norm(kout, axis=1), K0, rtol=1e-14, atol=0)
+    # scattering angle from q_z: q_z = k0 (cos(theta) - 1) <= 0 for the exported sign
+    assert np.all(q[:, 2] <= 0.0)
+
+
+@pytest.mark.parametrize("n,theta", [(16, 30.0), (17, 60.0), (9, 80.0)])
+def test_qmap_pixel_directions(n, theta):
+    # khat_out points at the pixel centre (u_i, v_j, 1) on a screen at unit distance;
+    # the outer edge of the edge pixel sits at tan(theta_max)
+    q = oracle.qmap(LAM, theta, n).reshape(n, n, 3)  # [j][i]
+    t = math.tan(math.radians(theta))
+    u = (2.0 * np.arange(n) + 1.0 - n) / n * t
+    kz = q[..., 2] + K0
+    assert np.allclose(q[..., 0] / kz, u[None, :], rtol=1e-13, atol=1e-15)
+    assert np.allclose(q[..., 1] / kz, u[:, None], rtol=1e-13, atol=1e-15)
+    assert math.isclose(u[-1] + t / n, t, rel_tol=1e-14)
+
+
+def test_qmap_mirror_exact_and_centre():
+    n = 33
+    q = oracle.qmap(LAM, 45.0, n).reshape(n, n, 3)
+    # mirroring the pixel index negates q_x bit-exactly and leaves q_y, q_z unchanged
+    assert np.array_equal(q[:, ::-1, 0], -q[:, :, 0])
+    assert np.array_equal(q[:, ::-1, 1], q[:, :, 1])
+    assert np.array_equal(q[:, ::-1, 2], q[:, :, 2])
+    assert np.array_equal(q[::-1, :, 1], -q[:, :, 1])
+    # odd N: the centre pixel looks straight along the beam, q = 0
+    assert np.all(q[n // 2, n // 2] == 0.0)
+
+
+def test_qmap_corner_angle():
+    # corner pixels of a flat detector see more than theta_max: cos(theta) = 1/r
+    n = 4096
+    q = oracle.qmap(LAM, 30.0, n)
+    cos_t = (q[:, 2] + K0) / K0
+    t = math.tan(math.radians(30.0))
+    uc = (n - 1.0) / n * t
+    assert math.isclose(math.degrees(math.acos(cos_t.min())),
+                        math.degrees(math.acos(1.0 / math.sqrt(1 + 2 * uc * uc))), rel_tol=1e-12)
+    assert 39.1 < math.degrees(math.acos(cos_t.min())) < 39.3
+
+
+def test_grid_centred():
+    for n, d in [(1, 3.0), (8, 2.5), (9, 4.7)]:
+        c = oracle.grid(n, d)
+        assert np.array_equal(c, -c[::-1])
+        assert np.allclose(np.diff(c), d, rtol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# scattering strength and the column scan (Eqs. (5)-(9))
+# ---------------------------------------------------------------------------
+
+def test_beer_lambert_exclusive():
+    # delta = 0 slab: the field amplitude entering slice k of the slab has decayed
+    # by exp(-k0 dz beta k) -- k slices passed, the slice itself not counted
+    nz, dz, b0 = 40, 3.0, 0.02
+    beta = np.zeros((1, 1, nz))
+    beta[0, 0, 5:30] = b0
+    delta = np.zeros_like(beta)
+    w = oracle.strength(oracle.MSFT, delta, beta, (2.0, 2.0, dz), LAM)[0, 0]
+    k = np.arange(25)
+    ratio = np.abs(w[5:30]) / abs(w[5])
+    assert np.allclose(ratio, np.exp(-K0 * dz * b0 * k), rtol=1e-13)
+    assert np.all(w[:5] == 0) and np.all(w[30:] == 0)
+
+
+def test_phase_delay_sign():
+    # beta = 0 slab: each passed slice retards the phase by k0 dz delta (Eq. (8))
+    nz, dz, d0 = 20, 2.0, 0.03
+    delta = np.full((1, 1, nz), d0)
+    beta = np.zeros_like(delta)
+    w = oracle.strength(oracle.MSFT, delta, beta, (1.0, 1.0, dz), LAM)[0, 0]
+    expect = np.exp(-1j * K0 * dz * d0 * np.arange(nz))
+    assert np.allclose(w / w[0], expect, rtol=0, atol=1e-13)
+    assert abs(abs(w[0]) - abs(1.0 * 2.0 * ((1 - d0) ** 2 - 1))) < 1e-15
+
+
+def test_strength_modes_special_cases():
+    rng = np.random.default_rng(1)
+    delta = rng.uniform(0, 0.05, (3, 4, 5))
+    beta = rng.uniform(0, 0.05, (3, 4, 5))
+    pitch = (1.5, 2.0, 2.5)
+    dV = 1.5 * 2.0 * 2.5
+    chi = (1 - delta + 1j * beta) ** 2 - 1
+    born = oracle.strength(oracle.BORN, delta, beta, pitch, LAM)
+    assert np.allclose(born, dV * chi, rtol=1e-14, atol=0)
+    dens = oracle.strength(oracle.DENSITY, delta, beta, pitch, LAM)
+    assert np.allclose(dens, dV * (delta + 1j * beta), rtol=1e-15, atol=0)
+    msft = oracle.strength(oracle.MSFT, delta, beta, pitch, LAM)
+    # first slice of every column sees the undisturbed plane wave
+    assert np.allclose(msft[:, :, 0], born[:, :, 0], rtol=1e-15, atol=0)
+    # vacuum (n = 1) does not scatter
+    z = oracle.strength(oracle.MSFT, np.zeros((2, 2, 3)), np.zeros((2, 2, 3)), pitch, LAM)
+    assert np.all(z == 0)
+
+
+def test_columns_independent_and_causal():
+    rng = np.random.default_rng(2)
+    delta = rng.uniform(0, 0.05, (3, 3, 12))
+    beta = rng.uniform(0, 0.05, (3, 3, 12))
+    w0 = oracle.strength(oracle.MSFT, delta, beta, (2, 2, 2), LAM)
+    d2 = delta.copy()
+    d2[1, 2, 6] += 0.1
+    w1 = oracle.strength(oracle.MSFT, d2, beta, (2, 2, 2), LAM)
+    diff = np.abs(w1 - w0) > 0
+    assert diff[1, 2, 6:].all()               # the voxel itself and everything behind it
+    assert not diff[1, 2, :6].any()           # nothing upstream of the change
+    diff[1, 2, :] = False
+    assert not diff.any()                     # no other column
+
+
+# ---------------------------------------------------------------------------
+# amplitude (Eq. (9)) against closed forms and library routines
+# ---------------------------------------------------------------------------
+
+def test_single_voxel():
+    # one voxel: |A|^2 = |w|^2 everywhere and arg A = arg w - q.r_v
+    nx, ny, nz = 5, 4, 6
+    pitch = (3.0, 4.0, 5.0)
+    delta = np.zeros((nx, ny, nz))
+    beta = np.zeros_like(delta)
+    a, b, c = 4, 1, 2
+    delta[a, b, c], beta[a, b, c] = 0.3, 0.1
+    w = oracle.strength(oracle.BORN, delta, beta, pitch, LAM)
+    q = oracle.qmap(LAM, 60.0, 12)
+    r = np.array([(2 * a + 1 - nx) * pitch[0] / 2, (2 * b + 1 - ny) * pitch[1] / 2,
+                  (2 * c + 1 - nz) * pitch[2] / 2])
+    for method in (0, 1):
+        A = oracle.amplitude(q, w, pitch, method)
+        assert np.allclose(np.abs(A), abs(w[a, b, c]), rtol=1e-13)
+        expect = w[a, b, c] * np.exp(-1j * (q @ r))
+        assert np.allclose(A, expect, rtol=0, atol=1e-13 * abs(w[a, b, c]))
+
+
+def _dirichlet(q, n, d, centre):
+    # sum_{m<n} exp(-i q (x0 + m d)) = exp(-i q centre) sin(n q d/2) / sin(q d/2)
+    s = np.sin(q * d / 2.0)
+    ratio = np.where(np.abs(s) < 1e-300, n, np.sin(n * q * d / 2.0) / np.where(s == 0, 1, s))
+    return np.exp(-1j * q * centre) * ratio
+
+
+def test_uniform_box_dirichlet_born():
+    nx, ny, nz = 9, 7, 6
+    pitch = (4.0, 5.0, 3.0)
+    box = ((1, 6), (2, 7), (0, 4))  # [start, stop) per axis, off-centre, non-cubic
+    d0, b0 = 0.02, 0.01
+    delta = np.zeros((nx, ny, nz))
+    beta = np.zeros_like(delta)
+    sl = tuple(slice(s, e) for s, e in box)
+    delta[sl], beta[sl] = d0, b0
+    w = oracle.strength(oracle.BORN, delta, beta, pitch, LAM)
+    q = oracle.qmap(LAM, 60.0, 10)
+    A = oracle.amplitude(q, w, pitch, 1)
+    dV = np.prod(pitch)
+    chi = (1 - d0 + 1j * b0) ** 2 - 1
+    expect = dV * chi
+    for ax, (s, e), n_ax in zip(range(3), box, (nx, ny, nz)):
+        cen = ((s + e - 1) - (n_ax - 1)) * pitch[ax] / 2.0
+        expect = expect * _dirichlet(q[:, ax], e - s, pitch[ax], cen)
+    assert np.allclose(A, expect, rtol=0, atol=1e-12 * np.abs(expect).max())
+
+
+def test_absorbing_box_geometric_series():
+    # MSFT: inside a uniform box the field ratio is a geometric sequence in z, so
+    # the z-sum is (1 - rho^nz)/(1 - rho) with rho = exp(-k0 dz (beta + i delta) - i qz dz)
+    nx, ny, nz = 6, 8, 10
+    pitch = (4.0, 3.0, 5.0)
+    box = ((0, 5), (2, 6), (3, 9))
+    d0, b0 = 0.03, 0.02
+    delta = np.zeros((nx, ny, nz))
+    beta = np.zeros_like(delta)
+    sl = tuple(slice(s, e) for s, e in box)
+    delta[sl], beta[sl] = d0, b0
+    w = oracle.strength(oracle.MSFT, delta, beta, pitch, LAM)
+    q = oracle.qmap(LAM, 60.0, 9)
+    dV = np.prod(pitch)
+    chi = (1 - d0 + 1j * b0) ** 2 - 1
+    expect = dV * chi + 0j
+    for ax in (0, 1):
+        s, e = box[ax]
+        n_ax = (nx, ny)[ax]
+        cen = ((s + e - 1) - (n_ax - 1)) * pitch[ax] / 2.0
+        expect = expect * _dirichlet(q[:, ax], e - s, pitch[ax], cen)
+    s, e = box[2]
+    dz = pitch[2]
+    z0 = (2 * s + 1 - nz) * dz / 2.0
+    rho = np.exp(-K0 * dz * (b0 + 1j * d0) - 1j * q[:, 2] * dz)
+    expect = expect * np.exp(-1j * q[:, 2] * z0) * (1 - rho ** (e - s)) / (1 - rho)
+    for method in (0, 1):
+        A = oracle.amplitude(q, w, pitch, method)
+        assert np.allclose(A, expect, rtol=0, atol=1e-12 * np.abs(expect).max())
+
+
+def test_q_zero_is_total_strength():
+    rng = np.random.default_rng(3)
+    delta = rng.uniform(0, 0.05, (4, 5, 6))
+    beta = rng.uniform(0, 0.05, (4, 5, 6))
+    w = oracle.strength(oracle.MSFT, delta, beta, (2.0, 3.0, 4.0), LAM)
+    q = oracle.qmap(LAM, 60.0, 7)
+    A = oracle.amplitude(q, w, (2.0, 3.0, 4.0), 1)
+    assert abs(A[24] - w.sum()) < 1e-13 * abs(w.sum())
+
+
+def test_small_angle_limit_is_fft2_of_projection():
+    # q_z -> 0 on the uniform Fourier grid: A is the 2D DFT of the projected strength
+    # (Sec. 1 and Fig. 3b), up to the phase ramp of the centred grid
+    rng = np.random.default_rng(4)
+    nx, ny, nz = 12, 10, 5
+    dx, dy, dz = 3.0, 2.0, 4.0
+    delta = rng.uniform(0, 0.05, (nx, ny, nz))
+    beta = rng.uniform(0, 0.05, (nx, ny, nz))
+    w = oracle.strength(oracle.MSFT, delta, beta, (dx, dy, dz), LAM)
+    kx, ky = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
+    q = np.stack([2 * np.pi * kx / (nx * dx), 2 * np.pi * ky / (ny * dy), np.zeros_like(kx, float)],
+                 axis=-1).reshape(-1, 3)
+    A = oracle.amplitude(q, w, (dx, dy, dz), 1).reshape(nx, ny)
+    F = np.fft.fft2(w.sum(axis=2))
+    ramp = np.exp(1j * np.pi * kx * (nx - 1) / nx) * np.exp(1j * np.pi * ky * (ny - 1) / ny)
+    assert np.allclose(A, ramp * F, rtol=0, atol=1e-12 * np.abs(F).max())
+
+
+def test_sphere_born_form_factor():
+    # homogeneous sphere, first Born: A(q) = V 3 (sin qR - qR cos qR)/(qR)^3
+    wl = inputs.sphere_workload(n=32, det_n=64)
+    R = wl.meta["radius"]
+    I, _ = oracle.simulate(oracle.DENSITY, wl.wavelength, wl.theta_max_deg, wl.det_n,
+                           wl.delta, wl.beta, wl.pitch)
+    q = oracle.qmap(wl.wavelength, wl.theta_max_deg, wl.det_n)
+    x = np.linalg.norm(q, axis=1) * R
+    V = float(wl.delta.sum()) * np.prod(wl.pitch)  # volume of the voxelized ball
+    Ian = (V * 3 * (np.sin(x) - x * np.cos(x)) / x ** 3) ** 2
+    assert _rel(I, Ian) < 1e-2
+    # in the wide-angle ring (theta > 3/4 theta_max) the Ewald q_z matters: the
+    # form factor of |q| fits, the one of |q_xy| alone (small-angle picture) does not
+    theta = np.degrees(np.arccos((q[:, 2] + 2 * np.pi / wl.wavelength) / (2 * np.pi / wl.wavelength)))
+    ring = theta > 0.75 * wl.theta_max_deg
+    xw = np.linalg.norm(q[:, :2], axis=1) * R
+    Iw = (V * 3 * (np.sin(xw) - xw * np.cos(xw)) / xw ** 3) ** 2
+    assert _rel(I[ring], Ian[ring]) < 0.1
+    assert _rel(I[ring], Iw[ring]) > 0.2
+
+
+def test_friedel_symmetry_and_its_breaking():
+    n = 16
+    q = oracle.qmap(LAM, 60.0, n)
+    mirror = (n * n - 1) - np.arange(n * n)  # (i, j) -> (n-1-i, n-1-j)
+    rng = np.random.default_rng(5)
+    # a real, single-slice object: I(q_xy) = I(-q_xy)
+    rho = rng.uniform(0, 1, (7, 6, 1))
+    w = oracle.strength(oracle.DENSITY, rho, np.zeros_like(rho), (5.0, 5.0, 5.0), LAM)
+    I = np.abs(oracle.amplitude(q, w, (5.0, 5.0, 5.0), 1)) ** 2
+    assert np.allclose(I, I[mirror], rtol=1e-12, atol=0)
+    # a real object that is not z-symmetric: at 60 deg the Ewald q_z breaks the symmetry
+    rho3 = rng.uniform(0, 1, (7, 6, 9))
+    rho3[:, :, 5:] = 0.0
+    w3 = oracle.strength(oracle.DENSITY, rho3, np.zeros_like(rho3), (20.0, 20.0, 20.0), LAM)
+    I3 = np.abs(oracle.amplitude(q, w3, (20.0, 20.0, 20.0), 1)) ** 2
+    assert _rel(I3[mirror], I3) > 1e-2
+    # ... while a z-mirror-symmetric real object keeps it
+    rho4 = rho3 + rho3[:, :, ::-1]
+    w4 = oracle.strength(oracle.DENSITY, rho4, np.zeros_like(rho4), (20.0, 20.0, 20.0), LAM)
+    I4 = np.abs(oracle.amplitude(q, w4, (20.0, 20.0, 20.0), 1)) ** 2
+    assert np.allclose(I4, I4[mirror], rtol=1e-11, atol=0)
+
+
+def test_translation_invariance():
+    rng = np.random.default_rng(6)
+    base = np.zeros((10, 9, 11))
+    blob = rng.uniform(0, 0.04, (5, 4, 6))
+    d1, d2 = base.copy(), base.copy()
+    d1[1:6, 2:6, 0:6] = blob
+    d2[4:9, 4:8, 5:11] = blob
+    q = oracle.qmap(LAM, 60.0, 12)
+    I = []
+    for d in (d1, d2):
+        w = oracle.strength(oracle.MSFT, d, d * 0.5, (4.0, 4.0, 4.0), LAM)
+        I.append(np.abs(oracle.amplitude(q, w, (4.0, 4.0, 4.0), 1)) ** 2)
+    assert np.allclose(I[0], I[1], rtol=1e-11, atol=0)
+
+
+def test_direct_equals_separable():
+    rng = np.random.default_rng(7)
+    delta = rng.uniform(0, 0.05, (6, 7, 8))
+    beta = rng.uniform(0, 0.05, (6, 7, 8))
+    w = oracle.strength(oracle.MSFT, delta, beta, (9.0, 8.0, 7.0), LAM)
+    q = oracle.qmap(LAM, 60.0, 14)
+    A0 = oracle.amplitude(q, w, (9.0, 8.0, 7.0), 0)
+    A1 = oracle.amplitude(q, w, (9.0, 8.0, 7.0), 1)
+    assert np.allclose(A0, A1, rtol=0, atol=1e-12 * np.abs(A1).max())
+
+
+# ---------------------------------------------------------------------------
+# gradient against central finite differences
+# ---------------------------------------------------------------------------
+
+def _fd_setup(seed):
+    rng = np.random.default_rng(seed)
+    shape = (5, 4, 7)
+    delta = rng.uniform(0.0, 0.05, shape)
+    beta = rng.uniform(0.0, 0.05, shape)
+    pitch = (6.0, 7.0, 5.0)
+    q = oracle.qmap(LAM, 60.0, 8)
+    return rng, delta, beta, pitch, q
+
+
+@pytest.mark.parametrize("mode", [oracle.MSFT, oracle.BORN, oracle.DENSITY])
+def test_backward_linear_loss_fd(mode):
+    rng, delta, beta, pitch, q = _fd_setup(10 + mode)
+    g = rng.normal(size=q.shape[0])
+
+    def loss(d, b):
+        w = oracle.strength(mode, d, b, pitch, LAM)
+        return float(g @ (np.abs(oracle.amplitude(q, w, pitch, 1)) ** 2))
+
+    w = oracle.strength(mode, delta, beta, pitch, LAM)
+    A = oracle.amplitude(q, w, pitch, 1)
+    gd, gb = oracle.backward(mode, q, g, A, delta, beta, pitch, LAM)
+    h = 1e-6
+    for idx in [(0, 0, 0), (2, 1, 3), (4, 3, 6), (1, 2, 5), (3, 0, 1)]:
+        for arr, grad in ((delta, gd), (beta, gb)):
+            p, m = arr.copy(), arr.copy()
+            p[idx] += h
+            m[idx] -= h
+            fd = (loss(p, beta) - loss(m, beta)) / (2 * h) if arr is delta else \
+                 (loss(delta, p) - loss(delta, m)) / (2 * h)
+            assert abs(fd - grad[idx]) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(grad).max())
+
+
+def test_backward_log_loss_fd_and_columns():
+    rng, delta, beta, pitch, q = _fd_setup(20)
+    tgt = np.abs(rng.normal(size=q.shape[0])) * 10.0
+    eps = 1e-6
+
+    def intens(d, b):
+        w = oracle.strength(oracle.MSFT, d, b, pitch, LAM)
+        return np.abs(oracle.amplitude(q, w, pitch, 1)) ** 2
+
+    def loss(d, b):
+        return float(np.mean((np.log(intens(d, b) + eps) - np.log(tgt + eps)) ** 2))
+
+    I = intens(delta, beta)
+    g = 2.0 * (np.log(I + eps) - np.log(tgt + eps)) / (I + eps) / I.size
+    w = oracle.strength(oracle.MSFT, delta, beta, pitch, LAM)
+    A = oracle.amplitude(q, w, pitch, 1)
+    gd, gb = oracle.backward(oracle.MSFT, q, g, A, delta, beta, pitch, LAM)
+    h = 1e-7
+    for idx in [(0, 1, 0), (3, 2, 4), (4, 0, 6)]:
+        p, m = delta.copy(), delta.copy()
+        p[idx] += h
+        m[idx] -= h
+        fd = (loss(p, beta) - loss(m, beta)) / (2 * h)
+        assert abs(fd - gd[idx]) <= 1e-5 * abs(fd) + 1e-9
+        p, m = beta.copy(), beta.copy()
+        p[idx] += h
+        m[idx] -= h
+        fd = (loss(delta, p) - loss(delta, m)) / (2 * h)
+        assert abs(fd - gb[idx]) <= 1e-5 * abs(fd) + 1e-9
+    # the column-restricted form returns the same numbers
+    cols = np.array([3, 9, 17], dtype=np.int64)
+    cd, cb = oracle.backward(oracle.MSFT, q, g, A, delta, beta, pitch, LAM, cols=cols)
+    ny = delta.shape[1]
+    for k, col in enumerate(cols):
+        assert np.array_equal(cd[k], gd[col // ny, col % ny])
+        assert np.array_equal(cb[k], gb[col // ny, col % ny])
