@@ -1,0 +1,227 @@
+#!/usr/bin/env python3
+"""MSFT forward-model benchmark on one MI355X.
+
+Workload: a star-shaped harmonic body (l <= 6, R0 = 200 nm, delta = 0.01,
+beta = 0.02) on a 128^3 voxel grid, lambda = 45 nm, flat 512 x 512 detector to
+60 deg.  One step = one pattern through the whole forward path: column scan,
+MFMA contraction with the fused y/z reduction, |A|^2.  Inputs are resident in
+HBM before timing starts.  Prints ONE JSON line.
+
+Reported beside the headline (FP32, one pattern per launch):
+  - the BF16 hi+lo split contraction,
+  - a batch of patterns in one persistent launch against the same patterns
+    launched one by one,
+  - the dominant kernel against the FP32 matrix-core roofline (HIP events on
+    the stream the kernel runs on),
+  - the FP64 CPU oracle timed on a bounded pixel sample (cpu_baseline).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "MSFT patterns/s at 128³ grid, 512² detector (FP32 vs BF16-split vs plain); p99 ms"
+PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2500.0}   # MI355X dense matrix peaks
+HBM_PEAK_GBS = 8000.0
+
+
+def _pct(xs, p):
+    xs = sorted(xs)
+    k = min(len(xs) - 1, max(0, int(round(p / 100.0 * (len(xs) - 1)))))
+    return xs[k]
+
+
+def time_single(msft, torch, plan, d, b, steps, warmup):
+    """Time `steps` patterns, one msft_simulate_scan + msft_simulate_contract pair each."""
+    ws = plan.workspace()
+    I = torch.empty(plan.npix, dtype=torch.float32, device="cuda")
+    for _ in range(warmup):
+        msft.msft_simulate(plan.handle, d, b, I, None, ws)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ev[k][0].record()
+        msft.msft_simulate_scan(plan.handle, d, b, ws)
+        ev[k][1].record()
+        msft.msft_simulate_contract(plan.handle, ws, I, None)
+        ev[k][2].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = [e[0].elapsed_time(e[2]) for e in ev]
+    scan_ms = [e[0].elapsed_time(e[1]) for e in ev]
+    contract_ms = [e[1].elapsed_time(e[2]) for e in ev]
+    return {"wall_s": wall, "step_ms": step_ms, "scan_ms": scan_ms, "contract_ms": contract_ms,
+            "intensity": I}
+
+
+def time_batch(msft, torch, plan, ds, bs, steps, warmup):
+    """The same patterns: one persistent launch for all, then one launch each."""
+    n = len(ds)
+    outs = [torch.empty(plan.npix, dtype=torch.float32, device="cuda") for _ in range(n)]
+    reqs = [(plan.handle, ds[k], bs[k], outs[k], None) for k in range(n)]
+    wsb = msft.workspace_tensor(msft.msft_batch_query(reqs), "cuda")
+    ws = plan.workspace()
+    for _ in range(warmup):
+        msft.msft_simulate_batch(reqs, wsb)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        msft.msft_simulate_batch(reqs, wsb)
+    e1.record()
+    torch.cuda.synchronize()
+    batched_ms = e0.elapsed_time(e1) / steps
+    e0.record()
+    for _ in range(steps):
+        for k in range(n):
+            msft.msft_simulate(plan.handle, ds[k], bs[k], outs[k], None, ws)
+    e1.record()
+    torch.cuda.synchronize()
+    plain_ms = e0.elapsed_time(e1) / steps
+    return batched_ms, plain_ms
+
+
+def cpu_baseline(wl, target_s):
+    """Time the FP64 oracle on a seeded pixel sample of the same pattern."""
+    import numpy as np
+
+    import oracle
+    from paper_2202_03411_amd import inputs
+
+    q = oracle.qmap(wl.wavelength, wl.theta_max_deg, wl.det_n)
+    P = q.shape[0]
+    t = time.perf_counter()
+    w = oracle.strength(wl.mode, wl.delta.astype(np.float64), wl.beta.astype(np.float64), wl.pitch,
+                        wl.wavelength)
+    t_strength = time.perf_counter() - t
+    cal = inputs.random_pixels(wl.det_n, 512, seed=5)
+    t = time.perf_counter()
+    oracle.amplitude(q[cal], w, wl.pitch, 1)
+    per_px = (time.perf_counter() - t) / cal.size
+    n = int(min(P, max(512, target_s / max(per_px, 1e-9))))
+    pix = inputs.random_pixels(wl.det_n, n, seed=6)
+    t = time.perf_counter()
+    oracle.amplitude(q[pix], w, wl.pitch, 1)
+    dt = time.perf_counter() - t
+    sec_per_pattern = t_strength + dt * P / n
+    return {"value": 1.0 / sec_per_pattern, "unit": "patterns/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"{n} of {P} seeded pixels of the same pattern (separable FP64 sum, "
+                      f"{dt:.1f} s) plus the full column scan, scaled to one whole pattern"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=8, help="patterns per persistent batch launch")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["fp32", "bf16x3"], default=None,
+                    help="time one precision only (profiling runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the forward model shards by pattern, so N GPUs would run N independent copies)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2202_03411_amd import inputs, msft
+
+    wl = inputs.pattern_workload()
+    P = wl.det_n ** 2
+    V = int(np.prod(wl.grid))
+    flops = 8.0 * P * V     # one complex multiply-add per voxel-pixel term
+    d = torch.from_numpy(wl.delta).cuda()
+    b = torch.from_numpy(wl.beta).cuda()
+    print(f"[bench] workload {wl.name} grid {wl.grid} det {wl.det_n}^2, {P * V:.3e} terms/pattern",
+          file=sys.stderr, flush=True)
+
+    results = {}
+    precisions = [args.only] if args.only else ["fp32", "bf16x3"]
+    for prec in precisions:
+        with msft.Plan.for_workload(wl, prec) as plan:
+            r = time_single(msft, torch, plan, d, b, args.steps, args.warmup)
+            ms = sum(r["step_ms"]) / len(r["step_ms"])
+            cms = sum(r["contract_ms"]) / len(r["contract_ms"])
+            sms = sum(r["scan_ms"]) / len(r["scan_ms"])
+            res = {"ms_per_step": ms, "patterns_per_s": 1000.0 / ms,
+                   "p50_ms": _pct(r["step_ms"], 50), "p99_ms": _pct(r["step_ms"], 99),
+                   "contract_ms": cms, "scan_ms": sms, "wall_s": r["wall_s"],
+                   "terms_per_s": P * V / (ms * 1e-3),
+                   "contract_tflops": flops / (cms * 1e-3) / 1e12,
+                   "resident_bytes": plan.resident_bytes, "workspace_bytes": plan.workspace_bytes}
+            print(f"[bench] {prec}: {ms:.3f} ms/pattern (contract {cms:.3f} ms, scan {sms:.4f} ms), "
+                  f"{res['contract_tflops']:.1f} TFLOP/s algorithmic", file=sys.stderr, flush=True)
+            if args.batch > 1 and not args.only:
+                ds = [torch.roll(d, shifts=k, dims=0) for k in range(args.batch)]
+                bs = [torch.roll(b, shifts=k, dims=0) for k in range(args.batch)]
+                bms, pms = time_batch(msft, torch, plan, ds, bs, max(2, args.steps // args.batch),
+                                      1)
+                res["batched"] = {"patterns": args.batch, "ms_per_batch": bms,
+                                  "patterns_per_s": args.batch * 1000.0 / bms,
+                                  "plain_ms_per_batch": pms,
+                                  "plain_patterns_per_s": args.batch * 1000.0 / pms}
+                print(f"[bench] {prec}: batch of {args.batch}: {bms:.2f} ms vs {pms:.2f} ms plain",
+                      file=sys.stderr, flush=True)
+            results[prec] = res
+
+    head = results.get("fp32") or results[precisions[0]]
+    head_prec = "fp32" if "fp32" in results else precisions[0]
+    # scan: delta and beta in (8 B per voxel), w out in the tile layout (8 B per voxel:
+    # FP32 re/im, or BF16 hi/lo re/im)
+    scan_bytes = 16.0 * V
+    line = {
+        "metric": METRIC,
+        "value": head["patterns_per_s"],
+        "unit": "patterns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if head_prec == "fp32" else "bf16x3",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "grid": list(wl.grid), "detector": [wl.det_n, wl.det_n],
+                   "wavelength_nm": wl.wavelength, "theta_max_deg": wl.theta_max_deg,
+                   "pitch_nm": wl.pitch[0], "precision": head_prec, "launch": "one pattern per launch"},
+        "p50_ms": head["p50_ms"],
+        "p99_ms": head["p99_ms"],
+        "terms_per_s": head["terms_per_s"],
+        "roofline": {"bound": "mfma", "achieved": head["contract_tflops"],
+                     "peak": PEAK_TFLOPS[head_prec], "unit": "TFLOP/s",
+                     "frac": head["contract_tflops"] / PEAK_TFLOPS[head_prec], "traffic": None,
+                     "kernel": f"fwd_kernel<{head_prec}>",
+                     "per_launch": f"{flops:.4e} algorithmic flops (8 per voxel-pixel term)"},
+        "scan": {"ms": head["scan_ms"], "gbs": scan_bytes / (head["scan_ms"] * 1e-3) / 1e9,
+                 "frac_hbm": scan_bytes / (head["scan_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "variants": results,
+    }
+    for v in line["variants"].values():
+        v.pop("intensity", None)
+    if "bf16x3" in results:
+        r = results["bf16x3"]
+        r["roofline_frac_bf16_peak_algorithmic"] = r["contract_tflops"] / PEAK_TFLOPS["bf16x3"]
+        r["roofline_frac_bf16_peak_executed"] = 3 * r["contract_tflops"] / PEAK_TFLOPS["bf16x3"]
+    if not args.no_cpu_baseline and not args.only:
+        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

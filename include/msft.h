@@ -1,0 +1,212 @@
+/*
+ * msft.h -- C ABI of the MI355X (gfx950) Multi-Slice Fourier Transform library.
+ *
+ * The library computes the wide-angle coherent diffraction pattern of a voxel
+ * map of the complex refractive index n = 1 - delta + i beta (Eq. (7) of "The
+ * Scatman", arXiv 2202.03411) on a flat N x N detector:
+ *
+ *   T_s  = exp(-k0 dz sum_{s'<s} (beta_s' + i delta_s'))      incident field ratio, Eq. (8)
+ *   w    = dV (n^2 - 1) T                                      effective strength, Eqs. (6), (9)
+ *   A_p  = sum_{x,y,z} w(x,y,z) exp(-i q_p . r)                 Eq. (9), all slices summed
+ *   I_p  = |A_p|^2                                             Sec. 2, measured intensity
+ *
+ * with k0 = 2 pi / lambda and q_p = k0 (khat_p - zhat) the transfer momentum of
+ * pixel p on the Ewald sphere (Eq. (3)).  The paper writes the kernel as
+ * exp(+i q . r) with q = k_in - k_out (Fig. 3); that is the same number, since the
+ * exported q here is k_out - k_in.
+ *
+ * Conventions shared by every call:
+ *  - Lengths share one arbitrary unit (Sec. 5.1); wavelength, pitches and
+ *    q (inverse length) are double precision.
+ *  - Voxel arrays are float32 [nx][ny][nz] row-major, z fastest; z is the beam
+ *    axis and the beam enters at iz = 0.  Voxel centres are
+ *    x_a = (2a + 1 - nx) dx / 2 (likewise y, z): the grid is centred on the origin.
+ *  - Detector: a flat screen at unit distance, normal to the beam, N x N square
+ *    pixels of equal size; tan(theta_max) is the outer edge of the edge pixel,
+ *    so pixel centres are u_i = (2i + 1 - N) tan(theta_max) / N (same for v_j) and
+ *    corner pixels see angles beyond theta_max.  Pixel p = j * N + i, i along x.
+ *  - Output arrays: intensity float32 [P]; amplitude complex64 [P] as
+ *    interleaved (re, im) float pairs.  P = N * N, or the length of an explicit
+ *    q list.
+ *  - Every device pointer is owned by the caller; the library never frees one.
+ *    A plan owns its own device tables and frees them in msft_plan_destroy.
+ *  - Calls taking a stream are asynchronous on it (a hipStream_t passed as
+ *    void*, NULL = the null stream).  Argument errors are returned
+ *    synchronously and nothing is launched; device faults surface at the next
+ *    synchronising call.  No C++ exception crosses this interface.
+ *  - A plan is immutable after creation and may be used from several streams.
+ *    Calls that share a workspace must not overlap.
+ */
+#ifndef MSFT_H
+#define MSFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MSFT_OK = 0,
+    MSFT_ERR_INVALID = 1,       /* bad argument, geometry or handle */
+    MSFT_ERR_UNDERSAMPLED = 2,  /* pitch * max|q| > pi on some axis (see MSFT_ALLOW_ALIAS) */
+    MSFT_ERR_NOMEM = 3,         /* device or host allocation failed */
+    MSFT_ERR_DEVICE = 4,        /* a HIP runtime call failed */
+    MSFT_ERR_BUSY = 5,          /* workspace too small for the batch */
+    MSFT_ERR_UNSUPPORTED = 6    /* the plan cannot run this call (host-only plan, ...) */
+} msft_status;
+
+/* Arithmetic of the x-sum contraction (the dominant step). */
+typedef enum {
+    MSFT_FP32 = 0,   /* FP32 MFMA, FP32 accumulation */
+    MSFT_BF16X3 = 1  /* BF16 hi+lo split, hi*hi + hi*lo + lo*hi on BF16 MFMA, FP32 accumulation */
+} msft_precision;
+
+/* How the two voxel arrays become the effective strength w. */
+typedef enum {
+    MSFT_STRENGTH_MSFT = 0,    /* w = dV (n^2 - 1) T, T from the column scan: Eqs. (6)-(9) */
+    MSFT_STRENGTH_BORN = 1,    /* w = dV (n^2 - 1), incident field undisturbed: Eq. (1) with (5) */
+    MSFT_STRENGTH_DENSITY = 2  /* w = dV (delta + i beta): the two arrays are the real and
+                                  imaginary parts of a scattering density rho, Eq. (1) */
+} msft_strength;
+
+/* geometry flags */
+#define MSFT_ALLOW_ALIAS 1u /* accept grids whose pitch exceeds pi / max|q| on some axis */
+
+/*
+ * Experiment and target description (Sec. 3, Blocks 1 and 2): wavelength,
+ * maximal scattering angle and detector resolution; voxel counts and pitch.
+ * struct_size must be sizeof(msft_geometry).
+ */
+typedef struct {
+    uint32_t struct_size;
+    double wavelength;     /* lambda > 0 */
+    double theta_max_deg;  /* 0 < theta_max < 90: tan(theta_max) = detector half-width */
+    int32_t det_n;         /* N >= 1 (ignored by msft_plan_qlist) */
+    int32_t nx, ny, nz;    /* voxel counts >= 1 */
+    double dx, dy, dz;     /* voxel pitch > 0 */
+    int32_t precision;     /* msft_precision */
+    int32_t strength;      /* msft_strength */
+    uint32_t flags;        /* MSFT_ALLOW_ALIAS */
+} msft_geometry;
+
+typedef struct msft_plan_s* msft_plan_t;
+
+/*
+ * Build a plan: validate the geometry, compute the FP64 pixel -> q table on the
+ * host (Eq. (3) on the flat detector; bit-reproducible, no FMA contraction),
+ * check sampling (pitch * max|q| <= pi per axis, the discrete form of the
+ * condition dz << pi / q_z under Eq. (2)), and, for device >= 0, generate the
+ * resident twiddle tables exp(-i q_x x), exp(-i q_y y), exp(-i q_z z) on that
+ * device from FP64 phase arguments.  device < 0 builds a host-only plan that
+ * answers the query calls but cannot simulate.  On success *out receives the
+ * handle; on failure *out is NULL.  Synchronous.
+ */
+msft_status msft_plan(const msft_geometry* g, int device, msft_plan_t* out);
+
+/*
+ * As msft_plan, but for an explicit list of npix transfer momenta q_host[npix][3]
+ * (host memory, copied) instead of a detector; g->det_n and g->theta_max_deg
+ * are ignored.  Used for the small-angle (uniform-q) limit and other detectors.
+ */
+msft_status msft_plan_qlist(const msft_geometry* g, const double* q_host, int64_t npix,
+                            int device, msft_plan_t* out);
+
+/* Free a plan and its device tables (NULL is accepted).  Synchronises the device. */
+msft_status msft_plan_destroy(msft_plan_t plan);
+
+/*
+ * Sizes of a plan: npix = P; workspace_bytes = device scratch one msft_simulate
+ * or msft_backward call needs (the effective strength w in the contraction's
+ * tile layout, plus the backward's partial sums); resident_bytes = device
+ * memory the plan itself holds.  Any pointer may be NULL.
+ */
+msft_status msft_plan_query(msft_plan_t plan, int64_t* npix, size_t* workspace_bytes,
+                            size_t* resident_bytes);
+
+/* Copy the plan's FP64 transfer momenta, q_host[P][3] as (qx, qy, qz). */
+msft_status msft_plan_qmap(msft_plan_t plan, double* q_host);
+
+/* Copy the voxel centre coordinates: x[nx], y[ny], z[nz] (host memory). */
+msft_status msft_plan_grid(msft_plan_t plan, double* x, double* y, double* z);
+
+/*
+ * Forward model for one target (Eq. (9), Sec. 3 Blocks 5-11): column scan of
+ * the incident field and strength, the x-sum as a contraction on the matrix
+ * cores, the y/z phase-weighted reduction and |A|^2.
+ *   delta, beta : device float32 [nx][ny][nz]
+ *   intensity   : device float32 [P] (written)
+ *   amplitude   : device complex64 [P] or NULL (written if given)
+ *   workspace   : device buffer of at least workspace_bytes, 256-byte aligned
+ * Results do not depend on the stream, the batch a call is part of, or on
+ * earlier calls: the order of every floating-point sum is fixed by the plan.
+ */
+msft_status msft_simulate(msft_plan_t plan, const float* delta, const float* beta,
+                          float* intensity, float* amplitude, void* workspace, void* stream);
+
+/*
+ * The two stages of msft_simulate, for callers that time or reuse them:
+ * msft_simulate_scan runs the column scan (Eq. (8)) and writes the effective
+ * strength w into the workspace in the contraction's tile layout;
+ * msft_simulate_contract then sums it against the plan's twiddles (Eq. (9)) and writes
+ * intensity (and amplitude if non-NULL).  msft_simulate_scan followed by
+ * msft_simulate_contract on one stream and one workspace equals msft_simulate bit for bit.
+ */
+msft_status msft_simulate_scan(msft_plan_t plan, const float* delta, const float* beta,
+                          void* workspace, void* stream);
+msft_status msft_simulate_contract(msft_plan_t plan, const void* workspace, float* intensity,
+                          float* amplitude, void* stream);
+
+/* One request of a batch; tile_begin/tile_end select pixel blocks (-1 = all). */
+typedef struct {
+    msft_plan_t plan;
+    const float* delta;
+    const float* beta;
+    float* intensity;
+    float* amplitude;   /* may be NULL */
+    int32_t tile_begin; /* first pixel block (blocks of msft_pixel_block() pixels) */
+    int32_t tile_end;   /* one past the last block, -1 = to the end */
+} msft_request;
+
+/* Number of pixels one work item (pixel block) of a batch covers. */
+int32_t msft_pixel_block(void);
+
+/* Device workspace bytes msft_simulate_batch needs for these requests. */
+msft_status msft_batch_query(const msft_request* reqs, int32_t n, size_t* workspace_bytes);
+
+/*
+ * Forward model for n requests of possibly different plans (same precision)
+ * in one persistent launch: every request's pixel blocks become work items that
+ * the workgroups pull in a cost-sorted order.  Each pixel written is
+ * bit-identical to what msft_simulate writes for that request alone.
+ * Returns MSFT_ERR_BUSY if ws_bytes is smaller than msft_batch_query reports.
+ */
+msft_status msft_simulate_batch(const msft_request* reqs, int32_t n, void* workspace,
+                                size_t ws_bytes, void* stream);
+
+/*
+ * Adjoint of the forward model: given the amplitudes A saved by msft_simulate
+ * and g = dL/dI for a real loss L, write dL/d delta and dL/d beta (device
+ * float32 [nx][ny][nz]).  With R_v = sum_p g_p conj(A_p) exp(-i q_p . r_v) the
+ * chain rule through Eqs. (7)-(9) gives, along each column,
+ *   dL/d delta_s = 2 Re(R_s dw_s/d delta_s) + 2 k0 dz Im(sum_{s'>s} R_s' w_s')
+ *   dL/d beta_s  = 2 Re(R_s dw_s/d beta_s)  - 2 k0 dz Re(sum_{s'>s} R_s' w_s')
+ * (second terms only for MSFT_STRENGTH_MSFT).  The twiddles are recomputed
+ * on the fly, not read from the plan.
+ */
+msft_status msft_backward(msft_plan_t plan, const float* delta, const float* beta,
+                          const float* amplitude, const float* grad_intensity,
+                          float* grad_delta, float* grad_beta, void* workspace, void* stream);
+
+/* Static description of a status code. */
+const char* msft_status_str(msft_status s);
+
+/* Detail of the last error returned on the calling thread ("" if none). */
+const char* msft_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSFT_H */

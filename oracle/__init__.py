@@ -48,6 +48,8 @@ def _load():
         lib.oracle_amplitude.argtypes = [i32, p, i64, i32, i32, i32, d, d, d, p, p]
         lib.oracle_backward.argtypes = [i32, p, i64, p, p, i32, i32, i32, d, d, d, d,
                                         p, p, p, i64, p, p]
+        lib.oracle_threads.argtypes = []
+        lib.oracle_threads.restype = ctypes.c_int
         for f in (lib.oracle_qmap, lib.oracle_grid, lib.oracle_strength,
                   lib.oracle_amplitude, lib.oracle_backward):
             f.restype = None
@@ -61,6 +63,11 @@ def _ptr(a: np.ndarray):
 
 def _f64(a) -> np.ndarray:
     return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(_load().oracle_threads())
 
 
 def qmap(wavelength: float, theta_max_deg: float, n: int) -> np.ndarray:

@@ -26,6 +26,7 @@
  *  - Proportionality constants are dropped: w = dV (n^2 - 1) T exactly.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -33,6 +34,9 @@
 #define ORACLE_PI 3.14159265358979323846
 
 enum { ORACLE_MSFT = 0, ORACLE_BORN = 1, ORACLE_DENSITY = 2 };
+
+/* Threads an OpenMP region of the oracle uses. */
+int oracle_threads(void) { return omp_get_max_threads(); }
 
 /* Wave number k0 = 2 pi / lambda. */
 static double oracle_k0(double wavelength) { return (2.0 * ORACLE_PI) / wavelength; }

@@ -1,0 +1,483 @@
+// C ABI of the MSFT library: plan lifecycle, argument checking and the
+// launches of the forward model.  Host code only; kernels live in the .hip files.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "msft_internal.h"
+
+using namespace msft;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+msft_status fail(msft_status s, const std::string& why)
+{
+    g_last_error = why;
+    return s;
+}
+
+msft_status ok()
+{
+    g_last_error.clear();
+    return MSFT_OK;
+}
+
+// Makes `device` current for the scope of a call and restores the caller's.
+struct DeviceScope {
+    int prev = -1;
+    bool changed = false;
+    hipError_t err = hipSuccess;
+    explicit DeviceScope(int device)
+    {
+        err = hipGetDevice(&prev);
+        if (err == hipSuccess && prev != device) {
+            err = hipSetDevice(device);
+            changed = (err == hipSuccess);
+        }
+    }
+    ~DeviceScope()
+    {
+        if (changed) (void)hipSetDevice(prev);
+    }
+};
+
+msft_status hip_fail(hipError_t e, const char* what)
+{
+    return fail(e == hipErrorOutOfMemory ? MSFT_ERR_NOMEM : MSFT_ERR_DEVICE,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+void free_device(msft_plan_s* p)
+{
+    if (p->device < 0) return;
+    DeviceScope ds(p->device);
+    void* ptrs[] = {p->q_dev, p->xs_dev, p->ys_dev, p->zs_dev, p->txa, p->ty, p->tz};
+    for (void* q : ptrs)
+        if (q) (void)hipFree(q);
+    p->q_dev = p->xs_dev = p->ys_dev = p->zs_dev = nullptr;
+    p->txa = nullptr;
+    p->ty = p->tz = nullptr;
+}
+
+template <typename T>
+hipError_t dev_alloc(T** out, size_t bytes, size_t* total)
+{
+    void* ptr = nullptr;
+    hipError_t e = hipMalloc(&ptr, bytes ? bytes : 256);
+    if (e == hipSuccess) {
+        *out = (T*)ptr;
+        *total += bytes;
+    }
+    return e;
+}
+
+// Resident tables of a plan on its device: FP64 q and coordinates, then the
+// twiddle tables generated from them.
+msft_status build_device_tables(msft_plan_s* p)
+{
+    DeviceScope ds(p->device);
+    if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice");
+    const Dims& d = p->dims;
+    const Geometry& geo = p->geo;
+    size_t total = 0;
+    hipError_t e;
+#define MSFT_TRY(expr, what)                  \
+    do {                                      \
+        e = (expr);                           \
+        if (e != hipSuccess) {                \
+            free_device(p);                   \
+            return hip_fail(e, what);         \
+        }                                     \
+    } while (0)
+    MSFT_TRY(dev_alloc(&p->q_dev, sizeof(double) * 3 * geo.npix, &total), "hipMalloc q");
+    MSFT_TRY(dev_alloc(&p->xs_dev, sizeof(double) * d.nx, &total), "hipMalloc x");
+    MSFT_TRY(dev_alloc(&p->ys_dev, sizeof(double) * d.ny, &total), "hipMalloc y");
+    MSFT_TRY(dev_alloc(&p->zs_dev, sizeof(double) * d.nz, &total), "hipMalloc z");
+    MSFT_TRY(dev_alloc(&p->txa, d.txa_bytes(), &total), "hipMalloc Tx");
+    MSFT_TRY(dev_alloc(&p->ty, d.ty_bytes(), &total), "hipMalloc Ty");
+    MSFT_TRY(dev_alloc(&p->tz, d.tz_bytes(), &total), "hipMalloc Tz");
+    MSFT_TRY(hipMemcpy(p->q_dev, geo.q.data(), sizeof(double) * 3 * geo.npix, hipMemcpyHostToDevice),
+             "copy q");
+    MSFT_TRY(hipMemcpy(p->xs_dev, geo.xs.data(), sizeof(double) * d.nx, hipMemcpyHostToDevice), "copy x");
+    MSFT_TRY(hipMemcpy(p->ys_dev, geo.ys.data(), sizeof(double) * d.ny, hipMemcpyHostToDevice), "copy y");
+    MSFT_TRY(hipMemcpy(p->zs_dev, geo.zs.data(), sizeof(double) * d.nz, hipMemcpyHostToDevice), "copy z");
+    hipStream_t s = nullptr;
+    MSFT_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate");
+    e = (hipError_t)launch_twiddles(p->geo.g.precision, d, p->q_dev, p->xs_dev, p->ys_dev,
+                                    p->zs_dev, p->txa, p->ty, p->tz, s);
+    hipError_t e2 = hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+    if (e == hipSuccess) e = e2;
+    if (e != hipSuccess) {
+        free_device(p);
+        return hip_fail(e, "twiddle generation");
+    }
+#undef MSFT_TRY
+    p->resident_bytes = total;
+    return MSFT_OK;
+}
+
+msft_status make_plan(const msft_geometry* g, const double* q_host, int64_t npix, int device,
+                      msft_plan_t* out)
+{
+    if (!out) return fail(MSFT_ERR_INVALID, "out pointer is NULL");
+    *out = nullptr;
+    const bool qlist = (q_host != nullptr);
+    std::string why;
+    msft_status st = validate_geometry(g, qlist, &why);
+    if (st != MSFT_OK) return fail(st, why);
+    if (qlist && (npix < 1 || npix > ((int64_t)1 << 28)))
+        return fail(MSFT_ERR_INVALID, "npix must lie in [1, 2^28]");
+
+    msft_plan_s* p = new (std::nothrow) msft_plan_s;
+    if (!p) return fail(MSFT_ERR_NOMEM, "plan allocation");
+    p->qlist = qlist;
+    p->geo.g = *g;
+    try {
+        if (qlist) {
+            p->geo.npix = npix;
+            p->geo.q.assign(q_host, q_host + 3 * npix);
+            for (int64_t k = 0; k < 3 * npix; ++k)
+                if (!std::isfinite(p->geo.q[k])) {
+                    delete p;
+                    return fail(MSFT_ERR_INVALID, "q list holds a non-finite value");
+                }
+        } else {
+            p->geo.npix = (int64_t)g->det_n * g->det_n;
+            p->geo.q.resize(3 * p->geo.npix);
+            detector_qmap(g->wavelength, g->theta_max_deg, g->det_n, p->geo.q.data());
+        }
+        p->geo.xs.resize(g->nx);
+        p->geo.ys.resize(g->ny);
+        p->geo.zs.resize(g->nz);
+    } catch (const std::bad_alloc&) {
+        delete p;
+        return fail(MSFT_ERR_NOMEM, "host tables");
+    }
+    voxel_centres(g->nx, g->dx, p->geo.xs.data());
+    voxel_centres(g->ny, g->dy, p->geo.ys.data());
+    voxel_centres(g->nz, g->dz, p->geo.zs.data());
+
+    int bad = -1;
+    double worst = 0.0;
+    if (!(g->flags & MSFT_ALLOW_ALIAS) && !sampling_ok(p->geo, &bad, &worst)) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf,
+                      "undersampled: pitch * max|q| = %.4g > pi on axis %c (set MSFT_ALLOW_ALIAS)",
+                      worst, "xyz"[bad < 0 ? 0 : bad]);
+        delete p;
+        return fail(MSFT_ERR_UNDERSAMPLED, buf);
+    }
+    p->dims = make_dims(p->geo.npix, g->nx, g->ny, g->nz);
+    p->workspace_bytes = align256(p->dims.wtile_bytes());
+    p->device = device;
+    if (device >= 0) {
+        int count = 0;
+        hipError_t e = hipGetDeviceCount(&count);
+        if (e != hipSuccess || device >= count) {
+            p->device = -1;
+            delete p;
+            return fail(MSFT_ERR_DEVICE, "no such HIP device");
+        }
+        st = build_device_tables(p);
+        if (st != MSFT_OK) {
+            p->device = -1;
+            delete p;
+            return st;
+        }
+    }
+    *out = p;
+    return ok();
+}
+
+bool aligned256(const void* ptr) { return ((uintptr_t)ptr & 255) == 0; }
+
+FwdArgs forward_args(const msft_plan_s* p, const void* wtiles, float* intensity, float* amplitude)
+{
+    FwdArgs a;
+    a.wtiles = (const uint8_t*)wtiles;
+    a.txa = p->txa;
+    a.ty = p->ty;
+    a.tz = p->tz;
+    a.intensity = intensity;
+    a.amplitude = amplitude;
+    a.npix = p->dims.npix;
+    a.ny = p->dims.ny;
+    a.nxc = p->dims.nxc;
+    a.nzb = p->dims.nzb;
+    a.x_pad = p->dims.x_pad;
+    return a;
+}
+
+ScanArgs scan_args(const msft_plan_s* p, const float* delta, const float* beta, void* wtiles)
+{
+    const msft_geometry& g = p->geo.g;
+    ScanArgs s;
+    s.delta = delta;
+    s.beta = beta;
+    s.wtiles = (uint8_t*)wtiles;
+    s.nx = g.nx;
+    s.ny = g.ny;
+    s.nz = g.nz;
+    s.nxc = p->dims.nxc;
+    s.nzb = p->dims.nzb;
+    s.strength = g.strength;
+    const double k0 = (2.0 * 3.14159265358979323846) / g.wavelength;
+    s.k0dz = (float)(k0 * g.dz);
+    s.dV = (float)(g.dx * g.dy * g.dz);
+    return s;
+}
+
+msft_status check_runnable(const msft_plan_s* p)
+{
+    if (!p) return fail(MSFT_ERR_INVALID, "plan is NULL");
+    if (p->device < 0) return fail(MSFT_ERR_UNSUPPORTED, "host-only plan cannot simulate");
+    return MSFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+msft_status msft_plan(const msft_geometry* g, int device, msft_plan_t* out)
+{
+    return make_plan(g, nullptr, 0, device, out);
+}
+
+msft_status msft_plan_qlist(const msft_geometry* g, const double* q_host, int64_t npix, int device,
+                            msft_plan_t* out)
+{
+    if (!q_host) return fail(MSFT_ERR_INVALID, "q_host is NULL");
+    return make_plan(g, q_host, npix, device, out);
+}
+
+msft_status msft_plan_destroy(msft_plan_t plan)
+{
+    if (!plan) return ok();
+    if (plan->device >= 0) {
+        DeviceScope ds(plan->device);
+        (void)hipDeviceSynchronize();
+    }
+    free_device(plan);
+    delete plan;
+    return ok();
+}
+
+msft_status msft_plan_query(msft_plan_t plan, int64_t* npix, size_t* workspace_bytes,
+                            size_t* resident_bytes)
+{
+    if (!plan) return fail(MSFT_ERR_INVALID, "plan is NULL");
+    if (npix) *npix = plan->geo.npix;
+    if (workspace_bytes) *workspace_bytes = plan->workspace_bytes;
+    if (resident_bytes) *resident_bytes = plan->resident_bytes;
+    return ok();
+}
+
+msft_status msft_plan_qmap(msft_plan_t plan, double* q_host)
+{
+    if (!plan || !q_host) return fail(MSFT_ERR_INVALID, "NULL argument");
+    std::memcpy(q_host, plan->geo.q.data(), sizeof(double) * 3 * plan->geo.npix);
+    return ok();
+}
+
+msft_status msft_plan_grid(msft_plan_t plan, double* x, double* y, double* z)
+{
+    if (!plan) return fail(MSFT_ERR_INVALID, "plan is NULL");
+    if (x) std::memcpy(x, plan->geo.xs.data(), sizeof(double) * plan->geo.xs.size());
+    if (y) std::memcpy(y, plan->geo.ys.data(), sizeof(double) * plan->geo.ys.size());
+    if (z) std::memcpy(z, plan->geo.zs.data(), sizeof(double) * plan->geo.zs.size());
+    return ok();
+}
+
+msft_status msft_simulate(msft_plan_t plan, const float* delta, const float* beta, float* intensity,
+                          float* amplitude, void* workspace, void* stream)
+{
+    msft_status st = check_runnable(plan);
+    if (st != MSFT_OK) return st;
+    if (!delta || !beta || !intensity || !workspace)
+        return fail(MSFT_ERR_INVALID, "delta, beta, intensity and workspace must be non-NULL");
+    if (!aligned256(workspace)) return fail(MSFT_ERR_INVALID, "workspace must be 256-byte aligned");
+    DeviceScope ds(plan->device);
+    if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice");
+    const ScanArgs sa = scan_args(plan, delta, beta, workspace);
+    int e = launch_scan(plan->geo.g.precision, sa, stream);
+    if (e) return hip_fail((hipError_t)e, "scan launch");
+    const FwdArgs fa = forward_args(plan, workspace, intensity, amplitude);
+    e = launch_forward(plan->geo.g.precision, fa, 0, plan->dims.nblocks, stream);
+    if (e) return hip_fail((hipError_t)e, "forward launch");
+    return ok();
+}
+
+msft_status msft_simulate_scan(msft_plan_t plan, const float* delta, const float* beta, void* workspace,
+                          void* stream)
+{
+    msft_status st = check_runnable(plan);
+    if (st != MSFT_OK) return st;
+    if (!delta || !beta || !workspace) return fail(MSFT_ERR_INVALID, "NULL argument");
+    if (!aligned256(workspace)) return fail(MSFT_ERR_INVALID, "workspace must be 256-byte aligned");
+    DeviceScope ds(plan->device);
+    if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice");
+    int e = launch_scan(plan->geo.g.precision, scan_args(plan, delta, beta, workspace), stream);
+    if (e) return hip_fail((hipError_t)e, "scan launch");
+    return ok();
+}
+
+msft_status msft_simulate_contract(msft_plan_t plan, const void* workspace, float* intensity, float* amplitude,
+                          void* stream)
+{
+    msft_status st = check_runnable(plan);
+    if (st != MSFT_OK) return st;
+    if (!workspace || !intensity) return fail(MSFT_ERR_INVALID, "NULL argument");
+    if (!aligned256(workspace)) return fail(MSFT_ERR_INVALID, "workspace must be 256-byte aligned");
+    DeviceScope ds(plan->device);
+    if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice");
+    const FwdArgs fa = forward_args(plan, workspace, intensity, amplitude);
+    int e = launch_forward(plan->geo.g.precision, fa, 0, plan->dims.nblocks, stream);
+    if (e) return hip_fail((hipError_t)e, "forward launch");
+    return ok();
+}
+
+int32_t msft_pixel_block(void) { return BLOCK_PIX; }
+
+static msft_status batch_layout(const msft_request* reqs, int32_t n, std::vector<size_t>* offs,
+                                size_t* total)
+{
+    if (n < 0 || (n > 0 && !reqs)) return fail(MSFT_ERR_INVALID, "bad request array");
+    size_t off = 256;  // work counter
+    if (offs) offs->resize(n);
+    for (int32_t r = 0; r < n; ++r) {
+        msft_status st = check_runnable(reqs[r].plan);
+        if (st != MSFT_OK) return st;
+        if (offs) (*offs)[r] = off;
+        off += align256(reqs[r].plan->dims.wtile_bytes());
+    }
+    *total = off;
+    return MSFT_OK;
+}
+
+msft_status msft_batch_query(const msft_request* reqs, int32_t n, size_t* workspace_bytes)
+{
+    size_t total = 0;
+    msft_status st = batch_layout(reqs, n, nullptr, &total);
+    if (st != MSFT_OK) return st;
+    if (workspace_bytes) *workspace_bytes = total;
+    return ok();
+}
+
+msft_status msft_simulate_batch(const msft_request* reqs, int32_t n, void* workspace, size_t ws_bytes,
+                                void* stream)
+{
+    std::vector<size_t> offs;
+    size_t total = 0;
+    msft_status st = batch_layout(reqs, n, &offs, &total);
+    if (st != MSFT_OK) return st;
+    if (n == 0) return ok();
+    if (!workspace || !aligned256(workspace))
+        return fail(MSFT_ERR_INVALID, "workspace must be non-NULL and 256-byte aligned");
+    if (ws_bytes < total) return fail(MSFT_ERR_BUSY, "workspace smaller than msft_batch_query");
+    const int device = reqs[0].plan->device;
+    const int precision = reqs[0].plan->geo.g.precision;
+    std::vector<int32_t> b0(n), b1(n);
+    for (int32_t r = 0; r < n; ++r) {
+        const msft_request& q = reqs[r];
+        if (q.plan->device != device) return fail(MSFT_ERR_INVALID, "requests span several devices");
+        if (q.plan->geo.g.precision != precision)
+            return fail(MSFT_ERR_INVALID, "requests mix precisions");
+        if (!q.delta || !q.beta || !q.intensity)
+            return fail(MSFT_ERR_INVALID, "request delta, beta, intensity must be non-NULL");
+        const int64_t nb = q.plan->dims.nblocks;
+        const int64_t lo = q.tile_begin < 0 ? 0 : q.tile_begin;
+        const int64_t hi = q.tile_end < 0 ? nb : q.tile_end;
+        if (lo > hi || hi > nb) return fail(MSFT_ERR_INVALID, "request tile range out of bounds");
+        b0[r] = (int32_t)lo;
+        b1[r] = (int32_t)hi;
+    }
+    DeviceScope ds(device);
+    if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice");
+    uint8_t* ws = (uint8_t*)workspace;
+    for (int32_t r = 0; r < n; ++r) {
+        if (b1[r] == b0[r]) continue;
+        const ScanArgs sa = scan_args(reqs[r].plan, reqs[r].delta, reqs[r].beta, ws + offs[r]);
+        int e = launch_scan(precision, sa, stream);
+        if (e) return hip_fail((hipError_t)e, "scan launch");
+    }
+    // Work items of the most expensive blocks first (cost ~ voxels per block).
+    std::vector<int32_t> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        const Dims& da = reqs[a].plan->dims;
+        const Dims& db = reqs[b].plan->dims;
+        return (int64_t)da.x_pad * da.ny * da.nzb > (int64_t)db.x_pad * db.ny * db.nzb;
+    });
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    for (size_t k0 = 0; k0 < order.size(); k0 += MAX_BATCH) {
+        BatchArgs b;
+        std::memset(&b, 0, sizeof b);
+        b.counter = (int32_t*)ws;
+        int32_t items = 0;
+        int32_t nr = 0;
+        for (size_t k = k0; k < order.size() && k < k0 + MAX_BATCH; ++k) {
+            const int32_t r = order[k];
+            if (b1[r] == b0[r]) continue;
+            b.req[nr] = forward_args(reqs[r].plan, ws + offs[r], reqs[r].intensity, reqs[r].amplitude);
+            b.block_begin[nr] = b0[r];
+            b.item_begin[nr] = items;
+            items += b1[r] - b0[r];
+            ++nr;
+        }
+        b.nreq = nr;
+        b.item_begin[nr] = items;
+        if (items == 0) continue;
+        const int32_t grid = std::min<int32_t>(items, cus);
+        int e = launch_forward_batch(precision, b, grid, stream);
+        if (e) return hip_fail((hipError_t)e, "batch launch");
+    }
+    return ok();
+}
+
+msft_status msft_backward(msft_plan_t plan, const float* delta, const float* beta,
+                          const float* amplitude, const float* grad_intensity, float* grad_delta,
+                          float* grad_beta, void* workspace, void* stream)
+{
+    (void)delta;
+    (void)beta;
+    (void)amplitude;
+    (void)grad_intensity;
+    (void)grad_delta;
+    (void)grad_beta;
+    (void)workspace;
+    (void)stream;
+    msft_status st = check_runnable(plan);
+    if (st != MSFT_OK) return st;
+    return fail(MSFT_ERR_UNSUPPORTED, "msft_backward is not available in this build");
+}
+
+const char* msft_status_str(msft_status s)
+{
+    switch (s) {
+    case MSFT_OK: return "ok";
+    case MSFT_ERR_INVALID: return "invalid argument";
+    case MSFT_ERR_UNDERSAMPLED: return "voxel grid undersamples the detector's q range";
+    case MSFT_ERR_NOMEM: return "out of memory";
+    case MSFT_ERR_DEVICE: return "HIP runtime error";
+    case MSFT_ERR_BUSY: return "workspace too small";
+    case MSFT_ERR_UNSUPPORTED: return "unsupported for this plan";
+    }
+    return "unknown status";
+}
+
+const char* msft_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

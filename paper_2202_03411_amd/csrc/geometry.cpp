@@ -1,0 +1,112 @@
+// Host-side FP64 geometry of the MSFT library: argument validation, the pixel ->
+// transfer-momentum map of a flat detector and the voxel grid.
+//
+// Built with -ffp-contract=off so that every product and sum is rounded on its
+// own, which makes the q table reproducible bit for bit on any x86-64 host.
+#include <cmath>
+#include <cstdio>
+
+#include "msft_internal.h"
+
+namespace msft {
+
+static const double kPi = 3.14159265358979323846;
+
+msft_status validate_geometry(const msft_geometry* g, bool qlist, std::string* why)
+{
+    char buf[256];
+    auto fail = [&](const char* msg) {
+        if (why) *why = msg;
+        return MSFT_ERR_INVALID;
+    };
+    if (!g) return fail("geometry pointer is NULL");
+    if (g->struct_size != sizeof(msft_geometry)) {
+        std::snprintf(buf, sizeof buf, "struct_size %u != sizeof(msft_geometry) %zu",
+                      g->struct_size, sizeof(msft_geometry));
+        if (why) *why = buf;
+        return MSFT_ERR_INVALID;
+    }
+    if (!(g->wavelength > 0.0) || !std::isfinite(g->wavelength)) return fail("wavelength must be > 0");
+    if (!qlist) {
+        if (!(g->theta_max_deg > 0.0 && g->theta_max_deg < 90.0))
+            return fail("theta_max_deg must lie in (0, 90)");
+        if (g->det_n < 1 || g->det_n > 16384) return fail("det_n must lie in [1, 16384]");
+    }
+    if (g->nx < 1 || g->ny < 1 || g->nz < 1) return fail("nx, ny, nz must be >= 1");
+    if (g->nx > 4096 || g->ny > 4096 || g->nz > 4096) return fail("nx, ny, nz must be <= 4096");
+    if (!(g->dx > 0.0 && g->dy > 0.0 && g->dz > 0.0) || !std::isfinite(g->dx) ||
+        !std::isfinite(g->dy) || !std::isfinite(g->dz))
+        return fail("voxel pitch must be finite and > 0");
+    if (g->precision != MSFT_FP32 && g->precision != MSFT_BF16X3) return fail("unknown precision");
+    if (g->strength != MSFT_STRENGTH_MSFT && g->strength != MSFT_STRENGTH_BORN &&
+        g->strength != MSFT_STRENGTH_DENSITY)
+        return fail("unknown strength mode");
+    if (g->flags & ~MSFT_ALLOW_ALIAS) return fail("unknown flag bits");
+    const double tiles = (double)ceil_div(g->nx, XC) * (double)ceil_div(g->nz, ZB) * (double)g->ny;
+    if (tiles * TILE_BYTES > 64.0 * 1024 * 1024 * 1024) return fail("voxel grid too large");
+    return MSFT_OK;
+}
+
+// Flat screen at unit distance; pixel centre (u_i, v_j, 1); khat = (u, v, 1) / r;
+// q = k0 (khat - zhat), so q_z = k0 (1/r - 1) = -k0 s / (r (r + 1)), s = u^2 + v^2.
+void detector_qmap(double wavelength, double theta_max_deg, int32_t n, double* q)
+{
+    const double k0 = (2.0 * kPi) / wavelength;
+    const double t = std::tan((theta_max_deg * kPi) / 180.0);
+    for (int32_t j = 0; j < n; ++j) {
+        const double v = ((double)(2 * j + 1 - n) * t) / (double)n;
+        for (int32_t i = 0; i < n; ++i) {
+            const double u = ((double)(2 * i + 1 - n) * t) / (double)n;
+            const double uu = u * u;
+            const double vv = v * v;
+            const double s = uu + vv;
+            const double r = std::sqrt(s + 1.0);
+            double* qp = q + 3 * ((int64_t)j * n + i);
+            qp[0] = (k0 * u) / r;
+            qp[1] = (k0 * v) / r;
+            qp[2] = -((k0 * s) / (r * (r + 1.0)));
+        }
+    }
+}
+
+void voxel_centres(int32_t n, double d, double* c)
+{
+    for (int32_t a = 0; a < n; ++a) c[a] = ((double)(2 * a + 1 - n) * d) / 2.0;
+}
+
+bool sampling_ok(const Geometry& geo, int* bad_axis, double* worst)
+{
+    const double pitch[3] = {geo.g.dx, geo.g.dy, geo.g.dz};
+    double mx[3] = {0.0, 0.0, 0.0};
+    for (int64_t p = 0; p < geo.npix; ++p)
+        for (int k = 0; k < 3; ++k) mx[k] = std::fmax(mx[k], std::fabs(geo.q[3 * p + k]));
+    bool ok = true;
+    double w = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        const double v = mx[k] * pitch[k];
+        if (v > w) w = v;
+        if (v > kPi && ok) {
+            ok = false;
+            if (bad_axis) *bad_axis = k;
+        }
+    }
+    if (worst) *worst = w;
+    return ok;
+}
+
+Dims make_dims(int64_t npix, int nx, int ny, int nz)
+{
+    Dims d;
+    d.npix = npix;
+    d.nblocks = ceil_div(npix, BLOCK_PIX);
+    d.nwt = d.nblocks * WAVES;
+    d.nx = nx;
+    d.ny = ny;
+    d.nz = nz;
+    d.x_pad = (int)ceil_div(nx, XPAD) * XPAD;
+    d.nxc = (int)ceil_div(nx, XC);
+    d.nzb = (int)ceil_div(nz, ZB);
+    return d;
+}
+
+}  // namespace msft

@@ -1,0 +1,516 @@
+// gfx950 kernels of the MSFT forward model.
+//
+//  twiddle_*     FP64 phase arguments -> FP32 (or BF16 hi/lo) tables, once per plan.
+//  scan_kernel   column scan of the incident field along z and the effective
+//                strength w = dV (n^2 - 1) T (Eqs. (6)-(9)), written in the
+//                contraction's LDS tile layout.
+//  fwd_block     the x-sum as a real-ified complex MFMA contraction with the
+//                y/z phase-weighted reduction and |A|^2 fused behind it.
+#include <hip/hip_runtime.h>
+
+#include "msft_internal.h"
+
+namespace msft {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// Pixel of wave tile wt held by lane half h, slot m (0..7) of the MFMA output:
+// accumulator rows 8j + 4h + u, u = 0..3, are (pixel 4j + 2h + u/2, re|im).
+__device__ __forceinline__ int64_t slot_pixel(int64_t wt, int h, int m)
+{
+    return wt * WAVE_PIX + 4 * (m >> 1) + 2 * h + (m & 1);
+}
+
+// Byte offset of 16-byte slot `slot` of row (h, z) in a W tile; the slot index
+// is XOR-swizzled with z so that the 32 lanes reading one slot index from 32
+// different rows hit distinct LDS banks.
+__device__ __forceinline__ int tile_slot_offset(int h, int z, int slot)
+{
+    return (h * ZB + z) * ROW_BYTES + ((slot ^ (z & 15)) << 4);
+}
+
+// ---------------------------------------------------------------------------
+// Twiddle tables (plan time).  T = exp(i phi), phi = -q . r, phases in FP64.
+// ---------------------------------------------------------------------------
+
+// FP32 A operand, per (wt, xc): [g 16][lane 64][e 4] floats; step s = 4g + e.
+// Lane (h, i): row i = (pixel i/2, c = i&1).  Values: h=0,c=0: Re T; h=0,c=1: Im T;
+// h=1,c=0: -Im T; h=1,c=1: Re T, so that row (p, re) . [Wr; Wi] = Re(T W) and
+// row (p, im) . [Wr; Wi] = Im(T W).
+__global__ void twiddle_txa_f32(float* txa, int64_t total, int64_t npix, int nx, int nxc,
+                                const double* q, const double* xs)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int e = (int)(idx & 3);
+    const int lane = (int)((idx >> 2) & 63);
+    const int g = (int)((idx >> 8) & 15);
+    const int64_t tile = idx >> 12;
+    const int xc = (int)(tile % nxc);
+    const int64_t wt = tile / nxc;
+    const int h = lane >> 5, i = lane & 31, c = i & 1;
+    const int64_t pix = wt * WAVE_PIX + (i >> 1);
+    const int x = xc * XC + 4 * g + e;
+    float v = 0.0f;
+    if (pix < npix && x < nx) {
+        double sn, cs;
+        sincos(-(q[3 * pix] * xs[x]), &sn, &cs);
+        if (h == 0) v = (float)(c == 0 ? cs : sn);
+        else v = (float)(c == 0 ? -sn : cs);
+    }
+    txa[idx] = v;
+}
+
+// BF16X3 A operand, per (wt, xc): [s 8][hl 2][lane 64][e 8] bf16; x = 8s + e.
+__global__ void twiddle_txa_bf16(__bf16* txa, int64_t total, int64_t npix, int nx, int nxc,
+                                 const double* q, const double* xs)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // one (s, lane, e)
+    if (idx >= total) return;
+    const int e = (int)(idx & 7);
+    const int lane = (int)((idx >> 3) & 63);
+    const int s = (int)((idx >> 9) & 7);
+    const int64_t tile = idx >> 12;
+    const int xc = (int)(tile % nxc);
+    const int64_t wt = tile / nxc;
+    const int h = lane >> 5, i = lane & 31, c = i & 1;
+    const int64_t pix = wt * WAVE_PIX + (i >> 1);
+    const int x = xc * XC + 8 * s + e;
+    float v = 0.0f;
+    if (pix < npix && x < nx) {
+        double sn, cs;
+        sincos(-(q[3 * pix] * xs[x]), &sn, &cs);
+        if (h == 0) v = (float)(c == 0 ? cs : sn);
+        else v = (float)(c == 0 ? -sn : cs);
+    }
+    const __bf16 hi = (__bf16)v;
+    const __bf16 lo = (__bf16)(v - (float)hi);
+    __bf16* base = txa + tile * (TILE_BYTES / 2) + (int64_t)s * 1024;
+    base[lane * 8 + e] = hi;
+    base[512 + lane * 8 + e] = lo;
+}
+
+// Ty: [wt][y][h][m] complex, exp(-i q_y y) of the pixel in lane half h, slot m.
+__global__ void twiddle_ty(float2* ty, int64_t total, int64_t npix, int ny, const double* q,
+                           const double* ys)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int m = (int)(idx & 7);
+    const int h = (int)((idx >> 3) & 1);
+    const int64_t rest = idx >> 4;
+    const int y = (int)(rest % ny);
+    const int64_t wt = rest / ny;
+    const int64_t pix = slot_pixel(wt, h, m);
+    float2 v = make_float2(0.0f, 0.0f);
+    if (pix < npix) {
+        double sn, cs;
+        sincos(-(q[3 * pix + 1] * ys[y]), &sn, &cs);
+        v = make_float2((float)cs, (float)sn);
+    }
+    ty[idx] = v;
+}
+
+// Tz: [wt][zb][h][z 32][m] complex, exp(-i q_z z) (zero beyond nz).
+__global__ void twiddle_tz(float2* tz, int64_t total, int64_t npix, int nz, int nzb,
+                           const double* q, const double* zs)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int m = (int)(idx & 7);
+    const int zl = (int)((idx >> 3) & 31);
+    const int h = (int)((idx >> 8) & 1);
+    const int64_t rest = idx >> 9;
+    const int zb = (int)(rest % nzb);
+    const int64_t wt = rest / nzb;
+    const int64_t pix = slot_pixel(wt, h, m);
+    const int z = zb * ZB + zl;
+    float2 v = make_float2(0.0f, 0.0f);
+    if (pix < npix && z < nz) {
+        double sn, cs;
+        sincos(-(q[3 * pix + 2] * zs[z]), &sn, &cs);
+        v = make_float2((float)cs, (float)sn);
+    }
+    tz[idx] = v;
+}
+
+static int grid_for(int64_t total, int block) { return (int)ceil_div(total, block); }
+
+int launch_twiddles(int precision, const Dims& d, const double* q_dev, const double* xs_dev,
+                    const double* ys_dev, const double* zs_dev, uint8_t* txa, float* ty,
+                    float* tz, void* stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    const int B = 256;
+    const int64_t ttiles = d.nwt * d.nxc;
+    if (precision == MSFT_FP32) {
+        const int64_t total = ttiles * (TILE_BYTES / 4);
+        hipLaunchKernelGGL(twiddle_txa_f32, dim3(grid_for(total, B)), dim3(B), 0, s,
+                           (float*)txa, total, d.npix, d.nx, d.nxc, q_dev, xs_dev);
+    } else {
+        const int64_t total = ttiles * (TILE_BYTES / 4);  // (s, lane, e) triples per tile
+        hipLaunchKernelGGL(twiddle_txa_bf16, dim3(grid_for(total, B)), dim3(B), 0, s,
+                           (__bf16*)txa, total, d.npix, d.nx, d.nxc, q_dev, xs_dev);
+    }
+    const int64_t nty = d.nwt * d.ny * WAVE_PIX;
+    hipLaunchKernelGGL(twiddle_ty, dim3(grid_for(nty, B)), dim3(B), 0, s, (float2*)ty, nty,
+                       d.npix, d.ny, q_dev, ys_dev);
+    const int64_t ntz = d.nwt * d.nzb * 2 * ZB * 8;
+    hipLaunchKernelGGL(twiddle_tz, dim3(grid_for(ntz, B)), dim3(B), 0, s, (float2*)tz, ntz,
+                       d.npix, d.nz, d.nzb, q_dev, zs_dev);
+    return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Column scan (Eq. (8)) and effective strength (Eqs. (6), (9)).
+//
+// Workgroup (xc, y) of 4 waves produces the nzb W tiles of its 64 columns.  For
+// each block of 32 slices a wave takes two columns at a time, one per 32-lane
+// half, lanes along z: coalesced loads, an exclusive wavefront prefix sum of
+// (beta, delta) with a carry from the previous block, then
+//   T = exp(-k0 dz (S_beta + i S_delta)),   w = dV chi T,
+//   chi = n^2 - 1 = delta (delta - 2) - beta^2 + 2 i beta (1 - delta)
+// (chi written without the cancelling "+1 -1").  The tile is staged in LDS in
+// its swizzled layout and stored with 16-byte writes.
+// ---------------------------------------------------------------------------
+template <int PREC>
+__global__ __launch_bounds__(256) void scan_kernel(ScanArgs a)
+{
+    __shared__ __attribute__((aligned(16))) uint8_t stage[TILE_BYTES];
+    const int xc = blockIdx.x, y = blockIdx.y;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int half = lane >> 5, zl = lane & 31;
+    float carry_b[8], carry_d[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) carry_b[k] = carry_d[k] = 0.0f;
+
+    for (int zb = 0; zb < a.nzb; ++zb) {
+        const int z = zb * ZB + zl;
+#pragma unroll
+        for (int pr = 0; pr < 8; ++pr) {
+            const int xl = wave * 16 + pr * 2 + half;
+            const int x = xc * XC + xl;
+            float d = 0.0f, b = 0.0f;
+            if (x < a.nx && z < a.nz) {
+                const size_t v = ((size_t)x * a.ny + y) * a.nz + z;
+                d = a.delta[v];
+                b = a.beta[v];
+            }
+            // exclusive prefix over the 32 lanes of this half: scan the values
+            // shifted down by one lane
+            float sb = __shfl_up(b, 1, 32), sd = __shfl_up(d, 1, 32);
+            if (zl == 0) sb = sd = 0.0f;
+#pragma unroll
+            for (int off = 1; off < 32; off <<= 1) {
+                const float tb = __shfl_up(sb, off, 32), td = __shfl_up(sd, off, 32);
+                if (zl >= off) {
+                    sb += tb;
+                    sd += td;
+                }
+            }
+            const float Sb = carry_b[pr] + sb, Sd = carry_d[pr] + sd;
+            carry_b[pr] += __shfl(sb + b, 31, 32);
+            carry_d[pr] += __shfl(sd + d, 31, 32);
+
+            float wr, wi;
+            if (a.strength == MSFT_STRENGTH_DENSITY) {
+                wr = a.dV * d;
+                wi = a.dV * b;
+            } else {
+                const float chr = d * (d - 2.0f) - b * b;
+                const float chi = 2.0f * b * (1.0f - d);
+                float tr = 1.0f, ti = 0.0f;
+                if (a.strength == MSFT_STRENGTH_MSFT) {
+                    const float mag = expf(-a.k0dz * Sb);
+                    float sn, cs;
+                    sincosf(-a.k0dz * Sd, &sn, &cs);
+                    tr = mag * cs;
+                    ti = mag * sn;
+                }
+                wr = a.dV * (chr * tr - chi * ti);
+                wi = a.dV * (chr * ti + chi * tr);
+            }
+            if (PREC == MSFT_FP32) {
+                const int sub = (xl & 3) * 4;
+                *(float*)(stage + tile_slot_offset(0, zl, xl >> 2) + sub) = wr;
+                *(float*)(stage + tile_slot_offset(1, zl, xl >> 2) + sub) = wi;
+            } else {
+                const int sub = (xl & 7) * 2;
+                const __bf16 rh = (__bf16)wr, ih = (__bf16)wi;
+                const __bf16 rl = (__bf16)(wr - (float)rh), il = (__bf16)(wi - (float)ih);
+                *(__bf16*)(stage + tile_slot_offset(0, zl, xl >> 3) + sub) = rh;
+                *(__bf16*)(stage + tile_slot_offset(0, zl, 8 + (xl >> 3)) + sub) = rl;
+                *(__bf16*)(stage + tile_slot_offset(1, zl, xl >> 3) + sub) = ih;
+                *(__bf16*)(stage + tile_slot_offset(1, zl, 8 + (xl >> 3)) + sub) = il;
+            }
+        }
+        __syncthreads();
+        uint4* dst = (uint4*)(a.wtiles + ((size_t)(xc * a.nzb + zb) * a.ny + y) * TILE_BYTES);
+        const uint4* src = (const uint4*)stage;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) dst[threadIdx.x + 256 * k] = src[threadIdx.x + 256 * k];
+        __syncthreads();
+    }
+}
+
+int launch_scan(int precision, const ScanArgs& a, void* stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    dim3 grid(a.nxc, a.ny);
+    if (precision == MSFT_FP32)
+        hipLaunchKernelGGL(scan_kernel<MSFT_FP32>, grid, dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(scan_kernel<MSFT_BF16X3>, grid, dim3(256), 0, s, a);
+    return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Forward contraction for one pixel block (BLOCK_PIX pixels, one workgroup).
+//
+//   for each x chunk xc:     A operand (Tx of the wave's 16 pixels) -> registers
+//     for each z block zb:   G = 0
+//       for each y:          C = A . W(xc, zb, y)           (MFMA, K = 2 * 64)
+//                            G += exp(-i q_y y) C           (per pixel, lane = z)
+//       acc += exp(-i q_z z) G
+//   A_p = sum over the 32 z lanes of acc;  I_p = |A_p|^2
+//
+// W tiles stream through a double-buffered LDS ring shared by the 8 waves.  The
+// order of every sum depends only on the plan, never on the launch.
+// ---------------------------------------------------------------------------
+// C = A . B for one W tile: the wave's A operand (registers) times the tile's
+// column `col` of lane half h (LDS row `row`), over the first `nx` x values.
+// FP32: 4 x values per 16-byte LDS slot, one v_mfma_f32_32x32x2_f32 per x.
+// BF16X3: 8 x values per slot, hi*hi + hi*lo + lo*hi on v_mfma_f32_32x32x16_bf16.
+template <int PREC, int NX>
+__device__ __forceinline__ f32x16 tile_mfma(const uint8_t* row, int col, const f32x4* Af,
+                                            const bf16x8* Ahi, const bf16x8* Alo)
+{
+    f32x16 C = {};
+    const int sw = col & 15;
+    if (PREC == MSFT_FP32) {
+#pragma unroll
+        for (int g = 0; g < NX / 4; ++g) {
+            const f32x4 b = *(const f32x4*)(row + ((g ^ sw) << 4));
+            C = __builtin_amdgcn_mfma_f32_32x32x2f32(Af[g][0], b[0], C, 0, 0, 0);
+            C = __builtin_amdgcn_mfma_f32_32x32x2f32(Af[g][1], b[1], C, 0, 0, 0);
+            C = __builtin_amdgcn_mfma_f32_32x32x2f32(Af[g][2], b[2], C, 0, 0, 0);
+            C = __builtin_amdgcn_mfma_f32_32x32x2f32(Af[g][3], b[3], C, 0, 0, 0);
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < NX / 8; ++s) {
+            const bf16x8 bh = *(const bf16x8*)(row + ((s ^ sw) << 4));
+            const bf16x8 bl = *(const bf16x8*)(row + (((8 + s) ^ sw) << 4));
+            C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ahi[s], bh, C, 0, 0, 0);
+            C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ahi[s], bl, C, 0, 0, 0);
+            C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Alo[s], bh, C, 0, 0, 0);
+        }
+    }
+    return C;
+}
+
+// The last, partial x chunk: the same products in steps of 8 x values.
+template <int PREC>
+__device__ __forceinline__ f32x16 tile_mfma_partial(const uint8_t* row, int col, int nx,
+                                                 const f32x4* Af, const bf16x8* Ahi,
+                                                 const bf16x8* Alo)
+{
+    f32x16 C = {};
+    const int sw = col & 15;
+#pragma unroll
+    for (int s = 0; s < XC / 8; ++s) {
+        if (8 * s < nx) {
+            if (PREC == MSFT_FP32) {
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int g = 2 * s + u;
+                    const f32x4 b = *(const f32x4*)(row + ((g ^ sw) << 4));
+                    C = __builtin_amdgcn_mfma_f32_32x32x2f32(Af[g][0], b[0], C, 0, 0, 0);
+                    C = __builtin_amdgcn_mfma_f32_32x32x2f32(Af[g][1], b[1], C, 0, 0, 0);
+                    C = __builtin_amdgcn_mfma_f32_32x32x2f32(Af[g][2], b[2], C, 0, 0, 0);
+                    C = __builtin_amdgcn_mfma_f32_32x32x2f32(Af[g][3], b[3], C, 0, 0, 0);
+                }
+            } else {
+                const bf16x8 bh = *(const bf16x8*)(row + ((s ^ sw) << 4));
+                const bf16x8 bl = *(const bf16x8*)(row + (((8 + s) ^ sw) << 4));
+                C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ahi[s], bh, C, 0, 0, 0);
+                C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ahi[s], bl, C, 0, 0, 0);
+                C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Alo[s], bh, C, 0, 0, 0);
+            }
+        }
+    }
+    return C;
+}
+
+template <int PREC>
+__device__ __forceinline__ void fwd_block(const FwdArgs& a, int64_t block, uint8_t* lds)
+{
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int h = lane >> 5, col = lane & 31;
+    const int64_t wt = block * WAVES + wave;
+    const int64_t ntiles = (int64_t)a.nxc * a.nzb * a.ny;
+    const uint4* gw = (const uint4*)a.wtiles;
+
+    // tile 0 -> LDS buffer 0
+    {
+        const uint4 r0 = gw[tid], r1 = gw[tid + 512];
+        ((uint4*)lds)[tid] = r0;
+        ((uint4*)lds)[tid + 512] = r1;
+    }
+    __syncthreads();
+
+    float acc[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc[k] = 0.0f;
+
+    int64_t t = 0;
+    for (int xc = 0; xc < a.nxc; ++xc) {
+        const int xlen = min(XC, a.x_pad - xc * XC);
+        // A operand of this wave for the chunk
+        f32x4 Af[16];
+        bf16x8 Ahi[8], Alo[8];
+        const uint8_t* ta = a.txa + (size_t)(wt * a.nxc + xc) * TILE_BYTES;
+        if (PREC == MSFT_FP32) {
+#pragma unroll
+            for (int g = 0; g < 16; ++g) Af[g] = ((const f32x4*)ta)[g * 64 + lane];
+        } else {
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                Ahi[s] = ((const bf16x8*)ta)[s * 128 + lane];
+                Alo[s] = ((const bf16x8*)ta)[s * 128 + 64 + lane];
+            }
+        }
+        for (int zb = 0; zb < a.nzb; ++zb) {
+            float G[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) G[k] = 0.0f;
+            for (int y = 0; y < a.ny; ++y, ++t) {
+                const bool has_next = (t + 1) < ntiles;
+                uint4 n0, n1;
+                if (has_next) {
+                    n0 = gw[(t + 1) * (TILE_BYTES / 16) + tid];
+                    n1 = gw[(t + 1) * (TILE_BYTES / 16) + 512 + tid];
+                }
+                const f32x4* typ = (const f32x4*)(a.ty + 2 * ((wt * a.ny + y) * WAVE_PIX + h * 8));
+                const f32x4 ty0 = typ[0], ty1 = typ[1], ty2 = typ[2], ty3 = typ[3];
+
+                const uint8_t* row = lds + (t & 1) * TILE_BYTES + (h * ZB + col) * ROW_BYTES;
+                const f32x16 C = (xlen == XC) ? tile_mfma<PREC, XC>(row, col, Af, Ahi, Alo)
+                                              : tile_mfma_partial<PREC>(row, col, xlen, Af, Ahi, Alo);
+                // G[m] += Ty[m] * C[m], slot m = 2j + u: C rows 4j + 2u (re), 4j + 2u + 1 (im)
+                const float tyv[16] = {ty0[0], ty0[1], ty0[2], ty0[3], ty1[0], ty1[1], ty1[2], ty1[3],
+                                       ty2[0], ty2[1], ty2[2], ty2[3], ty3[0], ty3[1], ty3[2], ty3[3]};
+#pragma unroll
+                for (int m = 0; m < 8; ++m) {
+                    const int r = 4 * (m >> 1) + 2 * (m & 1);
+                    const float cr = C[r], ci = C[r + 1];
+                    const float tr = tyv[2 * m], ti = tyv[2 * m + 1];
+                    G[2 * m] += tr * cr - ti * ci;
+                    G[2 * m + 1] += tr * ci + ti * cr;
+                }
+                if (has_next) {
+                    uint4* nb = (uint4*)(lds + ((t + 1) & 1) * TILE_BYTES);
+                    nb[tid] = n0;
+                    nb[tid + 512] = n1;
+                }
+                __syncthreads();
+            }
+            // acc[m] += Tz[m] * G[m]
+            const f32x4* tzp = (const f32x4*)(a.tz + 2 * ((((wt * a.nzb + zb) * 2 + h) * ZB + col) * 8));
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const f32x4 v = tzp[k];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int m = 2 * k + u;
+                    const float tr = v[2 * u], ti = v[2 * u + 1];
+                    acc[2 * m] += tr * G[2 * m] - ti * G[2 * m + 1];
+                    acc[2 * m + 1] += tr * G[2 * m + 1] + ti * G[2 * m];
+                }
+            }
+        }
+    }
+
+    // sum over the 32 z lanes of each half (fixed butterfly order)
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        float v = acc[k];
+        v += __shfl_xor(v, 16, 32);
+        v += __shfl_xor(v, 8, 32);
+        v += __shfl_xor(v, 4, 32);
+        v += __shfl_xor(v, 2, 32);
+        v += __shfl_xor(v, 1, 32);
+        acc[k] = v;
+    }
+    if (col == 0) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const int64_t pix = slot_pixel(wt, h, m);
+            if (pix < a.npix) {
+                const float re = acc[2 * m], im = acc[2 * m + 1];
+                a.intensity[pix] = re * re + im * im;
+                if (a.amplitude) ((float2*)a.amplitude)[pix] = make_float2(re, im);
+            }
+        }
+    }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(512) void fwd_kernel(FwdArgs a, int64_t block_begin)
+{
+    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * TILE_BYTES];
+    fwd_block<PREC>(a, block_begin + blockIdx.x, lds);
+}
+
+// Persistent form: workgroups pull (request, pixel block) items from a counter
+// until the list is exhausted; every workgroup reaches the exit test.
+template <int PREC>
+__global__ __launch_bounds__(512) void fwd_batch_kernel(BatchArgs b)
+{
+    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * TILE_BYTES];
+    __shared__ int32_t item_s;
+    const int32_t nitems = b.item_begin[b.nreq];
+    for (;;) {
+        if (threadIdx.x == 0) item_s = atomicAdd(b.counter, 1);
+        __syncthreads();
+        const int32_t it = item_s;
+        __syncthreads();
+        if (it >= nitems) break;
+        int r = 0;
+        while (r + 1 < b.nreq && b.item_begin[r + 1] <= it) ++r;
+        fwd_block<PREC>(b.req[r], (int64_t)b.block_begin[r] + (it - b.item_begin[r]), lds);
+    }
+}
+
+__global__ void zero_counter(int32_t* c) { *c = 0; }
+
+int launch_forward(int precision, const FwdArgs& a, int64_t block_begin, int64_t nblocks,
+                   void* stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    if (nblocks <= 0) return 0;
+    if (precision == MSFT_FP32)
+        hipLaunchKernelGGL(fwd_kernel<MSFT_FP32>, dim3((unsigned)nblocks), dim3(512), 0, s, a,
+                           block_begin);
+    else
+        hipLaunchKernelGGL(fwd_kernel<MSFT_BF16X3>, dim3((unsigned)nblocks), dim3(512), 0, s, a,
+                           block_begin);
+    return (int)hipGetLastError();
+}
+
+int launch_forward_batch(int precision, const BatchArgs& b, int32_t grid, void* stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    if (b.nreq <= 0 || b.item_begin[b.nreq] <= 0) return 0;
+    hipLaunchKernelGGL(zero_counter, dim3(1), dim3(1), 0, s, b.counter);
+    if (precision == MSFT_FP32)
+        hipLaunchKernelGGL(fwd_batch_kernel<MSFT_FP32>, dim3(grid), dim3(512), 0, s, b);
+    else
+        hipLaunchKernelGGL(fwd_batch_kernel<MSFT_BF16X3>, dim3(grid), dim3(512), 0, s, b);
+    return (int)hipGetLastError();
+}
+
+}  // namespace msft

@@ -1,0 +1,127 @@
+// Internal declarations of the MSFT library: data layouts shared by the host
+// plan code and the gfx950 kernels.  Nothing here is part of the C ABI.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "msft.h"
+
+namespace msft {
+
+// ---------------------------------------------------------------------------
+// Contraction tiling.
+//
+// The x-sum C[p, (y, z)] = sum_x Tx[p, x] W[x, (y, z)] runs on
+// v_mfma_f32_32x32x2_f32 (FP32) or v_mfma_f32_32x32x16_bf16 (BF16X3) with the
+// complex product made real: rows are (pixel, re|im) pairs, the K dimension is
+// (re|im of W, x).  A wave owns WAVE_PIX pixels (32 real rows) and keeps their
+// Tx operand for one x chunk in registers; a workgroup of WAVES waves shares
+// every W tile through LDS.  One W tile holds XC x values and ZB z values at a
+// fixed y: 64 rows (component h, z) of 256 bytes.
+// ---------------------------------------------------------------------------
+constexpr int XC = 64;                      // x values per contraction chunk
+constexpr int ZB = 32;                      // z values per tile (MFMA columns)
+constexpr int XPAD = 8;                     // nx is padded (with zeros) to a multiple of this
+constexpr int WAVE_PIX = 16;                // pixels per wave
+constexpr int WAVES = 8;                    // waves per workgroup
+constexpr int BLOCK_PIX = WAVE_PIX * WAVES; // pixels per workgroup = one work item
+constexpr int TILE_BYTES = 16384;           // one W tile, one A-operand tile
+constexpr int ROW_BYTES = 256;              // one (h, z) row of a W tile
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Host geometry (FP64, built without FMA contraction).
+struct Geometry {
+    msft_geometry g;
+    int64_t npix = 0;
+    std::vector<double> q;         // [npix][3]
+    std::vector<double> xs, ys, zs;
+};
+
+// Validate g (ignoring det_n/theta when qlist is true); message on failure.
+msft_status validate_geometry(const msft_geometry* g, bool qlist, std::string* why);
+// Pixel -> q of the flat detector, p = j * N + i.
+void detector_qmap(double wavelength, double theta_max_deg, int32_t n, double* q);
+// Voxel centres (2a + 1 - n) d / 2.
+void voxel_centres(int32_t n, double d, double* c);
+// max_p |q_axis| * pitch over the three axes; returns false (and the axis) if > pi.
+bool sampling_ok(const Geometry& geo, int* bad_axis, double* worst);
+
+// Device-side sizes of a plan.
+struct Dims {
+    int64_t npix, nblocks, nwt;   // pixels, workgroup blocks, wave tiles
+    int nx, ny, nz, x_pad, nxc, nzb;
+    int64_t ntiles() const { return (int64_t)nxc * nzb * ny; }
+    size_t wtile_bytes() const { return (size_t)ntiles() * TILE_BYTES; }
+    size_t txa_bytes() const { return (size_t)nwt * nxc * TILE_BYTES; }
+    size_t ty_bytes() const { return (size_t)nwt * ny * WAVE_PIX * 8; }
+    size_t tz_bytes() const { return (size_t)nwt * nzb * 2 * ZB * 8 * 8; }
+};
+Dims make_dims(int64_t npix, int nx, int ny, int nz);
+
+// Arguments of the forward contraction for one plan/target.
+struct FwdArgs {
+    const uint8_t* wtiles;  // effective strength, tile t = (xc * nzb + zb) * ny + y
+    const uint8_t* txa;     // A operand tiles [wt][xc]
+    const float* ty;        // [wt][y][h][8] complex
+    const float* tz;        // [wt][zb][h][32][8] complex
+    float* intensity;       // [npix]
+    float* amplitude;       // [npix] complex or null
+    int64_t npix;
+    int32_t ny, nxc, nzb, x_pad;
+};
+
+// Arguments of the column scan producing the W tiles.
+struct ScanArgs {
+    const float* delta;
+    const float* beta;
+    uint8_t* wtiles;
+    int32_t nx, ny, nz, nxc, nzb;
+    int32_t strength;
+    float k0dz;   // k0 * dz
+    float dV;     // dx * dy * dz
+};
+
+// A batch launch carries every request descriptor in its kernel arguments
+// (no host -> device copy): request r owns work items [item_begin[r],
+// item_begin[r + 1]), item k of it being pixel block block_begin[r] + k.
+constexpr int MAX_BATCH = 24;
+struct BatchArgs {
+    FwdArgs req[MAX_BATCH];
+    int32_t block_begin[MAX_BATCH];
+    int32_t item_begin[MAX_BATCH + 1];
+    int32_t nreq;
+    int32_t* counter;  // device int, reset by the launcher
+};
+
+// Kernel launchers (defined in the .hip sources); return a HIP error code.
+int launch_twiddles(int precision, const Dims& d, const double* q_dev, const double* xs_dev,
+                    const double* ys_dev, const double* zs_dev, uint8_t* txa, float* ty,
+                    float* tz, void* stream);
+int launch_scan(int precision, const ScanArgs& a, void* stream);
+int launch_forward(int precision, const FwdArgs& a, int64_t block_begin, int64_t nblocks,
+                   void* stream);
+int launch_forward_batch(int precision, const BatchArgs& b, int32_t grid, void* stream);
+
+}  // namespace msft
+
+// The plan object behind msft_plan_t.
+struct msft_plan_s {
+    msft::Geometry geo;
+    msft::Dims dims;
+    int device = -1;
+    bool qlist = false;
+    // resident device tables
+    double* q_dev = nullptr;      // [npix][3]
+    double* xs_dev = nullptr;
+    double* ys_dev = nullptr;
+    double* zs_dev = nullptr;
+    uint8_t* txa = nullptr;
+    float* ty = nullptr;
+    float* tz = nullptr;
+    size_t resident_bytes = 0;
+    size_t workspace_bytes = 0;
+};

