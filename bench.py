@@ -32,6 +32,23 @@ PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2500.0}   # MI355X dense matrix peaks
 HBM_PEAK_GBS = 8000.0
 
 
+def profiled_traffic(prec):
+    """HBM bytes per launch of the contraction kernel from the committed counter
+    summary, or None when the kernel source has changed since it was counted."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"fwd_kernel_{prec}_star128_det512_traffic.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"traffic per launch[^:]*:\s*([0-9.eE+]+) bytes", text)
+    h = re.search(r"sha256 when counted:\s*([0-9a-f]{64})", text)
+    src = os.path.join(ROOT, "paper_2202_03411_amd", "csrc", "kernels.hip")
+    if not m or not h or hashlib.sha256(open(src, "rb").read()).hexdigest() != h.group(1):
+        return None
+    return float(m.group(1))
+
+
 def _pct(xs, p):
     xs = sorted(xs)
     k = min(len(xs) - 1, max(0, int(round(p / 100.0 * (len(xs) - 1)))))
@@ -129,6 +146,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["fp32", "bf16x3"], default=None,
                     help="time one precision only (profiling runs)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one 256 MiB device-to-device copy, the reference for "
+                         "scaling hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -140,6 +160,13 @@ def main():
     import torch
 
     from paper_2202_03411_amd import inputs, msft
+
+    if args.calibrate_copy:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     wl = inputs.pattern_workload()
     P = wl.det_n ** 2
@@ -205,7 +232,8 @@ def main():
         "terms_per_s": head["terms_per_s"],
         "roofline": {"bound": "mfma", "achieved": head["contract_tflops"],
                      "peak": PEAK_TFLOPS[head_prec], "unit": "TFLOP/s",
-                     "frac": head["contract_tflops"] / PEAK_TFLOPS[head_prec], "traffic": None,
+                     "frac": head["contract_tflops"] / PEAK_TFLOPS[head_prec],
+                     "traffic": profiled_traffic(head_prec),
                      "kernel": f"fwd_kernel<{head_prec}>",
                      "per_launch": f"{flops:.4e} algorithmic flops (8 per voxel-pixel term)"},
         "scan": {"ms": head["scan_ms"], "gbs": scan_bytes / (head["scan_ms"] * 1e-3) / 1e9,
