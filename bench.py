@@ -146,6 +146,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["fp32", "bf16x3"], default=None,
                     help="time one precision only (profiling runs)")
+    ap.add_argument("--serving", type=int, default=64,
+                    help="requests of the mixed-size serving stream (0 = skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 256 MiB device-to-device copy, the reference for "
                          "scaling hardware byte counters")
@@ -246,6 +248,14 @@ def main():
         r = results["bf16x3"]
         r["roofline_frac_bf16_peak_algorithmic"] = r["contract_tflops"] / PEAK_TFLOPS["bf16x3"]
         r["roofline_frac_bf16_peak_executed"] = 3 * r["contract_tflops"] / PEAK_TFLOPS["bf16x3"]
+    if args.serving > 0 and not args.only:
+        from paper_2202_03411_amd import serving
+        sv = serving.benchmark(args.serving, "fp32", load=0.8)
+        line["serving"] = sv
+        for k in ("offline_batched", "offline_plain", "poisson_batched", "poisson_plain"):
+            print(f"[bench] serving {k}: {sv[k]['patterns_per_s']:.2f} patterns/s, "
+                  f"p50 {sv[k]['p50_ms']:.1f} ms, p99 {sv[k]['p99_ms']:.1f} ms",
+                  file=sys.stderr, flush=True)
     if not args.no_cpu_baseline and not args.only:
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(line))

@@ -180,7 +180,7 @@ msft_status make_plan(const msft_geometry* g, const double* q_host, int64_t npix
         return fail(MSFT_ERR_UNDERSAMPLED, buf);
     }
     p->dims = make_dims(p->geo.npix, g->nx, g->ny, g->nz);
-    p->workspace_bytes = align256(p->dims.wtile_bytes());
+    p->workspace_bytes = std::max(align256(p->dims.wtile_bytes()), align256(make_adj_dims(p->dims).bytes()));
     p->device = device;
     if (device >= 0) {
         int count = 0;
@@ -451,17 +451,55 @@ msft_status msft_backward(msft_plan_t plan, const float* delta, const float* bet
                           const float* amplitude, const float* grad_intensity, float* grad_delta,
                           float* grad_beta, void* workspace, void* stream)
 {
-    (void)delta;
-    (void)beta;
-    (void)amplitude;
-    (void)grad_intensity;
-    (void)grad_delta;
-    (void)grad_beta;
-    (void)workspace;
-    (void)stream;
     msft_status st = check_runnable(plan);
     if (st != MSFT_OK) return st;
-    return fail(MSFT_ERR_UNSUPPORTED, "msft_backward is not available in this build");
+    if (!delta || !beta || !amplitude || !grad_intensity || !grad_delta || !grad_beta || !workspace)
+        return fail(MSFT_ERR_INVALID, "NULL argument");
+    if (!aligned256(workspace)) return fail(MSFT_ERR_INVALID, "workspace must be 256-byte aligned");
+    const Dims& d = plan->dims;
+    const msft_geometry& g = plan->geo.g;
+    const AdjDims ad = make_adj_dims(d);
+    uint8_t* ws = (uint8_t*)workspace;
+    AdjArgs a;
+    a.q = plan->q_dev;
+    a.h = (float*)ws;
+    a.rpart = (float*)(ws + ad.h_bytes);
+    a.npix = d.npix;
+    a.npix_pad = d.nblocks * BLOCK_PIX;
+    a.group_pix = ad.group_pix;
+    a.nx = d.nx;
+    a.ny = d.ny;
+    a.nz = d.nz;
+    a.nxc = d.nxc;
+    a.nzb = d.nzb;
+    a.nyb = ad.nyb;
+    a.nsplit = ad.nsplit;
+    a.xs0 = plan->geo.xs[0];
+    a.ys0 = plan->geo.ys[0];
+    a.zs0 = plan->geo.zs[0];
+    a.dx = g.dx;
+    a.dy = g.dy;
+    a.dz = g.dz;
+    FinArgs f;
+    f.delta = delta;
+    f.beta = beta;
+    f.rpart = a.rpart;
+    f.grad_delta = grad_delta;
+    f.grad_beta = grad_beta;
+    f.nx = d.nx;
+    f.ny = d.ny;
+    f.nz = d.nz;
+    f.nxc = d.nxc;
+    f.nzb = d.nzb;
+    f.nsplit = ad.nsplit;
+    f.strength = g.strength;
+    f.dV = g.dx * g.dy * g.dz;
+    f.k0dz = (2.0 * 3.14159265358979323846) / g.wavelength * g.dz;
+    DeviceScope ds(plan->device);
+    if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice");
+    int e = launch_backward(a, f, amplitude, grad_intensity, stream);
+    if (e) return hip_fail((hipError_t)e, "backward launch");
+    return ok();
 }
 
 const char* msft_status_str(msft_status s)

@@ -1,0 +1,256 @@
+// gfx950 kernels of the MSFT adjoint (gradient of a real loss L(I) with respect
+// to the voxel delta and beta).
+//
+// With h_p = g_p conj(A_p), g = dL/dI, the strength gradient is
+//   R_v = sum_p h_p exp(-i q_p . r_v),        dL = sum_v 2 Re(R_v dw_v),
+// the transposed contraction of the forward model: pixels are the K dimension.
+//  adj_prep      h_p from g and the saved amplitudes.
+//  adj_contract  R over one pixel group per workgroup (split K), MFMA; the
+//                twiddles are regenerated per pixel chunk into LDS from FP64
+//                phases, not read from the plan.
+//  adj_finalize  sums the pixel groups in a fixed order and applies the chain
+//                rule through w = dV (n^2 - 1) T and the column scan (Eqs. (7)-(9)).
+#include <hip/hip_runtime.h>
+
+#include "msft_internal.h"
+
+namespace msft {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr double kInvTwoPi = 0.15915494309189533576888376337251;
+
+__global__ void adj_prep(const float2* amplitude, const float* grad_intensity, float2* h,
+                         int64_t npix, int64_t npix_pad)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npix_pad) return;
+    float2 v = make_float2(0.0f, 0.0f);
+    if (p < npix) {
+        const float2 a = amplitude[p];
+        const float g = grad_intensity[p];
+        v = make_float2(g * a.x, -g * a.y);
+    }
+    h[p] = v;
+}
+
+// exp(i phi) for an FP64 phase: reduced modulo 2 pi in FP64, then FP32 sin/cos
+// of the reduced argument (|phi_r| <= pi).
+__device__ __forceinline__ float2 cis_reduced(double phi)
+{
+    const double k = rint(phi * kInvTwoPi);
+    const float r = (float)(phi - k * kTwoPi);
+    float s, c;
+    sincosf(r, &s, &c);
+    return make_float2(c, s);
+}
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b)
+{
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Workgroup (s, xc, zb, yb): R for x chunk xc (64 x), z block zb (32 z), the 8 y
+// values yb*8 .. yb*8+7 (one per wave), summed over pixel group s.  Per chunk of
+// ADJ_CHUNK pixels the workgroup first writes into LDS
+//   A fragments of Tx = exp(-i q_x x) for the 64 x values, in register order
+//       (row tile rt = x/16, lane (h, i): row i = (x%16, re|im), k-half h),
+//   G = h_p exp(-i q_z z) for the 32 z values, and Ty = exp(-i q_y y) for 8 y,
+// then every wave runs 4 v_mfma_f32_32x32x2_f32 per pixel (one per row tile)
+// with B = component h of Ty * G.  Runs of 8 x (4 z) share one FP64-reduced
+// anchor and a step exp(-i q d) applied by complex multiplication.
+__global__ __launch_bounds__(512) void adj_contract(AdjArgs a)
+{
+    __shared__ __attribute__((aligned(16))) float afrag[ADJ_CHUNK * 64 * 4];
+    __shared__ __attribute__((aligned(16))) float2 gz[ADJ_CHUNK * ZB];
+    __shared__ __attribute__((aligned(16))) float2 ty[ADJ_CHUNK * 8];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int h = lane >> 5, col = lane & 31;
+    int64_t b = blockIdx.x;
+    const int yb = (int)(b % a.nyb);
+    b /= a.nyb;
+    const int zb = (int)(b % a.nzb);
+    b /= a.nzb;
+    const int xc = (int)(b % a.nxc);
+    const int s = (int)(b / a.nxc);
+    const int y = yb * 8 + wave;
+    const bool wave_active = y < a.ny;
+
+    f32x16 C[4];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) C[rt] = f32x16{};
+
+    const int64_t p_begin = (int64_t)s * a.group_pix;
+    const int64_t p_end = min(p_begin + a.group_pix, a.npix_pad);
+    const int gp = tid >> 3, sub = tid & 7;   // generation: pixel, run index
+
+    for (int64_t p0 = p_begin; p0 < p_end; p0 += ADJ_CHUNK) {
+        // ---- twiddles of ADJ_CHUNK pixels into LDS ----
+        {
+            const int64_t p = p0 + gp;
+            double qx = 0.0, qy = 0.0, qz = 0.0;
+            float2 hp = make_float2(0.0f, 0.0f);
+            if (p < a.npix) {
+                qx = a.q[3 * p];
+                qy = a.q[3 * p + 1];
+                qz = a.q[3 * p + 2];
+                hp = ((const float2*)a.h)[p];
+            }
+            // Tx: x = xc*64 + sub*8 + k
+            {
+                const int xl0 = sub * 8;
+                const int x0 = xc * XC + xl0;
+                float2 t = cis_reduced(-(qx * (a.xs0 + (double)x0 * a.dx)));
+                const float2 e = cis_reduced(-(qx * a.dx));
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int xl = xl0 + k;
+                    const float2 v = (x0 + k < a.nx) ? t : make_float2(0.0f, 0.0f);
+                    const int rt = xl >> 4, i0 = 2 * (xl & 15);
+                    float* base = afrag + gp * 256;
+                    base[(i0) * 4 + rt] = v.x;            // h=0, re row: Re T
+                    base[(i0 + 1) * 4 + rt] = v.y;        // h=0, im row: Im T
+                    base[(32 + i0) * 4 + rt] = -v.y;      // h=1, re row: -Im T
+                    base[(32 + i0 + 1) * 4 + rt] = v.x;   // h=1, im row: Re T
+                    t = cmul(t, e);
+                }
+            }
+            // G: z = zb*32 + sub*4 + k
+            {
+                const int zl0 = sub * 4;
+                const int z0 = zb * ZB + zl0;
+                float2 t = cis_reduced(-(qz * (a.zs0 + (double)z0 * a.dz)));
+                const float2 e = cis_reduced(-(qz * a.dz));
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    gz[gp * ZB + zl0 + k] = (z0 + k < a.nz) ? cmul(hp, t) : make_float2(0.0f, 0.0f);
+                    t = cmul(t, e);
+                }
+            }
+            // Ty: y = yb*8 + sub
+            {
+                const int yy = yb * 8 + sub;
+                ty[gp * 8 + sub] = (yy < a.ny) ? cis_reduced(-(qy * (a.ys0 + (double)yy * a.dy)))
+                                               : make_float2(0.0f, 0.0f);
+            }
+        }
+        __syncthreads();
+        // ---- contraction over the chunk's pixels ----
+        if (wave_active) {
+#pragma unroll 4
+            for (int pl = 0; pl < ADJ_CHUNK; ++pl) {
+                const f32x4 av = *(const f32x4*)(afrag + (pl * 64 + lane) * 4);
+                const float2 g = gz[pl * ZB + col];
+                const float2 t = ty[pl * 8 + wave];
+                const float bv = (h == 0) ? (t.x * g.x - t.y * g.y) : (t.x * g.y + t.y * g.x);
+                C[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[0], bv, C[0], 0, 0, 0);
+                C[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[1], bv, C[1], 0, 0, 0);
+                C[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[2], bv, C[2], 0, 0, 0);
+                C[3] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[3], bv, C[3], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+
+    if (!wave_active) return;
+    // rows 8j + 4h + u of row tile rt: x = rt*16 + 4j + 2h + u/2, component u&1
+    const int64_t X2 = (int64_t)a.nxc * XC, NZ2 = (int64_t)a.nzb * ZB;
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+#pragma unroll
+            for (int u2 = 0; u2 < 2; ++u2) {
+                const int xl = rt * 16 + 4 * j + 2 * h + u2;
+                const int64_t idx = (((int64_t)s * X2 + xc * XC + xl) * a.ny + y) * NZ2 + zb * ZB + col;
+                ((float2*)a.rpart)[idx] = make_float2(C[rt][4 * j + 2 * u2], C[rt][4 * j + 2 * u2 + 1]);
+            }
+        }
+    }
+}
+
+// One thread per (x, y) column.  Reverse pass over z with FP64 running sums:
+// the exclusive prefix S_c of (beta + i delta) is the column total minus the
+// suffix, and sum_{c'>c} R_c' w_c' accumulates on the way down.
+__global__ void adj_finalize(FinArgs a)
+{
+    const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= (int64_t)a.nx * a.ny) return;
+    const int x = (int)(col / a.ny), y = (int)(col % a.ny);
+    const float* dcol = a.delta + col * a.nz;
+    const float* bcol = a.beta + col * a.nz;
+    double tot_b = 0.0, tot_d = 0.0;
+    for (int c = 0; c < a.nz; ++c) {
+        tot_b += (double)bcol[c];
+        tot_d += (double)dcol[c];
+    }
+    const int64_t X2 = (int64_t)a.nxc * XC, NZ2 = (int64_t)a.nzb * ZB;
+    const int64_t part_stride = X2 * a.ny * NZ2;
+    const float2* rp = (const float2*)a.rpart + ((int64_t)x * a.ny + y) * NZ2;
+    double suf_b = 0.0, suf_d = 0.0, srw_r = 0.0, srw_i = 0.0;
+    const double dV = a.dV, k0dz = a.k0dz;
+    for (int c = a.nz - 1; c >= 0; --c) {
+        const double d = dcol[c], bt = bcol[c];
+        double rr = 0.0, ri = 0.0;
+        for (int s = 0; s < a.nsplit; ++s) {
+            const float2 v = rp[s * part_stride + c];
+            rr += v.x;
+            ri += v.y;
+        }
+        double gd, gb;
+        if (a.strength == MSFT_STRENGTH_DENSITY) {
+            gd = 2.0 * dV * rr;
+            gb = -2.0 * dV * ri;
+        } else {
+            double tr = 1.0, ti = 0.0;
+            if (a.strength == MSFT_STRENGTH_MSFT) {
+                const double sb = tot_b - suf_b - bt, sd = tot_d - suf_d - d;
+                const double mag = exp(-k0dz * sb);
+                double sn, cs;
+                sincos(-k0dz * sd, &sn, &cs);
+                tr = mag * cs;
+                ti = mag * sn;
+            }
+            const double nr = 1.0 - d, ni = bt;
+            // dw/d delta = dV T (-2 n), dw/d beta = dV T (2 i n)
+            const double dd_r = dV * (-2.0) * (tr * nr - ti * ni);
+            const double dd_i = dV * (-2.0) * (tr * ni + ti * nr);
+            const double db_r = dV * 2.0 * (-(tr * ni + ti * nr));
+            const double db_i = dV * 2.0 * (tr * nr - ti * ni);
+            gd = 2.0 * (rr * dd_r - ri * dd_i);
+            gb = 2.0 * (rr * db_r - ri * db_i);
+            if (a.strength == MSFT_STRENGTH_MSFT) {
+                gd += 2.0 * k0dz * srw_i;
+                gb -= 2.0 * k0dz * srw_r;
+                const double chr = d * (d - 2.0) - bt * bt, chi = 2.0 * bt * (1.0 - d);
+                const double wr = dV * (chr * tr - chi * ti), wi = dV * (chr * ti + chi * tr);
+                srw_r += rr * wr - ri * wi;
+                srw_i += rr * wi + ri * wr;
+            }
+        }
+        a.grad_delta[col * a.nz + c] = (float)gd;
+        a.grad_beta[col * a.nz + c] = (float)gb;
+        suf_b += bt;
+        suf_d += d;
+    }
+}
+
+int launch_backward(const AdjArgs& adj, const FinArgs& fin, const float* amplitude,
+                    const float* grad_intensity, void* stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t np = adj.npix_pad;
+    hipLaunchKernelGGL(adj_prep, dim3((unsigned)ceil_div(np, 256)), dim3(256), 0, s,
+                       (const float2*)amplitude, grad_intensity, (float2*)adj.h, adj.npix, np);
+    const int64_t nblocks = (int64_t)adj.nsplit * adj.nxc * adj.nzb * adj.nyb;
+    hipLaunchKernelGGL(adj_contract, dim3((unsigned)nblocks), dim3(512), 0, s, adj);
+    const int64_t ncol = (int64_t)fin.nx * fin.ny;
+    hipLaunchKernelGGL(adj_finalize, dim3((unsigned)ceil_div(ncol, 128)), dim3(128), 0, s, fin);
+    return (int)hipGetLastError();
+}
+
+}  // namespace msft

@@ -109,4 +109,23 @@ Dims make_dims(int64_t npix, int nx, int ny, int nz)
     return d;
 }
 
+// Pixel groups of the adjoint's split K: enough workgroups to fill the chip
+// (about 2048) without making a group smaller than one LDS chunk.
+AdjDims make_adj_dims(const Dims& d)
+{
+    AdjDims a;
+    a.nyb = (int32_t)ceil_div(d.ny, 8);
+    const int64_t npix_pad = d.nblocks * BLOCK_PIX;
+    const int64_t chunks = ceil_div(npix_pad, ADJ_CHUNK);
+    const int64_t base = (int64_t)d.nxc * d.nzb * a.nyb;
+    int64_t split = ceil_div(2048, base);
+    if (split < 1) split = 1;
+    if (split > chunks) split = chunks;
+    a.group_pix = ceil_div(chunks, split) * ADJ_CHUNK;
+    a.nsplit = (int32_t)ceil_div(npix_pad, a.group_pix);
+    a.h_bytes = (size_t)(ceil_div(npix_pad * 8, 256) * 256);
+    a.rpart_bytes = (size_t)a.nsplit * d.nxc * XC * d.ny * d.nzb * ZB * 8;
+    return a;
+}
+
 }  // namespace msft

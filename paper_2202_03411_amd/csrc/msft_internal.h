@@ -97,7 +97,42 @@ struct BatchArgs {
     int32_t* counter;  // device int, reset by the launcher
 };
 
+// Adjoint: pixels per LDS chunk of the transposed contraction (one per 8 threads).
+constexpr int ADJ_CHUNK = 64;
+
+// Split-K layout of the adjoint: pixel group s of group_pix pixels writes its
+// partial R into rpart[s][x (nxc*64)][y][z (nzb*32)] complex.
+struct AdjDims {
+    int64_t group_pix;
+    int32_t nsplit, nyb;
+    size_t h_bytes, rpart_bytes;
+    size_t bytes() const { return h_bytes + rpart_bytes; }
+};
+AdjDims make_adj_dims(const Dims& d);
+
+struct AdjArgs {
+    const double* q;   // [npix][3]
+    float* h;          // [npix_pad] complex: g_p conj(A_p)
+    float* rpart;      // partial strength gradients, see AdjDims
+    int64_t npix, npix_pad, group_pix;
+    int32_t nx, ny, nz, nxc, nzb, nyb, nsplit;
+    double xs0, ys0, zs0;  // coordinate of voxel index 0 on each axis
+    double dx, dy, dz;
+};
+
+struct FinArgs {
+    const float* delta;
+    const float* beta;
+    const float* rpart;
+    float* grad_delta;
+    float* grad_beta;
+    int32_t nx, ny, nz, nxc, nzb, nsplit, strength;
+    double dV, k0dz;
+};
+
 // Kernel launchers (defined in the .hip sources); return a HIP error code.
+int launch_backward(const AdjArgs& adj, const FinArgs& fin, const float* amplitude,
+                    const float* grad_intensity, void* stream);
 int launch_twiddles(int precision, const Dims& d, const double* q_dev, const double* xs_dev,
                     const double* ys_dev, const double* zs_dev, uint8_t* txa, float* ty,
                     float* tz, void* stream);

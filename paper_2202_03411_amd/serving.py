@@ -1,0 +1,396 @@
+"""Continuous-batching server for MSFT pattern requests.
+
+Requests of uneven grid and detector sizes arrive over time (the candidate
+simulations of forward fitting, Sec. 6).  The scheduler keeps one plan per
+geometry resident (q map and twiddle tables), admits queued requests while the
+in-flight HBM footprint stays under a budget and a launch slot is free, and
+runs each admitted group as one persistent batched launch
+(``msft_simulate_batch``).  Several launches can be in flight on separate
+streams, so requests that arrive while others are on the GPU start as soon as
+a slot and memory free up and their work overlaps the tail of earlier
+launches.  Per-request latency is arrival -> completion as seen by the host.
+
+The scheduler talks to an executor object; ``GpuExecutor`` drives the library,
+tests use a fake one with modelled durations.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import math
+import time
+from typing import Callable
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    arrival: float                 # seconds, on the server clock
+    key: tuple                     # geometry key: (wavelength, theta, det_n, grid, pitch, mode)
+    payload: object = None         # executor-specific inputs (device delta/beta, ...)
+    admitted: float = math.nan
+    done: float = math.nan
+    footprint: int = 0
+    result: object = None
+
+    @property
+    def latency(self):
+        return self.done - self.arrival
+
+
+@dataclasses.dataclass
+class Batch:
+    requests: list
+    handle: object
+    footprint: int
+    launched: float
+
+
+class Scheduler:
+    """Admission + batching policy, independent of the device.
+
+    executor must provide:
+      footprint(req) -> bytes the request holds while in flight
+      launch(list[Request]) -> handle        (asynchronous)
+      poll(handle) -> bool                    (True once finished)
+      finish(handle, list[Request])          (collect results, free buffers)
+    """
+
+    def __init__(self, executor, hbm_budget: int, max_inflight: int = 3, max_batch: int = 24,
+                 clock: Callable[[], float] = time.perf_counter):
+        if max_inflight < 1 or max_batch < 1:
+            raise ValueError("max_inflight and max_batch must be >= 1")
+        self.ex = executor
+        self.budget = int(hbm_budget)
+        self.max_inflight = max_inflight
+        self.max_batch = max_batch
+        self.clock = clock
+        self.queue: collections.deque = collections.deque()
+        self.inflight: list = []
+        self.used = 0
+        self.completed: list = []
+        self.rejected: list = []
+
+    def submit(self, req: Request):
+        req.footprint = int(self.ex.footprint(req))
+        if req.footprint > self.budget:
+            # could never be admitted: refuse instead of blocking the queue
+            self.rejected.append(req)
+            return False
+        self.queue.append(req)
+        return True
+
+    def retire(self):
+        now = self.clock()
+        still = []
+        for b in self.inflight:
+            if self.ex.poll(b.handle):
+                self.ex.finish(b.handle, b.requests)
+                for r in b.requests:
+                    r.done = now
+                    self.completed.append(r)
+                self.used -= b.footprint
+            else:
+                still.append(b)
+        self.inflight = still
+
+    def admit_and_launch(self):
+        """Form at most one batch from the head of the queue (FIFO, no overtaking)."""
+        if len(self.inflight) >= self.max_inflight or not self.queue:
+            return None
+        batch, foot = [], 0
+        while self.queue and len(batch) < self.max_batch:
+            r = self.queue[0]
+            if self.used + foot + r.footprint > self.budget:
+                break
+            batch.append(self.queue.popleft())
+            foot += r.footprint
+        if not batch:
+            return None
+        now = self.clock()
+        for r in batch:
+            r.admitted = now
+        handle = self.ex.launch(batch)
+        b = Batch(batch, handle, foot, now)
+        self.inflight.append(b)
+        self.used += foot
+        return b
+
+    def idle(self):
+        return not self.queue and not self.inflight
+
+    def step(self):
+        self.retire()
+        launched = 0
+        while self.admit_and_launch() is not None:
+            launched += 1
+        return launched
+
+
+def run_stream(scheduler: Scheduler, requests, poll_sleep: float = 2e-4):
+    """Replay requests at their arrival times (seconds from start) through a scheduler."""
+    pending = sorted(requests, key=lambda r: r.arrival)
+    t0 = scheduler.clock()
+    for r in pending:
+        r.arrival += t0
+    i = 0
+    while i < len(pending) or not scheduler.idle():
+        now = scheduler.clock()
+        while i < len(pending) and pending[i].arrival <= now:
+            scheduler.submit(pending[i])
+            i += 1
+        launched = scheduler.step()
+        if not launched and i < len(pending) and scheduler.idle():
+            wait = pending[i].arrival - scheduler.clock()
+            if wait > 0:
+                time.sleep(min(wait, 0.01))
+        elif not launched:
+            time.sleep(poll_sleep)
+    return t0
+
+
+def poisson_arrivals(n: int, rate: float, seed: int):
+    """Arrival times (s) of a Poisson process of the given rate."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=n))
+
+
+def summarize(requests, t0: float, t_end: float):
+    lat = sorted(r.latency for r in requests)
+
+    def pct(p):
+        if not lat:
+            return math.nan
+        k = min(len(lat) - 1, max(0, int(math.ceil(p / 100.0 * len(lat))) - 1))
+        return lat[k]
+
+    span = t_end - t0
+    return {"requests": len(lat), "makespan_s": span,
+            "patterns_per_s": len(lat) / span if span > 0 else math.nan,
+            "p50_ms": 1e3 * pct(50), "p99_ms": 1e3 * pct(99), "max_ms": 1e3 * (lat[-1] if lat else math.nan),
+            "mean_ms": 1e3 * (sum(lat) / len(lat) if lat else math.nan)}
+
+
+# ---------------------------------------------------------------------------
+# GPU executor
+# ---------------------------------------------------------------------------
+
+class PlanCache:
+    """One resident plan per (geometry, precision); plans are built on first use."""
+
+    def __init__(self, msft, precision: str, device: int = 0):
+        self.msft = msft
+        self.precision = precision
+        self.device = device
+        self.plans = {}
+
+    def get(self, key):
+        p = self.plans.get(key)
+        if p is None:
+            wavelength, theta, det_n, grid, pitch, mode = key
+            p = self.msft.Plan(wavelength, theta, det_n, grid, pitch, self.precision, mode,
+                               self.device)
+            self.plans[key] = p
+        return p
+
+    def resident_bytes(self):
+        return sum(p.resident_bytes for p in self.plans.values())
+
+    def close(self):
+        for p in self.plans.values():
+            p.close()
+        self.plans.clear()
+
+
+class GpuExecutor:
+    """Runs each admitted group as one persistent batched launch.
+
+    Every in-flight launch owns one stream of a small pool (default priority)
+    and its own workspace, so launches overlap on the device.  With
+    ``batched=False`` every request is its own msft_simulate launch on a single
+    stream (the plain one-pattern-per-launch form), reusing the plan's workspace.
+    """
+
+    def __init__(self, plans: PlanCache, torch, nstreams: int = 3, batched: bool = True):
+        self.plans = plans
+        self.torch = torch
+        self.msft = plans.msft
+        self.batched = batched
+        n = nstreams if batched else 1
+        self.streams = [torch.cuda.Stream() for _ in range(n)]
+        self.free = list(range(n))
+
+    def footprint(self, req):
+        p = self.plans.get(req.key)
+        out = 4 * p.npix
+        if not self.batched:
+            return out
+        d, b = req.payload
+        return self.msft.msft_batch_query([(p.handle, d, b, d, None)]) + out
+
+    def launch(self, batch):
+        torch = self.torch
+        sidx = self.free.pop() if self.batched else 0
+        s = self.streams[sidx]
+        outs, reqs, keep = [], [], []
+        with torch.cuda.stream(s):
+            for r in batch:
+                p = self.plans.get(r.key)
+                d, b = r.payload
+                I = torch.empty(p.npix, dtype=torch.float32, device="cuda")
+                outs.append(I)
+                reqs.append((p.handle, d, b, I, None))
+            if self.batched:
+                ws = self.msft.workspace_tensor(self.msft.msft_batch_query(reqs), "cuda")
+                self.msft.msft_simulate_batch(reqs, ws, stream=s)
+                keep.append(ws)
+            else:
+                for (h, d, b, I, _), r in zip(reqs, batch):
+                    self.msft.msft_simulate(h, d, b, I, None, self.plans.get(r.key).workspace(),
+                                            stream=s)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        return {"event": ev, "stream": sidx, "outs": outs, "keep": keep}
+
+    def poll(self, handle):
+        return handle["event"].query()
+
+    def finish(self, handle, batch):
+        for r, I in zip(batch, handle["outs"]):
+            r.result = I
+        handle["keep"].clear()
+        if self.batched:
+            self.free.append(handle["stream"])
+
+
+# ---------------------------------------------------------------------------
+# seeded request streams (shapes rendered on the device)
+# ---------------------------------------------------------------------------
+
+SERVE_GRIDS = (64, 96, 128, 192)
+SERVE_DETS = (256, 512, 1024)
+
+
+class ShapePool:
+    """A few hard-voxel shapes per grid size, rendered on the GPU from seeds:
+    ellipsoids (semi-axes U[80, 250] nm, Haar-random orientation) and l <= 8
+    harmonic bodies (R0 ~ U[80, 170] nm, c ~ N(0, 0.08^2), r_max <= 340 nm),
+    all in one fixed box so that a (grid, detector) pair shares one plan."""
+
+    def __init__(self, torch, grids=SERVE_GRIDS, per_kind=2, box=700.0, delta0=0.01, beta0=0.02,
+                 seed=0, device="cuda"):
+        import numpy as np
+
+        from . import inputs
+        from .fit import real_sh_torch
+        self.box = box
+        self.shapes = {}
+        rng = np.random.default_rng(seed)
+        for n in grids:
+            c = (torch.arange(n, dtype=torch.float32, device=device) * 2.0 + 1.0 - n) * (box / n) / 2.0
+            X, Y, Z = torch.meshgrid(c, c, c, indexing="ij")
+            rr = torch.sqrt(X * X + Y * Y + Z * Z)
+            theta = torch.arccos(torch.clamp(Z / torch.where(rr > 0, rr, torch.ones_like(rr)), -1, 1))
+            phi = torch.atan2(Y, X)
+            basis = real_sh_torch(8, theta, phi).reshape(81, -1)
+            lst = []
+            for _ in range(per_kind):
+                axes = rng.uniform(80.0, 250.0, size=3)
+                R = torch.tensor(inputs.haar_rotation(rng), dtype=torch.float32, device=device)
+                P = torch.stack([X, Y, Z], dim=-1) @ R
+                s = sum((P[..., k] / float(axes[k])) ** 2 for k in range(3))
+                lst.append((s <= 1.0).float())
+            for _ in range(per_kind):
+                while True:
+                    r0 = float(rng.uniform(80.0, 170.0))
+                    coeffs = inputs.sh_coefficients(rng, 1, 8, 0.08)
+                    _, rmax = inputs.sh_radius_range(coeffs, r0, 91, 181)
+                    if rmax <= 340.0:
+                        break
+                cvec = torch.zeros(81, dtype=torch.float32, device=device)
+                for l, m, v in coeffs:
+                    cvec[l * l + l + m] = v
+                rs = r0 * (1.0 + cvec @ basis)
+                lst.append((rr.reshape(-1) <= rs).float().reshape(n, n, n))
+            self.shapes[n] = [((o * delta0).contiguous(), (o * beta0).contiguous()) for o in lst]
+            del basis
+
+    def pick(self, n, k):
+        return self.shapes[n][k % len(self.shapes[n])]
+
+
+def make_requests(pool, count, seed, rate=None, wavelength=45.0, theta=60.0,
+                  grids=SERVE_GRIDS, dets=SERVE_DETS):
+    """Seeded requests: uniform grid and detector size, a pool shape; Poisson
+    arrivals at `rate` per second, or all at t = 0 when rate is None."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    arr = poisson_arrivals(count, rate, seed + 1) if rate else np.zeros(count)
+    out = []
+    for k in range(count):
+        n = int(rng.choice(grids))
+        det = int(rng.choice(dets))
+        shape = int(rng.integers(0, 1 << 30))
+        pitch = pool.box / n
+        key = (wavelength, theta, det, (n, n, n), (pitch, pitch, pitch), "msft")
+        out.append(Request(k, float(arr[k]), key, pool.pick(n, shape)))
+    return out
+
+
+def serve(torch, msft, plans, requests, batched=True, hbm_budget=16 << 30, slots=3, max_batch=24):
+    """Run a request list through the server; returns (summary, requests)."""
+    ex = GpuExecutor(plans, torch, nstreams=slots, batched=batched)
+    sched = Scheduler(ex, hbm_budget, max_inflight=slots if batched else 1 << 30,
+                      max_batch=max_batch if batched else 1)
+    t0 = run_stream(sched, requests)
+    torch.cuda.synchronize()
+    t_end = max(r.done for r in sched.completed) if sched.completed else t0
+    s = summarize(sched.completed, t0, t_end)
+    s["rejected"] = len(sched.rejected)
+    s["mode"] = "batched" if batched else "plain"
+    return s, sched.completed
+
+
+def service_estimate_s(key, tflops):
+    """Rough contraction time of one request at a given algorithmic TFLOP/s."""
+    _, _, det, grid, _, _ = key
+    n = grid[0]
+    return 8.0 * det * det * n ** 3 / (tflops * 1e12)
+
+
+def benchmark(count=96, precision="fp32", load=0.8, seed=20220205, device=0):
+    """Offline (all requests at t = 0) and Poisson (offered load `load` of the
+    estimated capacity) streams, batched against one pattern per launch."""
+    import torch
+
+    from . import msft
+    pool = ShapePool(torch, seed=seed)
+    plans = PlanCache(msft, precision, device)
+    tf = 126.0 if precision == "fp32" else 440.0
+    probe = make_requests(pool, count, seed, None)
+    for r in probe:
+        plans.get(r.key)          # plans and twiddles resident before the clock starts
+    mean_s = sum(service_estimate_s(r.key, tf) for r in probe) / len(probe)
+    rate = load / mean_s
+    out = {"precision": precision, "requests": count, "resident_plans": len(plans.plans),
+           "resident_bytes": plans.resident_bytes(), "offered_rate_per_s": rate,
+           "mean_service_estimate_ms": 1e3 * mean_s}
+    for name, r8 in (("offline", None), ("poisson", rate)):
+        for batched in (True, False):
+            reqs = make_requests(pool, count, seed, r8)
+            s, _ = serve(torch, msft, plans, reqs, batched=batched)
+            out[f"{name}_{s['mode']}"] = s
+    plans.close()
+    return out
+
+
+if __name__ == "__main__":
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description="serve a seeded stream of MSFT requests")
+    ap.add_argument("--requests", type=int, default=96)
+    ap.add_argument("--precision", choices=["fp32", "bf16x3"], default="fp32")
+    ap.add_argument("--load", type=float, default=0.8)
+    args = ap.parse_args()
+    print(json.dumps(benchmark(args.requests, args.precision, args.load)))

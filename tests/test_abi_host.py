@@ -108,8 +108,12 @@ def test_query_sizes_and_host_only_refusal():
     try:
         npix, ws, res = msft.msft_plan_query(h)
         assert npix == 400
-        # W tiles: ceil(150/64) x chunks * ceil(33/32) z blocks * 5 y, 16 KiB each
-        assert ws == 3 * 2 * 5 * 16384
+        # forward: W tiles, ceil(150/64) x chunks * ceil(33/32) z blocks * 5 y, 16 KiB each;
+        # backward: h (512 padded pixels, complex64) + 8 pixel groups of partial
+        # strength gradients over the padded 192 x 5 x 64 grid
+        fwd = 3 * 2 * 5 * 16384
+        bwd = 512 * 8 + 8 * 192 * 5 * 64 * 8
+        assert ws == max(fwd, bwd)
         assert res == 0
         s = msft._lib.msft_simulate(ctypes.c_void_p(h), None, None, None, None, None, None)
         assert s == msft.MSFT_ERR_UNSUPPORTED

@@ -1,0 +1,204 @@
+"""GPU adjoint: msft_backward against the FP64 oracle's gradient and against
+finite differences of the library's own forward model.  Tolerance: relative
+error 1e-3, the bound required for the adjoint gradient."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2202_03411_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-3
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2202_03411_amd import fit, msft
+    return torch, msft, fit
+
+
+def _rel(a, b):
+    a, b = np.ravel(a), np.ravel(b)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _gpu_grad(env, wl, g, mode_name):
+    torch, msft, _ = env
+    with msft.Plan(wl.wavelength, wl.theta_max_deg, wl.det_n, wl.grid, wl.pitch, "fp32",
+                   mode_name) as plan:
+        d = torch.from_numpy(wl.delta).cuda()
+        b = torch.from_numpy(wl.beta).cuda()
+        I, A = plan.simulate(d, b, amplitude=True)
+        gd, gb = torch.empty_like(d), torch.empty_like(b)
+        msft.msft_backward(plan.handle, d, b, torch.view_as_real(A).contiguous(),
+                           torch.from_numpy(g.astype(np.float32)).cuda(), gd, gb, plan.workspace())
+        torch.cuda.synchronize()
+        return gd.cpu().numpy().astype(np.float64), gb.cpu().numpy().astype(np.float64)
+
+
+CASES = [
+    ("ragged_msft", (37, 29, 45), 23, (9.0, 8.0, 7.0), "msft", inputs.MODE_MSFT, 1),
+    ("xchunks_born", (150, 5, 33), 20, (3.0, 9.0, 8.0), "born", inputs.MODE_BORN, 2),
+    ("density", (20, 17, 40), 30, (8.0, 8.0, 8.0), "density", inputs.MODE_DENSITY, 3),
+    ("tiny", (1, 1, 1), 1, (10.0, 10.0, 10.0), "msft", inputs.MODE_MSFT, 4),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_backward_matches_oracle(env, case):
+    name, grid, det, pitch, mode_name, mode, seed = case
+    rng = np.random.default_rng(seed)
+    d = rng.uniform(0, 0.05, grid).astype(np.float32)
+    b = rng.uniform(0, 0.05, grid).astype(np.float32)
+    wl = inputs.Workload(name, 45.0, 60.0, det, pitch, mode, d, b)
+    g = rng.normal(size=det * det)
+    print(f"[gpu] backward {name} grid={grid} det={det}", flush=True)
+    gd, gb = _gpu_grad(env, wl, g, mode_name)
+    q = oracle.qmap(45.0, 60.0, det)
+    w = oracle.strength(mode, d.astype(np.float64), b.astype(np.float64), pitch, 45.0)
+    A = oracle.amplitude(q, w, pitch, 1)
+    od, ob = oracle.backward(mode, q, g, A, d.astype(np.float64), b.astype(np.float64), pitch, 45.0)
+    print(f"  rel L2 d/delta {_rel(gd, od):.3e}  d/beta {_rel(gb, ob):.3e}")
+    assert _rel(gd, od) <= TOL
+    assert _rel(gb, ob) <= TOL
+
+
+def test_backward_sampled_columns(env):
+    # a 64^3 star body on a 128^2 detector, gradient checked on seeded columns
+    wl = inputs.star_workload(n=64, det_n=128, seed=inputs.SEED_BASE + 7)
+    rng = np.random.default_rng(8)
+    g = rng.normal(size=wl.det_n ** 2)
+    gd, gb = _gpu_grad(env, wl, g, "msft")
+    q = oracle.qmap(wl.wavelength, wl.theta_max_deg, wl.det_n)
+    d64, b64 = wl.delta.astype(np.float64), wl.beta.astype(np.float64)
+    w = oracle.strength(oracle.MSFT, d64, b64, wl.pitch, wl.wavelength)
+    A = oracle.amplitude(q, w, wl.pitch, 1)
+    # columns through the object, where the gradient is large
+    filled = np.flatnonzero(wl.delta.reshape(-1, wl.grid[2]).sum(axis=1) > 0)
+    cols = np.sort(rng.choice(filled, size=24, replace=False))
+    od, ob = oracle.backward(oracle.MSFT, q, g, A, d64, b64, wl.pitch, wl.wavelength, cols=cols)
+    nz = wl.grid[2]
+    gd_c, gb_c = gd.reshape(-1, nz)[cols], gb.reshape(-1, nz)[cols]
+    print(f"  sampled columns rel L2 {_rel(gd_c, od):.3e} {_rel(gb_c, ob):.3e}")
+    assert _rel(gd_c, od) <= TOL
+    assert _rel(gb_c, ob) <= TOL
+
+
+def test_backward_directional_fd_full_size(env):
+    # the 128^3 / 512^2 pattern: <grad, v> against a central difference of the
+    # library's FP32 forward along a random direction v inside the object.  The
+    # difference of two FP32 patterns carries rounding noise of about 1e-7 of L,
+    # so the step is large (8% of delta per voxel) and the pixel weights positive
+    # (no cancellation in L); smaller steps are noise-bound, not truncation-bound.
+    torch, msft, _ = env
+    wl = inputs.pattern_workload()
+    rng = np.random.default_rng(9)
+    mask = (wl.delta > 0).astype(np.float32)
+    vd = (rng.normal(size=wl.grid).astype(np.float32) * mask * 0.01)
+    vb = (rng.normal(size=wl.grid).astype(np.float32) * mask * 0.01)
+    gw = np.abs(rng.normal(size=wl.det_n ** 2)) + 0.5
+    g = torch.from_numpy(gw.astype(np.float32)).cuda()
+    with msft.Plan.for_workload(wl, "fp32") as plan:
+        d = torch.from_numpy(wl.delta).cuda()
+        b = torch.from_numpy(wl.beta).cuda()
+        I, A = plan.simulate(d, b, amplitude=True)
+        gd, gb = torch.empty_like(d), torch.empty_like(b)
+        msft.msft_backward(plan.handle, d, b, torch.view_as_real(A).contiguous(), g, gd, gb,
+                           plan.workspace())
+        vdt, vbt = torch.from_numpy(vd).cuda(), torch.from_numpy(vb).cuda()
+        pred = float((gd.double() * vdt.double()).sum() + (gb.double() * vbt.double()).sum())
+        eps = 0.08
+
+        def L(s):
+            Ip = plan.simulate(d + s * vdt, b + s * vbt)
+            return float((g.double() * Ip.double()).sum())
+
+        fd = (L(eps) - L(-eps)) / (2 * eps)
+        torch.cuda.synchronize()
+    print(f"  directional derivative: adjoint {pred:.6e}  central difference {fd:.6e}")
+    assert abs(fd - pred) <= TOL * abs(pred)
+
+
+def _sh_setup(torch, fit, unit):
+    # the same harmonic body and experiment in nm (unit = 1) or um (unit = 1e-3)
+    n, det, lmax = 32, 48, 4
+    star = fit.SoftStar(n, 680.0 * unit, lmax, r0=200.0 * unit, device="cuda")
+    rng = np.random.default_rng(10)
+    c_true = torch.tensor(rng.normal(0, 0.08, star.ncoef), dtype=torch.float32, device="cuda")
+    c_true[0] = 0.0
+    c0 = c_true + torch.tensor(rng.normal(0, 0.03, star.ncoef), dtype=torch.float32, device="cuda")
+    return n, det, star, c_true, c0
+
+
+def _autograd_grad(torch, msft, fit, plan, star, c_true, c0):
+    with torch.no_grad():
+        dt, bt = star.voxelize(c_true)
+        target = plan.simulate(dt.contiguous(), bt.contiguous())
+    c = c0.clone().requires_grad_(True)
+    d, b = star.voxelize(c)
+    loss = fit.log_mse_loss(fit.simulate(d, b, plan), target)
+    loss.backward()
+    return c.grad.double().cpu().numpy(), target
+
+
+IDX = [1, 2, 5, 9, 14, 20]
+
+
+def test_autograd_sh_coefficients_fd(env):
+    # soft-voxelized harmonic body -> library forward -> log-intensity MSE loss;
+    # d loss / d c_lm by autograd through msft_backward against central
+    # differences of the same FP32 pipeline.  Lengths in um: the loss's +1e-6
+    # then sits about 1e-4 below the peak intensity and keeps the finite
+    # difference above the FP32 rounding of the darkest pixels.
+    torch, msft, fit = env
+    unit = 1e-3
+    n, det, star, c_true, c0 = _sh_setup(torch, fit, unit)
+    with msft.Plan(45.0 * unit, 60.0, det, (n, n, n), (star.pitch,) * 3, "fp32", "msft") as plan:
+        grad, target = _autograd_grad(torch, msft, fit, plan, star, c_true, c0)
+
+        def f(cv):
+            with torch.no_grad():
+                dd, bb = star.voxelize(cv)
+                I = plan.simulate(dd.contiguous(), bb.contiguous())
+                return float(torch.mean((torch.log(I.double() + 1e-6) - torch.log(target.double() + 1e-6)) ** 2))
+
+        h = 1e-3
+        fd = []
+        for k in IDX:
+            e = torch.zeros_like(c0)
+            e[k] = h
+            fd.append((f(c0 + e) - f(c0 - e)) / (2 * h))
+    fd = np.array(fd)
+    print(f"  autograd {grad[IDX]}\n  central  {fd}")
+    assert np.linalg.norm(grad[IDX] - fd) <= TOL * np.linalg.norm(fd)
+
+
+def test_autograd_sh_coefficients_vs_oracle_nm(env):
+    # the same fit in nm, where the +1e-6 is inert and the loss is dominated by
+    # pixels 1e-13 below the peak: the FP32 forward resolves those to ~1%, which
+    # bounds the coefficient gradient at a few 1e-3 of the FP64 gradient
+    # (oracle forward, oracle adjoint, float64 chain through the voxelizer).
+    import torch
+    _, msft, fit = env
+    n, det, star, c_true, c0 = _sh_setup(torch, fit, 1.0)
+    pitch = (star.pitch,) * 3
+    with msft.Plan(45.0, 60.0, det, (n, n, n), pitch, "fp32", "msft") as plan:
+        grad, target = _autograd_grad(torch, msft, fit, plan, star, c_true, c0)
+    star64 = fit.SoftStar(n, 680.0, 4, r0=200.0, device="cpu", dtype=torch.float64)
+    c64 = c0.double().cpu().requires_grad_(True)
+    d64, b64 = star64.voxelize(c64)
+    dn, bn = d64.detach().numpy(), b64.detach().numpy()
+    I64, A64 = oracle.simulate(oracle.MSFT, 45.0, 60.0, det, dn, bn, pitch)
+    T = target.double().cpu().numpy()
+    gI = 2.0 * (np.log(I64 + 1e-6) - np.log(T + 1e-6)) / (I64 + 1e-6) / I64.size
+    q = oracle.qmap(45.0, 60.0, det)
+    gd, gb = oracle.backward(oracle.MSFT, q, gI, A64, dn, bn, pitch, 45.0)
+    (d64 * torch.from_numpy(gd) + b64 * torch.from_numpy(gb)).sum().backward()
+    exact = c64.grad.numpy()
+    err = np.linalg.norm(grad - exact) / np.linalg.norm(exact)
+    print(f"  coefficient gradient vs FP64: relative {err:.3e}")
+    assert err <= 5e-3
