@@ -107,6 +107,30 @@ def time_batch(msft, torch, plan, ds, bs, steps, warmup):
     return batched_ms, plain_ms
 
 
+def oracle_error(wl, I_gpu, npix=256):
+    """Relative L2 intensity error of a GPU pattern against the FP64 oracle on
+    seeded pixels (all of them and the wide-angle ring theta > 3/4 theta_max)."""
+    import numpy as np
+
+    import oracle
+    from paper_2202_03411_amd import inputs
+
+    pix = inputs.random_pixels(wl.det_n, npix, seed=31)
+    Io, _ = oracle.simulate(wl.mode, wl.wavelength, wl.theta_max_deg, wl.det_n,
+                            wl.delta.astype(np.float64), wl.beta.astype(np.float64), wl.pitch,
+                            pixels=pix)
+    Ig = I_gpu.detach().cpu().numpy().astype(np.float64)[pix]
+    q = oracle.qmap(wl.wavelength, wl.theta_max_deg, wl.det_n)[pix]
+    k0 = 2 * np.pi / wl.wavelength
+    ring = np.degrees(np.arccos((q[:, 2] + k0) / k0)) > 0.75 * wl.theta_max_deg
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    return {"pixels": int(npix), "rel_l2": rel(Ig, Io), "rel_l2_ring": rel(Ig[ring], Io[ring]),
+            "max_pixel_rel": float(np.max(np.abs(Ig - Io) / Io))}
+
+
 def cpu_baseline(wl, target_s):
     """Time the FP64 oracle on a seeded pixel sample of the same pattern."""
     import numpy as np
@@ -148,6 +172,8 @@ def main():
                     help="time one precision only (profiling runs)")
     ap.add_argument("--serving", type=int, default=64,
                     help="requests of the mixed-size serving stream (0 = skip)")
+    ap.add_argument("--large", action="store_true",
+                    help="also time the 256^3 / 1024^2 pattern (l <= 10 body with voids, 80 deg)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 256 MiB device-to-device copy, the reference for "
                          "scaling hardware byte counters")
@@ -192,7 +218,8 @@ def main():
                    "contract_ms": cms, "scan_ms": sms, "wall_s": r["wall_s"],
                    "terms_per_s": P * V / (ms * 1e-3),
                    "contract_tflops": flops / (cms * 1e-3) / 1e12,
-                   "resident_bytes": plan.resident_bytes, "workspace_bytes": plan.workspace_bytes}
+                   "resident_bytes": plan.resident_bytes, "workspace_bytes": plan.workspace_bytes,
+                   "error_vs_fp64_oracle": oracle_error(wl, r["intensity"])}
             print(f"[bench] {prec}: {ms:.3f} ms/pattern (contract {cms:.3f} ms, scan {sms:.4f} ms), "
                   f"{res['contract_tflops']:.1f} TFLOP/s algorithmic", file=sys.stderr, flush=True)
             if args.batch > 1 and not args.only:
@@ -248,6 +275,23 @@ def main():
         r = results["bf16x3"]
         r["roofline_frac_bf16_peak_algorithmic"] = r["contract_tflops"] / PEAK_TFLOPS["bf16x3"]
         r["roofline_frac_bf16_peak_executed"] = 3 * r["contract_tflops"] / PEAK_TFLOPS["bf16x3"]
+    if args.large and not args.only:
+        lw = inputs.large_workload()
+        lP, lV = lw.det_n ** 2, int(np.prod(lw.grid))
+        ld, lb = torch.from_numpy(lw.delta).cuda(), torch.from_numpy(lw.beta).cuda()
+        line["large"] = {"workload": lw.name, "grid": list(lw.grid), "detector": [lw.det_n] * 2,
+                         "terms": lP * lV}
+        for prec in ("fp32", "bf16x3"):
+            with msft.Plan.for_workload(lw, prec) as plan:
+                r = time_single(msft, torch, plan, ld, lb, 3, 1)
+            ms = sum(r["step_ms"]) / len(r["step_ms"])
+            cms = sum(r["contract_ms"]) / len(r["contract_ms"])
+            line["large"][prec] = {"ms_per_pattern": ms, "patterns_per_s": 1000.0 / ms,
+                                   "contract_tflops": 8.0 * lP * lV / (cms * 1e-3) / 1e12}
+            print(f"[bench] large {prec}: {ms:.1f} ms/pattern, "
+                  f"{line['large'][prec]['contract_tflops']:.1f} TFLOP/s algorithmic",
+                  file=sys.stderr, flush=True)
+        del ld, lb
     if args.serving > 0 and not args.only:
         from paper_2202_03411_amd import serving
         sv = serving.benchmark(args.serving, "fp32", load=0.8)

@@ -166,61 +166,106 @@ int launch_twiddles(int precision, const Dims& d, const double* q_dev, const dou
 // ---------------------------------------------------------------------------
 // Column scan (Eq. (8)) and effective strength (Eqs. (6), (9)).
 //
-// Workgroup (xc, y) of 4 waves produces the nzb W tiles of its 64 columns.  For
-// each block of 32 slices a wave takes two columns at a time, one per 32-lane
-// half, lanes along z: coalesced loads, an exclusive wavefront prefix sum of
-// (beta, delta) with a carry from the previous block, then
+// Workgroup (xc, y) owns the 64 columns x = xc*64 + lane at one y; wave k owns
+// z block k (32 slices), looping by SCAN_WAVES when there are more blocks.
+// Phase 1: each lane reads its column's 32 slices (two 128-byte runs, delta and
+// beta) and sums them; the block totals go through LDS and every lane forms the
+// exclusive prefix of the blocks before its own (the carry).  Phase 2: the lane
+// walks its slices in beam order, keeping the running exclusive sum
+// S = sum_{s'<s} (beta + i delta), and writes
 //   T = exp(-k0 dz (S_beta + i S_delta)),   w = dV chi T,
 //   chi = n^2 - 1 = delta (delta - 2) - beta^2 + 2 i beta (1 - delta)
-// (chi written without the cancelling "+1 -1").  The tile is staged in LDS in
-// its swizzled layout and stored with 16-byte writes.
+// (chi written without the cancelling "+1 -1") straight into the tile rows:
+// the 64 lanes of a row are 64 consecutive x, so each row store is one
+// contiguous 256-byte (FP32) or 2 x 128-byte (BF16 hi, lo) segment.
 // ---------------------------------------------------------------------------
+constexpr int SCAN_WAVES = 8;
+
 template <int PREC>
-__global__ __launch_bounds__(256) void scan_kernel(ScanArgs a)
+__device__ __forceinline__ void store_w(uint8_t* tile, int lane, int zl, float wr, float wi)
 {
-    __shared__ __attribute__((aligned(16))) uint8_t stage[TILE_BYTES];
+    if (PREC == MSFT_FP32) {
+        const int sub = (lane & 3) * 4;
+        *(float*)(tile + tile_slot_offset(0, zl, lane >> 2) + sub) = wr;
+        *(float*)(tile + tile_slot_offset(1, zl, lane >> 2) + sub) = wi;
+    } else {
+        const int sub = (lane & 7) * 2;
+        const __bf16 rh = (__bf16)wr, ih = (__bf16)wi;
+        const __bf16 rl = (__bf16)(wr - (float)rh), il = (__bf16)(wi - (float)ih);
+        *(__bf16*)(tile + tile_slot_offset(0, zl, lane >> 3) + sub) = rh;
+        *(__bf16*)(tile + tile_slot_offset(0, zl, 8 + (lane >> 3)) + sub) = rl;
+        *(__bf16*)(tile + tile_slot_offset(1, zl, lane >> 3) + sub) = ih;
+        *(__bf16*)(tile + tile_slot_offset(1, zl, 8 + (lane >> 3)) + sub) = il;
+    }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(64 * SCAN_WAVES) void scan_kernel(ScanArgs a)
+{
+    __shared__ float tot_b[SCAN_WAVES][64], tot_d[SCAN_WAVES][64];
     const int xc = blockIdx.x, y = blockIdx.y;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int half = lane >> 5, zl = lane & 31;
-    float carry_b[8], carry_d[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) carry_b[k] = carry_d[k] = 0.0f;
+    const int x = xc * XC + lane;
+    const bool xin = x < a.nx;
+    const size_t col = ((size_t)x * a.ny + y) * a.nz;
+    float carry_b = 0.0f, carry_d = 0.0f;   // sum over all earlier rounds
 
-    for (int zb = 0; zb < a.nzb; ++zb) {
-        const int z = zb * ZB + zl;
+    for (int zb0 = 0; zb0 < a.nzb; zb0 += SCAN_WAVES) {
+        const int zb = zb0 + wave;
+        const bool active = zb < a.nzb;
+        const int z0 = zb * ZB;
+        const int nzl = active ? min(ZB, a.nz - z0) : 0;   // slices of this block inside the grid
+        float d[ZB], b[ZB];
+        if (xin && nzl == ZB && (a.nz & 3) == 0) {
 #pragma unroll
-        for (int pr = 0; pr < 8; ++pr) {
-            const int xl = wave * 16 + pr * 2 + half;
-            const int x = xc * XC + xl;
-            float d = 0.0f, b = 0.0f;
-            if (x < a.nx && z < a.nz) {
-                const size_t v = ((size_t)x * a.ny + y) * a.nz + z;
-                d = a.delta[v];
-                b = a.beta[v];
+            for (int k = 0; k < ZB / 4; ++k) {
+                const float4 dv = ((const float4*)(a.delta + col + z0))[k];
+                const float4 bv = ((const float4*)(a.beta + col + z0))[k];
+                d[4 * k] = dv.x; d[4 * k + 1] = dv.y; d[4 * k + 2] = dv.z; d[4 * k + 3] = dv.w;
+                b[4 * k] = bv.x; b[4 * k + 1] = bv.y; b[4 * k + 2] = bv.z; b[4 * k + 3] = bv.w;
             }
-            // exclusive prefix over the 32 lanes of this half: scan the values
-            // shifted down by one lane
-            float sb = __shfl_up(b, 1, 32), sd = __shfl_up(d, 1, 32);
-            if (zl == 0) sb = sd = 0.0f;
+        } else {
 #pragma unroll
-            for (int off = 1; off < 32; off <<= 1) {
-                const float tb = __shfl_up(sb, off, 32), td = __shfl_up(sd, off, 32);
-                if (zl >= off) {
-                    sb += tb;
-                    sd += td;
-                }
+            for (int k = 0; k < ZB; ++k) {
+                const bool in = xin && k < nzl;
+                d[k] = in ? a.delta[col + z0 + k] : 0.0f;
+                b[k] = in ? a.beta[col + z0 + k] : 0.0f;
             }
-            const float Sb = carry_b[pr] + sb, Sd = carry_d[pr] + sd;
-            carry_b[pr] += __shfl(sb + b, 31, 32);
-            carry_d[pr] += __shfl(sd + d, 31, 32);
+        }
+        float sb = 0.0f, sd = 0.0f;
+#pragma unroll
+        for (int k = 0; k < ZB; ++k) {
+            sb += b[k];
+            sd += d[k];
+        }
+        tot_b[wave][lane] = sb;
+        tot_d[wave][lane] = sd;
+        __syncthreads();
+        float Sb = carry_b, Sd = carry_d;
+        for (int k = 0; k < wave; ++k) {
+            Sb += tot_b[k][lane];
+            Sd += tot_d[k][lane];
+        }
+        float rb = 0.0f, rd = 0.0f;
+        for (int k = 0; k < SCAN_WAVES && zb0 + k < a.nzb; ++k) {
+            rb += tot_b[k][lane];
+            rd += tot_d[k][lane];
+        }
+        __syncthreads();
+        carry_b += rb;
+        carry_d += rd;
+        if (!active) continue;
 
+        uint8_t* tile = a.wtiles + ((size_t)(xc * a.nzb + zb) * a.ny + y) * TILE_BYTES;
+#pragma unroll
+        for (int k = 0; k < ZB; ++k) {
             float wr, wi;
             if (a.strength == MSFT_STRENGTH_DENSITY) {
-                wr = a.dV * d;
-                wi = a.dV * b;
+                wr = a.dV * d[k];
+                wi = a.dV * b[k];
             } else {
-                const float chr = d * (d - 2.0f) - b * b;
-                const float chi = 2.0f * b * (1.0f - d);
+                const float chr = d[k] * (d[k] - 2.0f) - b[k] * b[k];
+                const float chi = 2.0f * b[k] * (1.0f - d[k]);
                 float tr = 1.0f, ti = 0.0f;
                 if (a.strength == MSFT_STRENGTH_MSFT) {
                     const float mag = expf(-a.k0dz * Sb);
@@ -232,26 +277,10 @@ __global__ __launch_bounds__(256) void scan_kernel(ScanArgs a)
                 wr = a.dV * (chr * tr - chi * ti);
                 wi = a.dV * (chr * ti + chi * tr);
             }
-            if (PREC == MSFT_FP32) {
-                const int sub = (xl & 3) * 4;
-                *(float*)(stage + tile_slot_offset(0, zl, xl >> 2) + sub) = wr;
-                *(float*)(stage + tile_slot_offset(1, zl, xl >> 2) + sub) = wi;
-            } else {
-                const int sub = (xl & 7) * 2;
-                const __bf16 rh = (__bf16)wr, ih = (__bf16)wi;
-                const __bf16 rl = (__bf16)(wr - (float)rh), il = (__bf16)(wi - (float)ih);
-                *(__bf16*)(stage + tile_slot_offset(0, zl, xl >> 3) + sub) = rh;
-                *(__bf16*)(stage + tile_slot_offset(0, zl, 8 + (xl >> 3)) + sub) = rl;
-                *(__bf16*)(stage + tile_slot_offset(1, zl, xl >> 3) + sub) = ih;
-                *(__bf16*)(stage + tile_slot_offset(1, zl, 8 + (xl >> 3)) + sub) = il;
-            }
+            store_w<PREC>(tile, lane, k, wr, wi);
+            Sb += b[k];
+            Sd += d[k];
         }
-        __syncthreads();
-        uint4* dst = (uint4*)(a.wtiles + ((size_t)(xc * a.nzb + zb) * a.ny + y) * TILE_BYTES);
-        const uint4* src = (const uint4*)stage;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) dst[threadIdx.x + 256 * k] = src[threadIdx.x + 256 * k];
-        __syncthreads();
     }
 }
 
@@ -259,10 +288,11 @@ int launch_scan(int precision, const ScanArgs& a, void* stream)
 {
     hipStream_t s = (hipStream_t)stream;
     dim3 grid(a.nxc, a.ny);
+    const int waves = a.nzb < SCAN_WAVES ? a.nzb : SCAN_WAVES;
     if (precision == MSFT_FP32)
-        hipLaunchKernelGGL(scan_kernel<MSFT_FP32>, grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL(scan_kernel<MSFT_FP32>, grid, dim3(64 * waves), 0, s, a);
     else
-        hipLaunchKernelGGL(scan_kernel<MSFT_BF16X3>, grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL(scan_kernel<MSFT_BF16X3>, grid, dim3(64 * waves), 0, s, a);
     return (int)hipGetLastError();
 }
 
@@ -279,43 +309,90 @@ int launch_scan(int precision, const ScanArgs& a, void* stream)
 // W tiles stream through a double-buffered LDS ring shared by the 8 waves.  The
 // order of every sum depends only on the plan, never on the launch.
 // ---------------------------------------------------------------------------
-// C = A . B for one W tile: the wave's A operand (registers) times the tile's
-// column `col` of lane half h (LDS row `row`), over the first `nx` x values.
-// FP32: 4 x values per 16-byte LDS slot, one v_mfma_f32_32x32x2_f32 per x.
-// BF16X3: 8 x values per slot, hi*hi + hi*lo + lo*hi on v_mfma_f32_32x32x16_bf16.
-template <int PREC, int NX>
+// G[m] += Ty[m] * C[m] for lane slot m (pixel 4(m/2) + 2h + m%2 of the wave):
+// accumulator rows 4j + 2u (re) and 4j + 2u + 1 (im), m = 2j + u.
+__device__ __forceinline__ void slot_update(float* G, const f32x16& C, const float* ty, int m)
+{
+    const int r = 4 * (m >> 1) + 2 * (m & 1);
+    const float cr = C[r], ci = C[r + 1];
+    const float tr = ty[2 * m], ti = ty[2 * m + 1];
+    G[2 * m] = __builtin_fmaf(-ti, ci, __builtin_fmaf(tr, cr, G[2 * m]));
+    G[2 * m + 1] = __builtin_fmaf(ti, cr, __builtin_fmaf(tr, ci, G[2 * m + 1]));
+}
+
+// C = A . B for one full W tile: the wave's A operand (registers) times column
+// `col` of lane half h (LDS row `row`).  FP32: 4 x values per 16-byte LDS slot,
+// one v_mfma_f32_32x32x2_f32 per x.  BF16X3: 8 x values per slot, hi*hi + hi*lo
+// + lo*hi on v_mfma_f32_32x32x16_bf16.  LDS operands are read one step ahead,
+// and the previous tile's y-update (Cp, tyP -> G) is spread slot by slot
+// between the matrix instructions so that the VALU work hides under them
+// (before the first tile Cp is zero and the update adds nothing).
+template <int PREC>
 __device__ __forceinline__ f32x16 tile_mfma(const uint8_t* row, int col, const f32x4* Af,
-                                            const bf16x8* Ahi, const bf16x8* Alo)
+                                            const bf16x8* Ahi, const bf16x8* Alo,
+                                            const f32x16& Cp, const float* tyP, float* G)
 {
     f32x16 C = {};
     const int sw = col & 15;
     if (PREC == MSFT_FP32) {
+        f32x4 bn = *(const f32x4*)(row + ((0 ^ sw) << 4));
 #pragma unroll
-        for (int g = 0; g < NX / 4; ++g) {
-            const f32x4 b = *(const f32x4*)(row + ((g ^ sw) << 4));
+        for (int g = 0; g < XC / 4; ++g) {
+            const f32x4 b = bn;
+            if (g + 1 < XC / 4) bn = *(const f32x4*)(row + (((g + 1) ^ sw) << 4));
             C = __builtin_amdgcn_mfma_f32_32x32x2f32(Af[g][0], b[0], C, 0, 0, 0);
             C = __builtin_amdgcn_mfma_f32_32x32x2f32(Af[g][1], b[1], C, 0, 0, 0);
             C = __builtin_amdgcn_mfma_f32_32x32x2f32(Af[g][2], b[2], C, 0, 0, 0);
             C = __builtin_amdgcn_mfma_f32_32x32x2f32(Af[g][3], b[3], C, 0, 0, 0);
+            if (g & 1) slot_update(G, Cp, tyP, g >> 1);
+        }
+        // order: per x group one LDS read, then the 4 matrix instructions with
+        // the slot update (4 VALU) of every second group between them
+#pragma unroll
+        for (int g = 0; g < XC / 4; ++g) {
+            if (g + 1 < XC / 4) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+            if (g & 1) __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+            if (g & 1) __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
         }
     } else {
+        bf16x8 bhn = *(const bf16x8*)(row + ((0 ^ sw) << 4));
+        bf16x8 bln = *(const bf16x8*)(row + ((8 ^ sw) << 4));
 #pragma unroll
-        for (int s = 0; s < NX / 8; ++s) {
-            const bf16x8 bh = *(const bf16x8*)(row + ((s ^ sw) << 4));
-            const bf16x8 bl = *(const bf16x8*)(row + (((8 + s) ^ sw) << 4));
+        for (int s = 0; s < XC / 8; ++s) {
+            const bf16x8 bh = bhn, bl = bln;
+            if (s + 1 < XC / 8) {
+                bhn = *(const bf16x8*)(row + (((s + 1) ^ sw) << 4));
+                bln = *(const bf16x8*)(row + (((9 + s) ^ sw) << 4));
+            }
             C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ahi[s], bh, C, 0, 0, 0);
             C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ahi[s], bl, C, 0, 0, 0);
             C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Alo[s], bh, C, 0, 0, 0);
+            slot_update(G, Cp, tyP, s);
+        }
+        // order: per step the two LDS reads of the next step, then the three
+        // matrix instructions with the slot update (4 VALU) between them
+#pragma unroll
+        for (int s = 0; s < XC / 8; ++s) {
+            if (s + 1 < XC / 8) __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
         }
     }
     return C;
 }
 
-// The last, partial x chunk: the same products in steps of 8 x values.
+// The last, partial x chunk: the same products in steps of 8 x values, then the
+// previous tile's y-update.
 template <int PREC>
 __device__ __forceinline__ f32x16 tile_mfma_partial(const uint8_t* row, int col, int nx,
-                                                 const f32x4* Af, const bf16x8* Ahi,
-                                                 const bf16x8* Alo)
+                                                    const f32x4* Af, const bf16x8* Ahi,
+                                                    const bf16x8* Alo, const f32x16& Cp,
+                                                    const float* tyP, float* G)
 {
     f32x16 C = {};
     const int sw = col & 15;
@@ -341,9 +418,51 @@ __device__ __forceinline__ f32x16 tile_mfma_partial(const uint8_t* row, int col,
             }
         }
     }
+#pragma unroll
+    for (int m = 0; m < 8; ++m) slot_update(G, Cp, tyP, m);
     return C;
 }
 
+// acc[m] += Tz[m] * G[m] for the z block just finished, then G = 0.
+__device__ __forceinline__ void close_zblock(float* acc, float* G, const float* tz, int64_t wt,
+                                             int nzb, int zb, int h, int col)
+{
+    const f32x4* tzp = (const f32x4*)(tz + 2 * ((((wt * nzb + zb) * 2 + h) * ZB + col) * 8));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const f32x4 v = tzp[k];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int m = 2 * k + u;
+            const float tr = v[2 * u], ti = v[2 * u + 1];
+            acc[2 * m] += tr * G[2 * m] - ti * G[2 * m + 1];
+            acc[2 * m + 1] += tr * G[2 * m + 1] + ti * G[2 * m];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) G[k] = 0.0f;
+}
+
+template <int PREC>
+__device__ __forceinline__ void load_a(const FwdArgs& a, int64_t wt, int xc, int lane, f32x4* Af,
+                                       bf16x8* Ahi, bf16x8* Alo)
+{
+    const uint8_t* ta = a.txa + (size_t)(wt * a.nxc + xc) * TILE_BYTES;
+    if (PREC == MSFT_FP32) {
+#pragma unroll
+        for (int g = 0; g < 16; ++g) Af[g] = ((const f32x4*)ta)[g * 64 + lane];
+    } else {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            Ahi[s] = ((const bf16x8*)ta)[s * 128 + lane];
+            Alo[s] = ((const bf16x8*)ta)[s * 128 + 64 + lane];
+        }
+    }
+}
+
+// Tiles are visited in storage order t = (xc * nzb + zb) * ny + y.  Tile t's
+// matrix products run while the previous tile's y-update is folded into G, so
+// each wave carries one finished-but-unreduced tile (Cp, tyP) across the loop.
 template <int PREC>
 __device__ __forceinline__ void fwd_block(const FwdArgs& a, int64_t block, uint8_t* lds)
 {
@@ -362,77 +481,64 @@ __device__ __forceinline__ void fwd_block(const FwdArgs& a, int64_t block, uint8
     }
     __syncthreads();
 
-    float acc[16];
+    float acc[16], G[16], tyP[16];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) acc[k] = 0.0f;
+    for (int k = 0; k < 16; ++k) acc[k] = G[k] = tyP[k] = 0.0f;
+    f32x16 Cp = {};
+    bool prev_closes = false;
+    int prev_zb = 0;
 
-    int64_t t = 0;
-    for (int xc = 0; xc < a.nxc; ++xc) {
-        const int xlen = min(XC, a.x_pad - xc * XC);
-        // A operand of this wave for the chunk
-        f32x4 Af[16];
-        bf16x8 Ahi[8], Alo[8];
-        const uint8_t* ta = a.txa + (size_t)(wt * a.nxc + xc) * TILE_BYTES;
-        if (PREC == MSFT_FP32) {
-#pragma unroll
-            for (int g = 0; g < 16; ++g) Af[g] = ((const f32x4*)ta)[g * 64 + lane];
-        } else {
-#pragma unroll
-            for (int s = 0; s < 8; ++s) {
-                Ahi[s] = ((const bf16x8*)ta)[s * 128 + lane];
-                Alo[s] = ((const bf16x8*)ta)[s * 128 + 64 + lane];
-            }
+    f32x4 Af[16];
+    bf16x8 Ahi[8], Alo[8];
+    int xc = 0, zb = 0, y = 0;
+    int xlen = min(XC, a.x_pad);
+    load_a<PREC>(a, wt, 0, lane, Af, Ahi, Alo);
+
+    for (int64_t t = 0; t < ntiles; ++t) {
+        const bool has_next = (t + 1) < ntiles;
+        uint4 n0, n1;
+        if (has_next) {
+            n0 = gw[(t + 1) * (TILE_BYTES / 16) + tid];
+            n1 = gw[(t + 1) * (TILE_BYTES / 16) + 512 + tid];
         }
-        for (int zb = 0; zb < a.nzb; ++zb) {
-            float G[16];
-#pragma unroll
-            for (int k = 0; k < 16; ++k) G[k] = 0.0f;
-            for (int y = 0; y < a.ny; ++y, ++t) {
-                const bool has_next = (t + 1) < ntiles;
-                uint4 n0, n1;
-                if (has_next) {
-                    n0 = gw[(t + 1) * (TILE_BYTES / 16) + tid];
-                    n1 = gw[(t + 1) * (TILE_BYTES / 16) + 512 + tid];
-                }
-                const f32x4* typ = (const f32x4*)(a.ty + 2 * ((wt * a.ny + y) * WAVE_PIX + h * 8));
-                const f32x4 ty0 = typ[0], ty1 = typ[1], ty2 = typ[2], ty3 = typ[3];
+        const f32x4* typ = (const f32x4*)(a.ty + 2 * ((wt * a.ny + y) * WAVE_PIX + h * 8));
+        const f32x4 ty0 = typ[0], ty1 = typ[1], ty2 = typ[2], ty3 = typ[3];
 
-                const uint8_t* row = lds + (t & 1) * TILE_BYTES + (h * ZB + col) * ROW_BYTES;
-                const f32x16 C = (xlen == XC) ? tile_mfma<PREC, XC>(row, col, Af, Ahi, Alo)
-                                              : tile_mfma_partial<PREC>(row, col, xlen, Af, Ahi, Alo);
-                // G[m] += Ty[m] * C[m], slot m = 2j + u: C rows 4j + 2u (re), 4j + 2u + 1 (im)
-                const float tyv[16] = {ty0[0], ty0[1], ty0[2], ty0[3], ty1[0], ty1[1], ty1[2], ty1[3],
-                                       ty2[0], ty2[1], ty2[2], ty2[3], ty3[0], ty3[1], ty3[2], ty3[3]};
-#pragma unroll
-                for (int m = 0; m < 8; ++m) {
-                    const int r = 4 * (m >> 1) + 2 * (m & 1);
-                    const float cr = C[r], ci = C[r + 1];
-                    const float tr = tyv[2 * m], ti = tyv[2 * m + 1];
-                    G[2 * m] += tr * cr - ti * ci;
-                    G[2 * m + 1] += tr * ci + ti * cr;
-                }
-                if (has_next) {
-                    uint4* nb = (uint4*)(lds + ((t + 1) & 1) * TILE_BYTES);
-                    nb[tid] = n0;
-                    nb[tid + 512] = n1;
-                }
-                __syncthreads();
-            }
-            // acc[m] += Tz[m] * G[m]
-            const f32x4* tzp = (const f32x4*)(a.tz + 2 * ((((wt * a.nzb + zb) * 2 + h) * ZB + col) * 8));
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const f32x4 v = tzp[k];
-#pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    const int m = 2 * k + u;
-                    const float tr = v[2 * u], ti = v[2 * u + 1];
-                    acc[2 * m] += tr * G[2 * m] - ti * G[2 * m + 1];
-                    acc[2 * m + 1] += tr * G[2 * m + 1] + ti * G[2 * m];
+        const uint8_t* row = lds + (t & 1) * TILE_BYTES + (h * ZB + col) * ROW_BYTES;
+        const f32x16 C = (xlen == XC)
+                             ? tile_mfma<PREC>(row, col, Af, Ahi, Alo, Cp, tyP, G)
+                             : tile_mfma_partial<PREC>(row, col, xlen, Af, Ahi, Alo, Cp, tyP, G);
+        if (prev_closes) close_zblock(acc, G, a.tz, wt, a.nzb, prev_zb, h, col);
+
+        if (has_next) {
+            uint4* nb = (uint4*)(lds + ((t + 1) & 1) * TILE_BYTES);
+            nb[tid] = n0;
+            nb[tid + 512] = n1;
+        }
+        Cp = C;
+        tyP[0] = ty0[0]; tyP[1] = ty0[1]; tyP[2] = ty0[2]; tyP[3] = ty0[3];
+        tyP[4] = ty1[0]; tyP[5] = ty1[1]; tyP[6] = ty1[2]; tyP[7] = ty1[3];
+        tyP[8] = ty2[0]; tyP[9] = ty2[1]; tyP[10] = ty2[2]; tyP[11] = ty2[3];
+        tyP[12] = ty3[0]; tyP[13] = ty3[1]; tyP[14] = ty3[2]; tyP[15] = ty3[3];
+        prev_closes = (y == a.ny - 1);
+        prev_zb = zb;
+        if (++y == a.ny) {
+            y = 0;
+            if (++zb == a.nzb) {
+                zb = 0;
+                ++xc;
+                if (xc < a.nxc) {
+                    xlen = min(XC, a.x_pad - xc * XC);
+                    load_a<PREC>(a, wt, xc, lane, Af, Ahi, Alo);
                 }
             }
         }
+        __syncthreads();
     }
+    // the last tile's y-update and its z block
+#pragma unroll
+    for (int m = 0; m < 8; ++m) slot_update(G, Cp, tyP, m);
+    close_zblock(acc, G, a.tz, wt, a.nzb, prev_zb, h, col);
 
     // sum over the 32 z lanes of each half (fixed butterfly order)
 #pragma unroll

@@ -123,12 +123,48 @@ def sh_coefficients(rng: np.random.Generator, lmin: int, lmax: int, sigma: float
 
 
 def sh_radius(coeffs, r0: float, theta, phi):
-    """r(theta, phi) = r0 (1 + sum c_lm Y_lm)."""
-    lmax = max(l for l, _, _ in coeffs) if coeffs else 0
-    Y = real_sh(lmax, theta, phi)
-    acc = np.zeros_like(np.asarray(theta, dtype=np.float64))
+    """r(theta, phi) = r0 (1 + sum c_lm Y_lm), the same harmonics as real_sh.
+
+    Evaluated order by order with the same normalized recurrences, keeping only
+    two degrees of the Legendre table at a time, so large grids fit in memory.
+    """
+    theta = np.asarray(theta, dtype=np.float64)
+    phi = np.asarray(phi, dtype=np.float64)
+    cmap = {}
     for l, m, c in coeffs:
-        acc = acc + c * Y[(l, m)]
+        cmap[(l, m)] = cmap.get((l, m), 0.0) + c
+    lmax = max((l for l, _ in cmap), default=0)
+    x = np.cos(theta)
+    s = np.sin(theta)
+    acc = np.zeros_like(theta)
+    qmm = np.full_like(theta, 1.0 / math.sqrt(4.0 * math.pi))
+    for m in range(0, lmax + 1):
+        if m > 0:
+            qmm = math.sqrt((2.0 * m + 1.0) / (2.0 * m)) * s * qmm
+        cos_m = np.cos(m * phi) if m > 0 else None
+        sin_m = np.sin(m * phi) if m > 0 else None
+        q_lm2, q_lm1 = None, qmm
+        for l in range(m, lmax + 1):
+            if l == m:
+                q = qmm
+            elif l == m + 1:
+                q = math.sqrt(2.0 * m + 3.0) * x * qmm
+            else:
+                a = math.sqrt((4.0 * l * l - 1.0) / (l * l - m * m))
+                b = math.sqrt(((l - 1.0) ** 2 - m * m) / (4.0 * (l - 1.0) ** 2 - 1.0))
+                q = a * (x * q_lm1 - b * q_lm2)
+            if l > m:
+                q_lm2, q_lm1 = q_lm1, q
+            if m == 0:
+                c = cmap.get((l, 0), 0.0)
+                if c:
+                    acc += c * q
+            else:
+                cp, cn = cmap.get((l, m), 0.0), cmap.get((l, -m), 0.0)
+                if cp:
+                    acc += (cp * math.sqrt(2.0)) * q * cos_m
+                if cn:
+                    acc += (cn * math.sqrt(2.0)) * q * sin_m
     return r0 * (1.0 + acc)
 
 

@@ -189,3 +189,20 @@ def test_repeatable(msft):
         I2 = p.simulate(d, b)
         torch.cuda.synchronize()
         assert torch.equal(I1, I2)
+
+
+@pytest.fixture(scope="module")
+def large_wl():
+    # l <= 10 harmonic body with three voids, 256^3, 1024^2 detector to 80 deg at 13.5 nm
+    return inputs.large_workload()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_parity_large_sampled(msft, large_wl, precision):
+    wl = large_wl
+    pix = inputs.random_pixels(wl.det_n, 384, seed=78)
+    I, A = _run(msft, wl, precision, pixels=pix)
+    Io, Ao = _oracle(wl, pixels=pix)
+    err = _rel(I, Io)
+    print(f"  large pattern rel L2 {err:.3e}  amplitude {_rel(A, Ao):.3e}")
+    assert err <= TOL[precision]
