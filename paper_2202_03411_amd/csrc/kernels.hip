@@ -309,90 +309,43 @@ int launch_scan(int precision, const ScanArgs& a, void* stream)
 // W tiles stream through a double-buffered LDS ring shared by the 8 waves.  The
 // order of every sum depends only on the plan, never on the launch.
 // ---------------------------------------------------------------------------
-// G[m] += Ty[m] * C[m] for lane slot m (pixel 4(m/2) + 2h + m%2 of the wave):
-// accumulator rows 4j + 2u (re) and 4j + 2u + 1 (im), m = 2j + u.
-__device__ __forceinline__ void slot_update(float* G, const f32x16& C, const float* ty, int m)
-{
-    const int r = 4 * (m >> 1) + 2 * (m & 1);
-    const float cr = C[r], ci = C[r + 1];
-    const float tr = ty[2 * m], ti = ty[2 * m + 1];
-    G[2 * m] = __builtin_fmaf(-ti, ci, __builtin_fmaf(tr, cr, G[2 * m]));
-    G[2 * m + 1] = __builtin_fmaf(ti, cr, __builtin_fmaf(tr, ci, G[2 * m + 1]));
-}
-
-// C = A . B for one full W tile: the wave's A operand (registers) times column
-// `col` of lane half h (LDS row `row`).  FP32: 4 x values per 16-byte LDS slot,
-// one v_mfma_f32_32x32x2_f32 per x.  BF16X3: 8 x values per slot, hi*hi + hi*lo
-// + lo*hi on v_mfma_f32_32x32x16_bf16.  LDS operands are read one step ahead,
-// and the previous tile's y-update (Cp, tyP -> G) is spread slot by slot
-// between the matrix instructions so that the VALU work hides under them
-// (before the first tile Cp is zero and the update adds nothing).
-template <int PREC>
+// C = A . B for one W tile: the wave's A operand (registers) times the tile's
+// column `col` of lane half h (LDS row `row`), over the first `nx` x values.
+// FP32: 4 x values per 16-byte LDS slot, one v_mfma_f32_32x32x2_f32 per x.
+// BF16X3: 8 x values per slot, hi*hi + hi*lo + lo*hi on v_mfma_f32_32x32x16_bf16.
+template <int PREC, int NX>
 __device__ __forceinline__ f32x16 tile_mfma(const uint8_t* row, int col, const f32x4* Af,
-                                            const bf16x8* Ahi, const bf16x8* Alo,
-                                            const f32x16& Cp, const float* tyP, float* G)
+                                            const bf16x8* Ahi, const bf16x8* Alo)
 {
     f32x16 C = {};
     const int sw = col & 15;
     if (PREC == MSFT_FP32) {
-        f32x4 bn = *(const f32x4*)(row + ((0 ^ sw) << 4));
 #pragma unroll
-        for (int g = 0; g < XC / 4; ++g) {
-            const f32x4 b = bn;
-            if (g + 1 < XC / 4) bn = *(const f32x4*)(row + (((g + 1) ^ sw) << 4));
+        for (int g = 0; g < NX / 4; ++g) {
+            const f32x4 b = *(const f32x4*)(row + ((g ^ sw) << 4));
             C = __builtin_amdgcn_mfma_f32_32x32x2f32(Af[g][0], b[0], C, 0, 0, 0);
             C = __builtin_amdgcn_mfma_f32_32x32x2f32(Af[g][1], b[1], C, 0, 0, 0);
             C = __builtin_amdgcn_mfma_f32_32x32x2f32(Af[g][2], b[2], C, 0, 0, 0);
             C = __builtin_amdgcn_mfma_f32_32x32x2f32(Af[g][3], b[3], C, 0, 0, 0);
-            if (g & 1) slot_update(G, Cp, tyP, g >> 1);
-        }
-        // order: per x group one LDS read, then the 4 matrix instructions with
-        // the slot update (4 VALU) of every second group between them
-#pragma unroll
-        for (int g = 0; g < XC / 4; ++g) {
-            if (g + 1 < XC / 4) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
-            if (g & 1) __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
-            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
-            if (g & 1) __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
         }
     } else {
-        bf16x8 bhn = *(const bf16x8*)(row + ((0 ^ sw) << 4));
-        bf16x8 bln = *(const bf16x8*)(row + ((8 ^ sw) << 4));
 #pragma unroll
-        for (int s = 0; s < XC / 8; ++s) {
-            const bf16x8 bh = bhn, bl = bln;
-            if (s + 1 < XC / 8) {
-                bhn = *(const bf16x8*)(row + (((s + 1) ^ sw) << 4));
-                bln = *(const bf16x8*)(row + (((9 + s) ^ sw) << 4));
-            }
+        for (int s = 0; s < NX / 8; ++s) {
+            const bf16x8 bh = *(const bf16x8*)(row + ((s ^ sw) << 4));
+            const bf16x8 bl = *(const bf16x8*)(row + (((8 + s) ^ sw) << 4));
             C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ahi[s], bh, C, 0, 0, 0);
             C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ahi[s], bl, C, 0, 0, 0);
             C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Alo[s], bh, C, 0, 0, 0);
-            slot_update(G, Cp, tyP, s);
-        }
-        // order: per step the two LDS reads of the next step, then the three
-        // matrix instructions with the slot update (4 VALU) between them
-#pragma unroll
-        for (int s = 0; s < XC / 8; ++s) {
-            if (s + 1 < XC / 8) __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
         }
     }
     return C;
 }
 
-// The last, partial x chunk: the same products in steps of 8 x values, then the
-// previous tile's y-update.
+// The last, partial x chunk: the same products in steps of 8 x values.
 template <int PREC>
 __device__ __forceinline__ f32x16 tile_mfma_partial(const uint8_t* row, int col, int nx,
-                                                    const f32x4* Af, const bf16x8* Ahi,
-                                                    const bf16x8* Alo, const f32x16& Cp,
-                                                    const float* tyP, float* G)
+                                                 const f32x4* Af, const bf16x8* Ahi,
+                                                 const bf16x8* Alo)
 {
     f32x16 C = {};
     const int sw = col & 15;
@@ -418,51 +371,9 @@ __device__ __forceinline__ f32x16 tile_mfma_partial(const uint8_t* row, int col,
             }
         }
     }
-#pragma unroll
-    for (int m = 0; m < 8; ++m) slot_update(G, Cp, tyP, m);
     return C;
 }
 
-// acc[m] += Tz[m] * G[m] for the z block just finished, then G = 0.
-__device__ __forceinline__ void close_zblock(float* acc, float* G, const float* tz, int64_t wt,
-                                             int nzb, int zb, int h, int col)
-{
-    const f32x4* tzp = (const f32x4*)(tz + 2 * ((((wt * nzb + zb) * 2 + h) * ZB + col) * 8));
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const f32x4 v = tzp[k];
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int m = 2 * k + u;
-            const float tr = v[2 * u], ti = v[2 * u + 1];
-            acc[2 * m] += tr * G[2 * m] - ti * G[2 * m + 1];
-            acc[2 * m + 1] += tr * G[2 * m + 1] + ti * G[2 * m];
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < 16; ++k) G[k] = 0.0f;
-}
-
-template <int PREC>
-__device__ __forceinline__ void load_a(const FwdArgs& a, int64_t wt, int xc, int lane, f32x4* Af,
-                                       bf16x8* Ahi, bf16x8* Alo)
-{
-    const uint8_t* ta = a.txa + (size_t)(wt * a.nxc + xc) * TILE_BYTES;
-    if (PREC == MSFT_FP32) {
-#pragma unroll
-        for (int g = 0; g < 16; ++g) Af[g] = ((const f32x4*)ta)[g * 64 + lane];
-    } else {
-#pragma unroll
-        for (int s = 0; s < 8; ++s) {
-            Ahi[s] = ((const bf16x8*)ta)[s * 128 + lane];
-            Alo[s] = ((const bf16x8*)ta)[s * 128 + 64 + lane];
-        }
-    }
-}
-
-// Tiles are visited in storage order t = (xc * nzb + zb) * ny + y.  Tile t's
-// matrix products run while the previous tile's y-update is folded into G, so
-// each wave carries one finished-but-unreduced tile (Cp, tyP) across the loop.
 template <int PREC>
 __device__ __forceinline__ void fwd_block(const FwdArgs& a, int64_t block, uint8_t* lds)
 {
@@ -481,64 +392,77 @@ __device__ __forceinline__ void fwd_block(const FwdArgs& a, int64_t block, uint8
     }
     __syncthreads();
 
-    float acc[16], G[16], tyP[16];
+    float acc[16];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) acc[k] = G[k] = tyP[k] = 0.0f;
-    f32x16 Cp = {};
-    bool prev_closes = false;
-    int prev_zb = 0;
+    for (int k = 0; k < 16; ++k) acc[k] = 0.0f;
 
-    f32x4 Af[16];
-    bf16x8 Ahi[8], Alo[8];
-    int xc = 0, zb = 0, y = 0;
-    int xlen = min(XC, a.x_pad);
-    load_a<PREC>(a, wt, 0, lane, Af, Ahi, Alo);
-
-    for (int64_t t = 0; t < ntiles; ++t) {
-        const bool has_next = (t + 1) < ntiles;
-        uint4 n0, n1;
-        if (has_next) {
-            n0 = gw[(t + 1) * (TILE_BYTES / 16) + tid];
-            n1 = gw[(t + 1) * (TILE_BYTES / 16) + 512 + tid];
+    int64_t t = 0;
+    for (int xc = 0; xc < a.nxc; ++xc) {
+        const int xlen = min(XC, a.x_pad - xc * XC);
+        // A operand of this wave for the chunk
+        f32x4 Af[16];
+        bf16x8 Ahi[8], Alo[8];
+        const uint8_t* ta = a.txa + (size_t)(wt * a.nxc + xc) * TILE_BYTES;
+        if (PREC == MSFT_FP32) {
+#pragma unroll
+            for (int g = 0; g < 16; ++g) Af[g] = ((const f32x4*)ta)[g * 64 + lane];
+        } else {
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                Ahi[s] = ((const bf16x8*)ta)[s * 128 + lane];
+                Alo[s] = ((const bf16x8*)ta)[s * 128 + 64 + lane];
+            }
         }
-        const f32x4* typ = (const f32x4*)(a.ty + 2 * ((wt * a.ny + y) * WAVE_PIX + h * 8));
-        const f32x4 ty0 = typ[0], ty1 = typ[1], ty2 = typ[2], ty3 = typ[3];
+        for (int zb = 0; zb < a.nzb; ++zb) {
+            float G[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) G[k] = 0.0f;
+            for (int y = 0; y < a.ny; ++y, ++t) {
+                const bool has_next = (t + 1) < ntiles;
+                uint4 n0, n1;
+                if (has_next) {
+                    n0 = gw[(t + 1) * (TILE_BYTES / 16) + tid];
+                    n1 = gw[(t + 1) * (TILE_BYTES / 16) + 512 + tid];
+                }
+                const f32x4* typ = (const f32x4*)(a.ty + 2 * ((wt * a.ny + y) * WAVE_PIX + h * 8));
+                const f32x4 ty0 = typ[0], ty1 = typ[1], ty2 = typ[2], ty3 = typ[3];
 
-        const uint8_t* row = lds + (t & 1) * TILE_BYTES + (h * ZB + col) * ROW_BYTES;
-        const f32x16 C = (xlen == XC)
-                             ? tile_mfma<PREC>(row, col, Af, Ahi, Alo, Cp, tyP, G)
-                             : tile_mfma_partial<PREC>(row, col, xlen, Af, Ahi, Alo, Cp, tyP, G);
-        if (prev_closes) close_zblock(acc, G, a.tz, wt, a.nzb, prev_zb, h, col);
-
-        if (has_next) {
-            uint4* nb = (uint4*)(lds + ((t + 1) & 1) * TILE_BYTES);
-            nb[tid] = n0;
-            nb[tid + 512] = n1;
-        }
-        Cp = C;
-        tyP[0] = ty0[0]; tyP[1] = ty0[1]; tyP[2] = ty0[2]; tyP[3] = ty0[3];
-        tyP[4] = ty1[0]; tyP[5] = ty1[1]; tyP[6] = ty1[2]; tyP[7] = ty1[3];
-        tyP[8] = ty2[0]; tyP[9] = ty2[1]; tyP[10] = ty2[2]; tyP[11] = ty2[3];
-        tyP[12] = ty3[0]; tyP[13] = ty3[1]; tyP[14] = ty3[2]; tyP[15] = ty3[3];
-        prev_closes = (y == a.ny - 1);
-        prev_zb = zb;
-        if (++y == a.ny) {
-            y = 0;
-            if (++zb == a.nzb) {
-                zb = 0;
-                ++xc;
-                if (xc < a.nxc) {
-                    xlen = min(XC, a.x_pad - xc * XC);
-                    load_a<PREC>(a, wt, xc, lane, Af, Ahi, Alo);
+                const uint8_t* row = lds + (t & 1) * TILE_BYTES + (h * ZB + col) * ROW_BYTES;
+                const f32x16 C = (xlen == XC) ? tile_mfma<PREC, XC>(row, col, Af, Ahi, Alo)
+                                              : tile_mfma_partial<PREC>(row, col, xlen, Af, Ahi, Alo);
+                // G[m] += Ty[m] * C[m], slot m = 2j + u: C rows 4j + 2u (re), 4j + 2u + 1 (im)
+                const float tyv[16] = {ty0[0], ty0[1], ty0[2], ty0[3], ty1[0], ty1[1], ty1[2], ty1[3],
+                                       ty2[0], ty2[1], ty2[2], ty2[3], ty3[0], ty3[1], ty3[2], ty3[3]};
+#pragma unroll
+                for (int m = 0; m < 8; ++m) {
+                    const int r = 4 * (m >> 1) + 2 * (m & 1);
+                    const float cr = C[r], ci = C[r + 1];
+                    const float tr = tyv[2 * m], ti = tyv[2 * m + 1];
+                    G[2 * m] += tr * cr - ti * ci;
+                    G[2 * m + 1] += tr * ci + ti * cr;
+                }
+                if (has_next) {
+                    uint4* nb = (uint4*)(lds + ((t + 1) & 1) * TILE_BYTES);
+                    nb[tid] = n0;
+                    nb[tid + 512] = n1;
+                }
+                __syncthreads();
+            }
+            // acc[m] += Tz[m] * G[m]
+            const f32x4* tzp = (const f32x4*)(a.tz + 2 * ((((wt * a.nzb + zb) * 2 + h) * ZB + col) * 8));
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const f32x4 v = tzp[k];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int m = 2 * k + u;
+                    const float tr = v[2 * u], ti = v[2 * u + 1];
+                    acc[2 * m] += tr * G[2 * m] - ti * G[2 * m + 1];
+                    acc[2 * m + 1] += tr * G[2 * m + 1] + ti * G[2 * m];
                 }
             }
         }
-        __syncthreads();
     }
-    // the last tile's y-update and its z block
-#pragma unroll
-    for (int m = 0; m < 8; ++m) slot_update(G, Cp, tyP, m);
-    close_zblock(acc, G, a.tz, wt, a.nzb, prev_zb, h, col);
 
     // sum over the 32 z lanes of each half (fixed butterfly order)
 #pragma unroll
