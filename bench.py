@@ -28,7 +28,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "MSFT patterns/s at 128³ grid, 512² detector (FP32 vs BF16-split vs plain); p99 ms"
-PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2500.0}   # MI355X dense matrix peaks
+PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2500.0, "bf16": 2500.0}   # MI355X dense matrix peaks
 HBM_PEAK_GBS = 8000.0
 
 
@@ -107,6 +107,26 @@ def time_batch(msft, torch, plan, ds, bs, steps, warmup):
     return batched_ms, plain_ms
 
 
+def time_backward(msft, torch, plan, d, b, steps, warmup):
+    """Time msft_backward (adjoint of one pattern) with a fixed seeded dL/dI."""
+    I, A = plan.simulate(d, b, amplitude=True)
+    A = torch.view_as_real(A).contiguous()
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    g = torch.randn(plan.npix, device="cuda", generator=gen)
+    gd, gb = torch.empty_like(d), torch.empty_like(b)
+    ws = plan.workspace()
+    for _ in range(warmup):
+        msft.msft_backward(plan.handle, d, b, A, g, gd, gb, ws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        msft.msft_backward(plan.handle, d, b, A, g, gd, gb, ws)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
 def oracle_error(wl, I_gpu, npix=256):
     """Relative L2 intensity error of a GPU pattern against the FP64 oracle on
     seeded pixels (all of them and the wide-angle ring theta > 3/4 theta_max)."""
@@ -168,7 +188,7 @@ def main():
     ap.add_argument("--batch", type=int, default=8, help="patterns per persistent batch launch")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["fp32", "bf16x3"], default=None,
+    ap.add_argument("--only", choices=["fp32", "bf16x3", "bf16"], default=None,
                     help="time one precision only (profiling runs)")
     ap.add_argument("--serving", type=int, default=64,
                     help="requests of the mixed-size serving stream (0 = skip)")
@@ -206,7 +226,7 @@ def main():
           file=sys.stderr, flush=True)
 
     results = {}
-    precisions = [args.only] if args.only else ["fp32", "bf16x3"]
+    precisions = [args.only] if args.only else ["fp32", "bf16x3", "bf16"]
     for prec in precisions:
         with msft.Plan.for_workload(wl, prec) as plan:
             r = time_single(msft, torch, plan, d, b, args.steps, args.warmup)
@@ -222,6 +242,15 @@ def main():
                    "error_vs_fp64_oracle": oracle_error(wl, r["intensity"])}
             print(f"[bench] {prec}: {ms:.3f} ms/pattern (contract {cms:.3f} ms, scan {sms:.4f} ms), "
                   f"{res['contract_tflops']:.1f} TFLOP/s algorithmic", file=sys.stderr, flush=True)
+            if prec == "fp32" and not args.only:
+                bms_adj = time_backward(msft, torch, plan, d, b, max(3, args.steps // 4), 1)
+                res["backward"] = {"ms_per_pattern": bms_adj,
+                                   "tflops": flops / (bms_adj * 1e-3) / 1e12,
+                                   "frac_fp32_mfma_peak": flops / (bms_adj * 1e-3) / 1e12 /
+                                   PEAK_TFLOPS["fp32"]}
+                print(f"[bench] fp32 backward: {bms_adj:.3f} ms/pattern, "
+                      f"{res['backward']['tflops']:.1f} TFLOP/s algorithmic",
+                      file=sys.stderr, flush=True)
             if args.batch > 1 and not args.only:
                 ds = [torch.roll(d, shifts=k, dims=0) for k in range(args.batch)]
                 bs = [torch.roll(b, shifts=k, dims=0) for k in range(args.batch)]

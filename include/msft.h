@@ -60,7 +60,9 @@ typedef enum {
 /* Arithmetic of the x-sum contraction (the dominant step). */
 typedef enum {
     MSFT_FP32 = 0,   /* FP32 MFMA, FP32 accumulation */
-    MSFT_BF16X3 = 1  /* BF16 hi+lo split, hi*hi + hi*lo + lo*hi on BF16 MFMA, FP32 accumulation */
+    MSFT_BF16X3 = 1, /* BF16 hi+lo split, hi*hi + hi*lo + lo*hi on BF16 MFMA, FP32 accumulation */
+    MSFT_BF16 = 2    /* plain BF16 operands (hi*hi only), FP32 accumulation: the unsplit
+                        reference point, about 1e-3 relative intensity error */
 } msft_precision;
 
 /* How the two voxel arrays become the effective strength w. */

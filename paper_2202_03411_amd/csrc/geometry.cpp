@@ -37,7 +37,8 @@ msft_status validate_geometry(const msft_geometry* g, bool qlist, std::string* w
     if (!(g->dx > 0.0 && g->dy > 0.0 && g->dz > 0.0) || !std::isfinite(g->dx) ||
         !std::isfinite(g->dy) || !std::isfinite(g->dz))
         return fail("voxel pitch must be finite and > 0");
-    if (g->precision != MSFT_FP32 && g->precision != MSFT_BF16X3) return fail("unknown precision");
+    if (g->precision != MSFT_FP32 && g->precision != MSFT_BF16X3 && g->precision != MSFT_BF16)
+        return fail("unknown precision");
     if (g->strength != MSFT_STRENGTH_MSFT && g->strength != MSFT_STRENGTH_BORN &&
         g->strength != MSFT_STRENGTH_DENSITY)
         return fail("unknown strength mode");

@@ -312,7 +312,8 @@ int launch_scan(int precision, const ScanArgs& a, void* stream)
 // C = A . B for one W tile: the wave's A operand (registers) times the tile's
 // column `col` of lane half h (LDS row `row`), over the first `nx` x values.
 // FP32: 4 x values per 16-byte LDS slot, one v_mfma_f32_32x32x2_f32 per x.
-// BF16X3: 8 x values per slot, hi*hi + hi*lo + lo*hi on v_mfma_f32_32x32x16_bf16.
+// BF16X3: 8 x values per slot, hi*hi + hi*lo + lo*hi on v_mfma_f32_32x32x16_bf16;
+// BF16 (plain): hi*hi only, from the same tables.
 template <int PREC, int NX>
 __device__ __forceinline__ f32x16 tile_mfma(const uint8_t* row, int col, const f32x4* Af,
                                             const bf16x8* Ahi, const bf16x8* Alo)
@@ -332,10 +333,12 @@ __device__ __forceinline__ f32x16 tile_mfma(const uint8_t* row, int col, const f
 #pragma unroll
         for (int s = 0; s < NX / 8; ++s) {
             const bf16x8 bh = *(const bf16x8*)(row + ((s ^ sw) << 4));
-            const bf16x8 bl = *(const bf16x8*)(row + (((8 + s) ^ sw) << 4));
             C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ahi[s], bh, C, 0, 0, 0);
-            C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ahi[s], bl, C, 0, 0, 0);
-            C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Alo[s], bh, C, 0, 0, 0);
+            if (PREC == MSFT_BF16X3) {
+                const bf16x8 bl = *(const bf16x8*)(row + (((8 + s) ^ sw) << 4));
+                C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ahi[s], bl, C, 0, 0, 0);
+                C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Alo[s], bh, C, 0, 0, 0);
+            }
         }
     }
     return C;
@@ -364,10 +367,12 @@ __device__ __forceinline__ f32x16 tile_mfma_partial(const uint8_t* row, int col,
                 }
             } else {
                 const bf16x8 bh = *(const bf16x8*)(row + ((s ^ sw) << 4));
-                const bf16x8 bl = *(const bf16x8*)(row + (((8 + s) ^ sw) << 4));
                 C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ahi[s], bh, C, 0, 0, 0);
-                C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ahi[s], bl, C, 0, 0, 0);
-                C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Alo[s], bh, C, 0, 0, 0);
+                if (PREC == MSFT_BF16X3) {
+                    const bf16x8 bl = *(const bf16x8*)(row + (((8 + s) ^ sw) << 4));
+                    C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ahi[s], bl, C, 0, 0, 0);
+                    C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Alo[s], bh, C, 0, 0, 0);
+                }
             }
         }
     }
@@ -410,7 +415,7 @@ __device__ __forceinline__ void fwd_block(const FwdArgs& a, int64_t block, uint8
 #pragma unroll
             for (int s = 0; s < 8; ++s) {
                 Ahi[s] = ((const bf16x8*)ta)[s * 128 + lane];
-                Alo[s] = ((const bf16x8*)ta)[s * 128 + 64 + lane];
+                if (PREC == MSFT_BF16X3) Alo[s] = ((const bf16x8*)ta)[s * 128 + 64 + lane];
             }
         }
         for (int zb = 0; zb < a.nzb; ++zb) {
@@ -525,8 +530,11 @@ int launch_forward(int precision, const FwdArgs& a, int64_t block_begin, int64_t
     if (precision == MSFT_FP32)
         hipLaunchKernelGGL(fwd_kernel<MSFT_FP32>, dim3((unsigned)nblocks), dim3(512), 0, s, a,
                            block_begin);
-    else
+    else if (precision == MSFT_BF16X3)
         hipLaunchKernelGGL(fwd_kernel<MSFT_BF16X3>, dim3((unsigned)nblocks), dim3(512), 0, s, a,
+                           block_begin);
+    else
+        hipLaunchKernelGGL(fwd_kernel<MSFT_BF16>, dim3((unsigned)nblocks), dim3(512), 0, s, a,
                            block_begin);
     return (int)hipGetLastError();
 }
@@ -538,8 +546,10 @@ int launch_forward_batch(int precision, const BatchArgs& b, int32_t grid, void* 
     hipLaunchKernelGGL(zero_counter, dim3(1), dim3(1), 0, s, b.counter);
     if (precision == MSFT_FP32)
         hipLaunchKernelGGL(fwd_batch_kernel<MSFT_FP32>, dim3(grid), dim3(512), 0, s, b);
-    else
+    else if (precision == MSFT_BF16X3)
         hipLaunchKernelGGL(fwd_batch_kernel<MSFT_BF16X3>, dim3(grid), dim3(512), 0, s, b);
+    else
+        hipLaunchKernelGGL(fwd_batch_kernel<MSFT_BF16>, dim3(grid), dim3(512), 0, s, b);
     return (int)hipGetLastError();
 }
 

@@ -18,11 +18,11 @@ from . import build as _build
 
 MSFT_OK, MSFT_ERR_INVALID, MSFT_ERR_UNDERSAMPLED = 0, 1, 2
 MSFT_ERR_NOMEM, MSFT_ERR_DEVICE, MSFT_ERR_BUSY, MSFT_ERR_UNSUPPORTED = 3, 4, 5, 6
-MSFT_FP32, MSFT_BF16X3 = 0, 1
+MSFT_FP32, MSFT_BF16X3, MSFT_BF16 = 0, 1, 2
 MSFT_STRENGTH_MSFT, MSFT_STRENGTH_BORN, MSFT_STRENGTH_DENSITY = 0, 1, 2
 MSFT_ALLOW_ALIAS = 1
 
-PRECISIONS = {"fp32": MSFT_FP32, "bf16x3": MSFT_BF16X3}
+PRECISIONS = {"fp32": MSFT_FP32, "bf16x3": MSFT_BF16X3, "bf16": MSFT_BF16}
 STRENGTHS = {"msft": MSFT_STRENGTH_MSFT, "born": MSFT_STRENGTH_BORN, "density": MSFT_STRENGTH_DENSITY}
 
 

@@ -116,6 +116,18 @@ def test_parity_pattern_sampled(msft, precision):
     assert _rel(I[ring], Io[ring]) <= TOL[precision]
 
 
+def test_plain_bf16_is_the_unsplit_reference(msft):
+    # single BF16 products: about 1e-3 of the intensity, clearly behind the split form
+    wl = inputs.pattern_workload()
+    pix = inputs.random_pixels(wl.det_n, 512, seed=79)
+    Io, _ = _oracle(wl, pixels=pix)
+    e_plain = _rel(_run(msft, wl, "bf16", pixels=pix)[0], Io)
+    e_split = _rel(_run(msft, wl, "bf16x3", pixels=pix)[0], Io)
+    print(f"  plain bf16 {e_plain:.3e}  split {e_split:.3e}")
+    assert e_plain <= 1e-2
+    assert e_split < 0.1 * e_plain
+
+
 def test_qlist_small_angle_is_fft(msft):
     # explicit q list on the Fourier grid with q_z = 0: |A|^2 = |fft2(projection)|^2
     import torch
