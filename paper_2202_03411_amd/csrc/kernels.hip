@@ -418,6 +418,10 @@ __device__ __forceinline__ void fwd_block(const FwdArgs& a, int64_t block, uint8
                 if (PREC == MSFT_BF16X3) Alo[s] = ((const bf16x8*)ta)[s * 128 + 64 + lane];
             }
         }
+        // Wait for the A operand here, once per chunk.  The memory counter is in
+        // order, so without this the waits the compiler places for A inside the
+        // tile loop would also wait for the next tile's prefetch, mid-chain.
+        __builtin_amdgcn_s_waitcnt(0);
         for (int zb = 0; zb < a.nzb; ++zb) {
             float G[16];
 #pragma unroll
