@@ -127,6 +127,89 @@ def time_backward(msft, torch, plan, d, b, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
+def time_fit(torch, batch, steps, warmup, log):
+    """One iteration of the differentiable fit: `batch` l <= 8 soft-voxelized
+    shapes (81 coefficients, edge width one pitch) in a 680 nm box on 128^3,
+    512^2 detector to 60 deg at 45 nm; loss = mean squared log-intensity error
+    against seeded targets; adjoint through msft_backward and the soft
+    voxelization; one Adam step.  Shapes go through the GPU one at a time and
+    their gradients accumulate, so the batch never has to be resident at once."""
+    import numpy as np
+
+    from paper_2202_03411_amd import fit, inputs, msft
+    n, det, box, lmax, r0 = 128, 512, 680.0, 8, 200.0
+    star = fit.SoftStar(n, box, lmax, r0)
+    plan = msft.Plan(45.0, 60.0, det, (n, n, n), (star.pitch,) * 3, "fp32", "msft")
+    rng = np.random.default_rng(inputs.SEED_BASE + 4)
+    ncoef = (lmax + 1) ** 2
+    tc = rng.normal(0.0, 0.08, size=(batch, ncoef))
+    tc[:, 0] = 0.0
+    targets = []
+    with torch.no_grad():
+        for k in range(batch):
+            dk, bk = star.voxelize(torch.tensor(tc[k], dtype=torch.float32, device="cuda"))
+            targets.append(plan.simulate(dk.contiguous(), bk.contiguous()).clone())
+    coeffs = torch.zeros(batch, ncoef, device="cuda", requires_grad=True)
+    opt = torch.optim.Adam([coeffs], lr=1e-3)
+
+    def iteration():
+        opt.zero_grad()
+        for k in range(batch):
+            dk, bk = star.voxelize(coeffs[k])
+            I = fit.simulate(dk.contiguous(), bk.contiguous(), plan)
+            (fit.log_mse_loss(I, targets[k]) / batch).backward()
+        opt.step()
+
+    for _ in range(warmup):
+        iteration()
+    torch.cuda.synchronize()
+    times = []
+    for it in range(steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        iteration()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) / 1e3)
+        log(f"fit iteration {it + 1}/{steps}: {times[-1]:.2f} s")
+    plan.close()
+    s = sum(times) / len(times)
+    P, V = det * det, n ** 3
+    return {"batch": batch, "iterations": steps, "s_per_iteration": s,
+            "shapes_per_s": batch / s,
+            "tflops_fwd_plus_bwd": 2 * 8.0 * P * V * batch / s / 1e12}
+
+
+def time_uniform(msft, torch, wl, d, b, prec, steps, warmup):
+    """The same body on the uniform transverse-q detector of the slice-transform
+    algorithm (separable two-stage contraction), checked on seeded pixels."""
+    import numpy as np
+
+    import oracle
+    from paper_2202_03411_amd import inputs
+    with msft.Plan(wl.wavelength, wl.theta_max_deg, wl.det_n, wl.grid, wl.pitch, prec, "msft",
+                   detector="uniform_q") as plan:
+        r = time_single(msft, torch, plan, d, b, steps, warmup)
+        I = r["intensity"].cpu().numpy().astype(np.float64)
+    n, (nx, ny, nz) = wl.det_n, wl.grid
+    flops = 8.0 * n * nx * ny * nz + 8.0 * n * n * ny * nz   # stage 1 + stage 2
+    ms = sum(r["step_ms"]) / len(r["step_ms"])
+    cms = sum(r["contract_ms"]) / len(r["contract_ms"])
+    pix = inputs.random_pixels(n, 256, seed=83)
+    q = oracle.qmap_uniform(wl.wavelength, wl.theta_max_deg, n)[pix]
+    ok = ~np.isnan(q[:, 2])
+    w = oracle.strength(wl.mode, wl.delta.astype(np.float64), wl.beta.astype(np.float64),
+                        wl.pitch, wl.wavelength)
+    Io = np.abs(oracle.amplitude(q[ok], w, wl.pitch, 1)) ** 2
+    err = float(np.linalg.norm(I[pix][ok] - Io) / np.linalg.norm(Io))
+    return {"ms_per_step": ms, "patterns_per_s": 1000.0 / ms,
+            "p50_ms": _pct(r["step_ms"], 50), "p99_ms": _pct(r["step_ms"], 99),
+            "contract_ms": cms, "separable_flops": flops,
+            "contract_tflops": flops / (cms * 1e-3) / 1e12,
+            "direct_equivalent_terms_per_s": n * n * nx * ny * nz / (ms * 1e-3),
+            "error_vs_fp64_oracle": {"rel_l2_intensity": err, "pixels": int(ok.sum())}}
+
+
 def oracle_error(wl, I_gpu, npix=256):
     """Relative L2 intensity error of a GPU pattern against the FP64 oracle on
     seeded pixels (all of them and the wide-angle ring theta > 3/4 theta_max)."""
@@ -188,12 +271,16 @@ def main():
     ap.add_argument("--batch", type=int, default=8, help="patterns per persistent batch launch")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["fp32", "bf16x3", "bf16"], default=None,
+    ap.add_argument("--only", choices=["fp32", "bf16x3", "bf16", "uniform_fp32", "uniform_bf16x3"],
+                    default=None,
                     help="time one precision only (profiling runs)")
     ap.add_argument("--serving", type=int, default=64,
                     help="requests of the mixed-size serving stream (0 = skip)")
     ap.add_argument("--large", action="store_true",
                     help="also time the 256^3 / 1024^2 pattern (l <= 10 body with voids, 80 deg)")
+    ap.add_argument("--fit", type=int, default=0, metavar="B",
+                    help="also time iterations of the differentiable fit with batch B")
+    ap.add_argument("--fit-steps", type=int, default=1)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 256 MiB device-to-device copy, the reference for "
                          "scaling hardware byte counters")
@@ -224,6 +311,17 @@ def main():
     b = torch.from_numpy(wl.beta).cuda()
     print(f"[bench] workload {wl.name} grid {wl.grid} det {wl.det_n}^2, {P * V:.3e} terms/pattern",
           file=sys.stderr, flush=True)
+
+    if args.only and args.only.startswith("uniform_"):
+        prec = args.only.split("_", 1)[1]
+        u = time_uniform(msft, torch, wl, d, b, prec, args.steps, args.warmup)
+        print(f"[bench] uniform-q {prec}: {u['ms_per_step']:.3f} ms/pattern, "
+              f"{u['contract_tflops']:.1f} TFLOP/s", file=sys.stderr, flush=True)
+        print(json.dumps({"metric": "MSFT patterns/s, uniform-q detector, 128³ grid, 512²",
+                          "value": u["patterns_per_s"], "unit": "patterns/s", "n_gpus": 1,
+                          "steps": args.steps, "warmup": args.warmup, "dtype": "f32",
+                          "higher_is_better": True, "uniform_q": {prec: u}}))
+        return
 
     results = {}
     precisions = [args.only] if args.only else ["fp32", "bf16x3", "bf16"]
@@ -323,12 +421,20 @@ def main():
         del ld, lb
     if args.serving > 0 and not args.only:
         from paper_2202_03411_amd import serving
-        sv = serving.benchmark(args.serving, "fp32", load=0.8)
-        line["serving"] = sv
-        for k in ("offline_batched", "offline_plain", "poisson_batched", "poisson_plain"):
-            print(f"[bench] serving {k}: {sv[k]['patterns_per_s']:.2f} patterns/s, "
-                  f"p50 {sv[k]['p50_ms']:.1f} ms, p99 {sv[k]['p99_ms']:.1f} ms",
-                  file=sys.stderr, flush=True)
+        line["serving"] = serving.benchmark(
+            args.serving, "fp32", loads=(0.8,),
+            log=lambda m: print(f"[bench] serving {m}", file=sys.stderr, flush=True))
+    if not args.only:
+        line["uniform_q"] = {}
+        for prec in ("fp32", "bf16x3"):
+            u = time_uniform(msft, torch, wl, d, b, prec, args.steps, args.warmup)
+            line["uniform_q"][prec] = u
+            print(f"[bench] uniform-q {prec}: {u['ms_per_step']:.3f} ms/pattern, "
+                  f"{u['contract_tflops']:.1f} TFLOP/s (two stages), error "
+                  f"{u['error_vs_fp64_oracle']['rel_l2_intensity']:.2e}", file=sys.stderr, flush=True)
+    if args.fit > 0:
+        line["fit"] = time_fit(torch, args.fit, args.fit_steps, 1 if args.fit_steps else 0,
+                               lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
     if not args.no_cpu_baseline and not args.only:
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(line))

@@ -77,6 +77,26 @@ typedef enum {
 #define MSFT_ALLOW_ALIAS 1u /* accept grids whose pitch exceeds pi / max|q| on some axis */
 
 /*
+ * MSFT_DETECTOR_UNIFORM_Q: instead of the flat screen, the virtual detector of the
+ * paper's slice-transform algorithm (Sec. 3, Blocks 3 and 6-7): pixels on a uniform
+ * grid of transverse momentum, q_x(i) = (2i + 1 - N) q_max / N and q_y(j) likewise,
+ * with q_max = k0 sin(theta_max) (the outer edge of the edge pixel along each axis
+ * is at theta_max), and q_z = sqrt(k0^2 - q_x^2 - q_y^2) - k0 on the Ewald sphere.
+ * A pixel with q_x^2 + q_y^2 >= k0^2 (a corner beyond the sphere's rim when
+ * sin(theta_max) > 1/sqrt(2)) receives no propagating wave: its intensity and
+ * amplitude are written as 0 and msft_plan_qmap reports its q_z as NaN.
+ * Because q_x depends on i alone and q_y on j alone, msft_simulate runs the
+ * separable form: H(i, y, z) = sum_x exp(-i q_x(i) x) w for every column i (one
+ * contraction of N x nx by nx x ny nz), then for every pixel
+ * A = sum_z exp(-i q_z z) sum_y exp(-i q_y(j) y) H(i, y, z) (a contraction over y
+ * with the z phase behind it): about N (nx + N) ny nz complex products instead of
+ * N^2 nx ny nz.  Same pixel order p = j * N + i and the same sum as the flat form
+ * for these q.  Not accepted by msft_plan_qlist or msft_simulate_batch;
+ * msft_backward uses the general adjoint.
+ */
+#define MSFT_DETECTOR_UNIFORM_Q 2u
+
+/*
  * Experiment and target description (Sec. 3, Blocks 1 and 2): wavelength,
  * maximal scattering angle and detector resolution; voxel counts and pitch.
  * struct_size must be sizeof(msft_geometry).
@@ -90,7 +110,7 @@ typedef struct {
     double dx, dy, dz;     /* voxel pitch > 0 */
     int32_t precision;     /* msft_precision */
     int32_t strength;      /* msft_strength */
-    uint32_t flags;        /* MSFT_ALLOW_ALIAS */
+    uint32_t flags;        /* MSFT_ALLOW_ALIAS | MSFT_DETECTOR_UNIFORM_Q */
 } msft_geometry;
 
 typedef struct msft_plan_s* msft_plan_t;
@@ -182,7 +202,8 @@ msft_status msft_batch_query(const msft_request* reqs, int32_t n, size_t* worksp
  * in one persistent launch: every request's pixel blocks become work items that
  * the workgroups pull in a cost-sorted order.  Each pixel written is
  * bit-identical to what msft_simulate writes for that request alone.
- * Returns MSFT_ERR_BUSY if ws_bytes is smaller than msft_batch_query reports.
+ * Returns MSFT_ERR_BUSY if ws_bytes is smaller than msft_batch_query reports,
+ * and MSFT_ERR_UNSUPPORTED for a plan of the uniform-q detector.
  */
 msft_status msft_simulate_batch(const msft_request* reqs, int32_t n, void* workspace,
                                 size_t ws_bytes, void* stream);

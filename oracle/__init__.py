@@ -43,6 +43,7 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         d, i32, i64, p = ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
         lib.oracle_qmap.argtypes = [d, d, i32, p]
+        lib.oracle_qmap_uniform.argtypes = [d, d, i32, p]
         lib.oracle_grid.argtypes = [i32, d, p]
         lib.oracle_strength.argtypes = [i32, i32, i32, i32, d, d, d, d, p, p, p]
         lib.oracle_amplitude.argtypes = [i32, p, i64, i32, i32, i32, d, d, d, p, p]
@@ -50,7 +51,7 @@ def _load():
                                         p, p, p, i64, p, p]
         lib.oracle_threads.argtypes = []
         lib.oracle_threads.restype = ctypes.c_int
-        for f in (lib.oracle_qmap, lib.oracle_grid, lib.oracle_strength,
+        for f in (lib.oracle_qmap, lib.oracle_qmap_uniform, lib.oracle_grid, lib.oracle_strength,
                   lib.oracle_amplitude, lib.oracle_backward):
             f.restype = None
         _lib = lib
@@ -74,6 +75,14 @@ def qmap(wavelength: float, theta_max_deg: float, n: int) -> np.ndarray:
     """Transfer momentum of every pixel of a flat n x n detector, shape (n*n, 3)."""
     out = np.empty((n * n, 3), np.float64)
     _load().oracle_qmap(float(wavelength), float(theta_max_deg), int(n), _ptr(out))
+    return out
+
+
+def qmap_uniform(wavelength: float, theta_max_deg: float, n: int) -> np.ndarray:
+    """Transfer momentum of every pixel of the uniform transverse-q virtual detector,
+    shape (n*n, 3); q_z is NaN where no outgoing wave exists."""
+    out = np.empty((n * n, 3), np.float64)
+    _load().oracle_qmap_uniform(float(wavelength), float(theta_max_deg), int(n), _ptr(out))
     return out
 
 

@@ -68,6 +68,38 @@ void oracle_qmap(double wavelength, double theta_max_deg, int32_t n, double* q)
     }
 }
 
+/*
+ * Pixel -> transfer momentum for the virtual detector of the slice-transform
+ * algorithm (Sec. 3, Blocks 3 and 6): the discrete transform of a slice lands on
+ * a uniform grid of transverse momentum, so pixel (i, j) has
+ * qx = (2i + 1 - N) qmax / N, qy = (2j + 1 - N) qmax / N with qmax = k0 sin(theta_max),
+ * and lies on the Ewald sphere: the outgoing wave vector is (qx, qy, kz) with
+ * kz = sqrt(k0^2 - qx^2 - qy^2), so qz = kz - k0 = -s / (kz + k0), s = qx^2 + qy^2.
+ * Where s >= k0^2 no outgoing wave exists and qz is NaN.  p = j * N + i.
+ */
+void oracle_qmap_uniform(double wavelength, double theta_max_deg, int32_t n, double* q)
+{
+    const double k0 = oracle_k0(wavelength);
+    const double qmax = k0 * sin((theta_max_deg * ORACLE_PI) / 180.0);
+    const double k2 = k0 * k0;
+    for (int32_t j = 0; j < n; ++j) {
+        const double qy = ((double)(2 * j + 1 - n) * qmax) / (double)n;
+        for (int32_t i = 0; i < n; ++i) {
+            const double qx = ((double)(2 * i + 1 - n) * qmax) / (double)n;
+            const double s = qx * qx + qy * qy;
+            double* qp = q + 3 * ((int64_t)j * n + i);
+            qp[0] = qx;
+            qp[1] = qy;
+            if (s < k2) {
+                const double kz = sqrt(k2 - s);
+                qp[2] = -(s / (kz + k0));
+            } else {
+                qp[2] = NAN;
+            }
+        }
+    }
+}
+
 /* Voxel centres of a grid of n cells with pitch d, centred on the origin. */
 void oracle_grid(int32_t n, double d, double* c)
 {

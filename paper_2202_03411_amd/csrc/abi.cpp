@@ -62,11 +62,11 @@ void free_device(msft_plan_s* p)
 {
     if (p->device < 0) return;
     DeviceScope ds(p->device);
-    void* ptrs[] = {p->q_dev, p->xs_dev, p->ys_dev, p->zs_dev, p->txa, p->ty, p->tz};
+    void* ptrs[] = {p->q_dev, p->xs_dev, p->ys_dev, p->zs_dev, p->txa, p->ty, p->tz, p->txa2};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     p->q_dev = p->xs_dev = p->ys_dev = p->zs_dev = nullptr;
-    p->txa = nullptr;
+    p->txa = p->txa2 = nullptr;
     p->ty = p->tz = nullptr;
 }
 
@@ -100,25 +100,70 @@ msft_status build_device_tables(msft_plan_s* p)
             return hip_fail(e, what);         \
         }                                     \
     } while (0)
+    // The adjoint reads q per pixel; a pixel beyond the Ewald sphere's rim (q_z NaN)
+    // has A = 0 and so h = 0, and any finite q_z keeps its terms at zero.
+    std::vector<double> qd(geo.q);
+    for (int64_t k = 2; k < 3 * geo.npix; k += 3)
+        if (!std::isfinite(qd[k])) qd[k] = 0.0;
     MSFT_TRY(dev_alloc(&p->q_dev, sizeof(double) * 3 * geo.npix, &total), "hipMalloc q");
     MSFT_TRY(dev_alloc(&p->xs_dev, sizeof(double) * d.nx, &total), "hipMalloc x");
     MSFT_TRY(dev_alloc(&p->ys_dev, sizeof(double) * d.ny, &total), "hipMalloc y");
     MSFT_TRY(dev_alloc(&p->zs_dev, sizeof(double) * d.nz, &total), "hipMalloc z");
-    MSFT_TRY(dev_alloc(&p->txa, d.txa_bytes(), &total), "hipMalloc Tx");
-    MSFT_TRY(dev_alloc(&p->ty, d.ty_bytes(), &total), "hipMalloc Ty");
-    MSFT_TRY(dev_alloc(&p->tz, d.tz_bytes(), &total), "hipMalloc Tz");
-    MSFT_TRY(hipMemcpy(p->q_dev, geo.q.data(), sizeof(double) * 3 * geo.npix, hipMemcpyHostToDevice),
+    if (p->separable) {
+        MSFT_TRY(dev_alloc(&p->txa, p->sep.txa1_bytes(d.nxc), &total), "hipMalloc Tx");
+        MSFT_TRY(dev_alloc(&p->txa2, p->sep.txa2_bytes(), &total), "hipMalloc Ty");
+        MSFT_TRY(dev_alloc(&p->tz, p->sep.tz_bytes(d.nzb), &total), "hipMalloc Tz");
+    } else {
+        MSFT_TRY(dev_alloc(&p->txa, d.txa_bytes(), &total), "hipMalloc Tx");
+        MSFT_TRY(dev_alloc(&p->ty, d.ty_bytes(), &total), "hipMalloc Ty");
+        MSFT_TRY(dev_alloc(&p->tz, d.tz_bytes(), &total), "hipMalloc Tz");
+    }
+    MSFT_TRY(hipMemcpy(p->q_dev, qd.data(), sizeof(double) * 3 * geo.npix, hipMemcpyHostToDevice),
              "copy q");
     MSFT_TRY(hipMemcpy(p->xs_dev, geo.xs.data(), sizeof(double) * d.nx, hipMemcpyHostToDevice), "copy x");
     MSFT_TRY(hipMemcpy(p->ys_dev, geo.ys.data(), sizeof(double) * d.ny, hipMemcpyHostToDevice), "copy y");
     MSFT_TRY(hipMemcpy(p->zs_dev, geo.zs.data(), sizeof(double) * d.nz, hipMemcpyHostToDevice), "copy z");
     hipStream_t s = nullptr;
     MSFT_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate");
-    e = (hipError_t)launch_twiddles(p->geo.g.precision, d, p->q_dev, p->xs_dev, p->ys_dev,
-                                    p->zs_dev, p->txa, p->ty, p->tz, s);
-    hipError_t e2 = hipStreamSynchronize(s);
+    if (p->separable) {
+        // per-column q_x, per-row q_y (slot 0 of a [N][3] array each) and q_z over the
+        // second stage's pixel order (i, j), NaN for padding rows j >= N
+        const SepDims& sd = p->sep;
+        std::vector<double> qcol(3 * (size_t)sd.n, 0.0), qrow(3 * (size_t)sd.n, 0.0);
+        std::vector<double> qk(3 * (size_t)sd.n * sd.npad, std::nan(""));
+        for (int32_t a = 0; a < sd.n; ++a) {
+            qcol[3 * a] = geo.q[3 * (size_t)a];                 // pixel (i = a, j = 0)
+            qrow[3 * a] = geo.q[3 * ((size_t)a * sd.n) + 1];    // pixel (i = 0, j = a)
+        }
+        for (int32_t i = 0; i < sd.n; ++i)
+            for (int32_t j = 0; j < sd.n; ++j)
+                qk[3 * ((size_t)i * sd.npad + j) + 2] = geo.q[3 * ((size_t)j * sd.n + i) + 2];
+        double *qcol_dev = nullptr, *qrow_dev = nullptr, *qk_dev = nullptr;
+        size_t scratch = 0;
+        e = dev_alloc(&qcol_dev, sizeof(double) * qcol.size(), &scratch);
+        if (e == hipSuccess) e = dev_alloc(&qrow_dev, sizeof(double) * qrow.size(), &scratch);
+        if (e == hipSuccess) e = dev_alloc(&qk_dev, sizeof(double) * qk.size(), &scratch);
+        if (e == hipSuccess)
+            e = hipMemcpy(qcol_dev, qcol.data(), sizeof(double) * qcol.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(qrow_dev, qrow.data(), sizeof(double) * qrow.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(qk_dev, qk.data(), sizeof(double) * qk.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = (hipError_t)launch_sep_twiddles(p->geo.g.precision, d, sd, qcol_dev, qrow_dev, qk_dev,
+                                                p->xs_dev, p->ys_dev, p->zs_dev, p->txa, p->txa2,
+                                                p->tz, s);
+        hipError_t e2 = hipStreamSynchronize(s);
+        if (e == hipSuccess) e = e2;
+        for (double* t : {qcol_dev, qrow_dev, qk_dev})
+            if (t) (void)hipFree(t);
+    } else {
+        e = (hipError_t)launch_twiddles(p->geo.g.precision, d, p->q_dev, p->xs_dev, p->ys_dev,
+                                        p->zs_dev, p->txa, p->ty, p->tz, s);
+        hipError_t e2 = hipStreamSynchronize(s);
+        if (e == hipSuccess) e = e2;
+    }
     (void)hipStreamDestroy(s);
-    if (e == hipSuccess) e = e2;
     if (e != hipSuccess) {
         free_device(p);
         return hip_fail(e, "twiddle generation");
@@ -153,6 +198,13 @@ msft_status make_plan(const msft_geometry* g, const double* q_host, int64_t npix
                     delete p;
                     return fail(MSFT_ERR_INVALID, "q list holds a non-finite value");
                 }
+        } else if (g->flags & MSFT_DETECTOR_UNIFORM_Q) {
+            p->separable = true;
+            p->geo.npix = (int64_t)g->det_n * g->det_n;
+            p->geo.q.resize(3 * p->geo.npix);
+            std::vector<double> qx(g->det_n), qy(g->det_n);
+            uniform_qmap(g->wavelength, g->theta_max_deg, g->det_n, p->geo.q.data(), qx.data(),
+                         qy.data());
         } else {
             p->geo.npix = (int64_t)g->det_n * g->det_n;
             p->geo.q.resize(3 * p->geo.npix);
@@ -180,7 +232,12 @@ msft_status make_plan(const msft_geometry* g, const double* q_host, int64_t npix
         return fail(MSFT_ERR_UNDERSAMPLED, buf);
     }
     p->dims = make_dims(p->geo.npix, g->nx, g->ny, g->nz);
-    p->workspace_bytes = std::max(align256(p->dims.wtile_bytes()), align256(make_adj_dims(p->dims).bytes()));
+    size_t fwd_ws = align256(p->dims.wtile_bytes());
+    if (p->separable) {
+        p->sep = make_sep_dims(g->det_n, g->ny);
+        fwd_ws += align256(p->sep.h_bytes(p->dims.nzb));
+    }
+    p->workspace_bytes = std::max(fwd_ws, align256(make_adj_dims(p->dims).bytes()));
     p->device = device;
     if (device >= 0) {
         int count = 0;
@@ -217,7 +274,65 @@ FwdArgs forward_args(const msft_plan_s* p, const void* wtiles, float* intensity,
     a.nxc = p->dims.nxc;
     a.nzb = p->dims.nzb;
     a.x_pad = p->dims.x_pad;
+    a.group_blocks = a.group_tiles = a.a_waves = a.out_n = a.out_npad = 0;
     return a;
+}
+
+// Second stage of the separable detector: H tiles (after the W tiles in the
+// workspace) contracted over y; one tile group of nyc * nzb tiles per column i.
+FwdArgs sep_stage2_args(const msft_plan_s* p, const void* workspace, float* intensity,
+                        float* amplitude)
+{
+    const SepDims& sd = p->sep;
+    FwdArgs a;
+    a.wtiles = (const uint8_t*)workspace + align256(p->dims.wtile_bytes());
+    a.txa = p->txa2;
+    a.ty = nullptr;
+    a.tz = p->tz;
+    a.intensity = intensity;
+    a.amplitude = amplitude;
+    a.npix = (int64_t)sd.n * sd.npad;
+    a.ny = 1;
+    a.nxc = sd.nyc;
+    a.nzb = p->dims.nzb;
+    a.x_pad = sd.y_pad;
+    a.group_blocks = sd.npad / BLOCK_PIX;
+    a.group_tiles = sd.nyc * p->dims.nzb;
+    a.a_waves = sd.npad / WAVE_PIX;
+    a.out_n = sd.n;
+    a.out_npad = sd.npad;
+    return a;
+}
+
+Stage1Args sep_stage1_args(const msft_plan_s* p, const void* workspace)
+{
+    Stage1Args a;
+    a.wtiles = (const uint8_t*)workspace;
+    a.txa = p->txa;
+    a.htiles = (uint8_t*)workspace + align256(p->dims.wtile_bytes());
+    a.n = p->sep.n;
+    a.ny = p->dims.ny;
+    a.nxc = p->dims.nxc;
+    a.nzb = p->dims.nzb;
+    a.x_pad = p->dims.x_pad;
+    a.nyc = p->sep.nyc;
+    return a;
+}
+
+// The contraction of a plan after the scan: one launch for the flat detector,
+// the two stages for the separable one.
+int launch_contraction(const msft_plan_s* p, const void* workspace, float* intensity,
+                       float* amplitude, void* stream)
+{
+    const int prec = p->geo.g.precision;
+    if (!p->separable)
+        return launch_forward(prec, forward_args(p, workspace, intensity, amplitude), 0,
+                              p->dims.nblocks, true, stream);
+    int e = launch_sep_stage1(prec, sep_stage1_args(p, workspace), p->sep.nblk1, stream);
+    if (e) return e;
+    const int64_t nblk2 = (int64_t)p->sep.n * (p->sep.npad / BLOCK_PIX);
+    return launch_forward(prec, sep_stage2_args(p, workspace, intensity, amplitude), 0, nblk2,
+                          false, stream);
 }
 
 ScanArgs scan_args(const msft_plan_s* p, const float* delta, const float* beta, void* wtiles)
@@ -313,8 +428,7 @@ msft_status msft_simulate(msft_plan_t plan, const float* delta, const float* bet
     const ScanArgs sa = scan_args(plan, delta, beta, workspace);
     int e = launch_scan(plan->geo.g.precision, sa, stream);
     if (e) return hip_fail((hipError_t)e, "scan launch");
-    const FwdArgs fa = forward_args(plan, workspace, intensity, amplitude);
-    e = launch_forward(plan->geo.g.precision, fa, 0, plan->dims.nblocks, stream);
+    e = launch_contraction(plan, workspace, intensity, amplitude, stream);
     if (e) return hip_fail((hipError_t)e, "forward launch");
     return ok();
 }
@@ -342,8 +456,7 @@ msft_status msft_simulate_contract(msft_plan_t plan, const void* workspace, floa
     if (!aligned256(workspace)) return fail(MSFT_ERR_INVALID, "workspace must be 256-byte aligned");
     DeviceScope ds(plan->device);
     if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice");
-    const FwdArgs fa = forward_args(plan, workspace, intensity, amplitude);
-    int e = launch_forward(plan->geo.g.precision, fa, 0, plan->dims.nblocks, stream);
+    int e = launch_contraction(plan, workspace, intensity, amplitude, stream);
     if (e) return hip_fail((hipError_t)e, "forward launch");
     return ok();
 }
@@ -359,6 +472,8 @@ static msft_status batch_layout(const msft_request* reqs, int32_t n, std::vector
     for (int32_t r = 0; r < n; ++r) {
         msft_status st = check_runnable(reqs[r].plan);
         if (st != MSFT_OK) return st;
+        if (reqs[r].plan->separable)
+            return fail(MSFT_ERR_UNSUPPORTED, "batches take flat-detector plans only");
         if (offs) (*offs)[r] = off;
         off += align256(reqs[r].plan->dims.wtile_bytes());
     }

@@ -42,7 +42,9 @@ msft_status validate_geometry(const msft_geometry* g, bool qlist, std::string* w
     if (g->strength != MSFT_STRENGTH_MSFT && g->strength != MSFT_STRENGTH_BORN &&
         g->strength != MSFT_STRENGTH_DENSITY)
         return fail("unknown strength mode");
-    if (g->flags & ~MSFT_ALLOW_ALIAS) return fail("unknown flag bits");
+    if (g->flags & ~(MSFT_ALLOW_ALIAS | MSFT_DETECTOR_UNIFORM_Q)) return fail("unknown flag bits");
+    if (qlist && (g->flags & MSFT_DETECTOR_UNIFORM_Q))
+        return fail("a q-list plan has no detector: MSFT_DETECTOR_UNIFORM_Q does not apply");
     const double tiles = (double)ceil_div(g->nx, XC) * (double)ceil_div(g->nz, ZB) * (double)g->ny;
     if (tiles * TILE_BYTES > 64.0 * 1024 * 1024 * 1024) return fail("voxel grid too large");
     return MSFT_OK;
@@ -68,6 +70,41 @@ void detector_qmap(double wavelength, double theta_max_deg, int32_t n, double* q
             qp[2] = -((k0 * s) / (r * (r + 1.0)));
         }
     }
+}
+
+// Uniform transverse-q grid: q_x(i) = (2i + 1 - N) q_max / N, q_max = k0 sin(theta_max);
+// q_z = sqrt(k0^2 - s) - k0 = -s / (sqrt(k0^2 - s) + k0), s = q_x^2 + q_y^2 (the
+// cancellation-free form); NaN where s >= k0^2.
+void uniform_qmap(double wavelength, double theta_max_deg, int32_t n, double* q, double* qx,
+                  double* qy)
+{
+    const double k0 = (2.0 * kPi) / wavelength;
+    const double qmax = k0 * std::sin((theta_max_deg * kPi) / 180.0);
+    const double kk = k0 * k0;
+    for (int32_t a = 0; a < n; ++a) {
+        const double v = ((double)(2 * a + 1 - n) * qmax) / (double)n;
+        qx[a] = v;
+        qy[a] = v;
+    }
+    for (int32_t j = 0; j < n; ++j)
+        for (int32_t i = 0; i < n; ++i) {
+            const double s = qx[i] * qx[i] + qy[j] * qy[j];
+            double* qp = q + 3 * ((int64_t)j * n + i);
+            qp[0] = qx[i];
+            qp[1] = qy[j];
+            qp[2] = s < kk ? -(s / (std::sqrt(kk - s) + k0)) : std::nan("");
+        }
+}
+
+SepDims make_sep_dims(int32_t n, int ny)
+{
+    SepDims s;
+    s.n = n;
+    s.npad = (int32_t)(ceil_div(n, BLOCK_PIX) * BLOCK_PIX);
+    s.nblk1 = ceil_div(n, BLOCK_PIX);
+    s.y_pad = (int32_t)(ceil_div(ny, XPAD) * XPAD);
+    s.nyc = (int32_t)ceil_div(ny, XC);
+    return s;
 }
 
 void voxel_centres(int32_t n, double d, double* c)

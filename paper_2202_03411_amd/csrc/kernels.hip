@@ -113,7 +113,8 @@ __global__ void twiddle_ty(float2* ty, int64_t total, int64_t npix, int ny, cons
     ty[idx] = v;
 }
 
-// Tz: [wt][zb][h][z 32][m] complex, exp(-i q_z z) (zero beyond nz).
+// Tz: [wt][zb][h][z 32][m] complex, exp(-i q_z z) (zero beyond nz, and for a
+// pixel whose q_z is not finite: no propagating wave reaches it).
 __global__ void twiddle_tz(float2* tz, int64_t total, int64_t npix, int nz, int nzb,
                            const double* q, const double* zs)
 {
@@ -128,7 +129,7 @@ __global__ void twiddle_tz(float2* tz, int64_t total, int64_t npix, int nz, int 
     const int64_t pix = slot_pixel(wt, h, m);
     const int z = zb * ZB + zl;
     float2 v = make_float2(0.0f, 0.0f);
-    if (pix < npix && z < nz) {
+    if (pix < npix && z < nz && isfinite(q[3 * pix + 2])) {
         double sn, cs;
         sincos(-(q[3 * pix + 2] * zs[z]), &sn, &cs);
         v = make_float2((float)cs, (float)sn);
@@ -160,6 +161,37 @@ int launch_twiddles(int precision, const Dims& d, const double* q_dev, const dou
     const int64_t ntz = d.nwt * d.nzb * 2 * ZB * 8;
     hipLaunchKernelGGL(twiddle_tz, dim3(grid_for(ntz, B)), dim3(B), 0, s, (float2*)tz, ntz,
                        d.npix, d.nz, d.nzb, q_dev, zs_dev);
+    return (int)hipGetLastError();
+}
+
+static void launch_txa(int precision, uint8_t* txa, int64_t nwt, int64_t npix, int nx, int nxc,
+                       const double* q, const double* xs, hipStream_t s)
+{
+    const int B = 256;
+    const int64_t total = nwt * nxc * (TILE_BYTES / 4);
+    if (precision == MSFT_FP32)
+        hipLaunchKernelGGL(twiddle_txa_f32, dim3(grid_for(total, B)), dim3(B), 0, s, (float*)txa,
+                           total, npix, nx, nxc, q, xs);
+    else
+        hipLaunchKernelGGL(twiddle_txa_bf16, dim3(grid_for(total, B)), dim3(B), 0, s, (__bf16*)txa,
+                           total, npix, nx, nxc, q, xs);
+}
+
+// Tables of the separable detector: A operands exp(-i q_x(i) x) of the first
+// stage and exp(-i q_y(j) y) of the second (the q arrays hold the one component
+// in slot 0), and Tz over the second stage's pixel order (i, j).
+int launch_sep_twiddles(int precision, const Dims& d, const SepDims& sd, const double* qcol,
+                        const double* qrow, const double* qk, const double* xs, const double* ys,
+                        const double* zs, uint8_t* txa1, uint8_t* txa2, float* tz, void* stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    const int B = 256;
+    launch_txa(precision, txa1, sd.nblk1 * WAVES, sd.n, d.nx, d.nxc, qcol, xs, s);
+    launch_txa(precision, txa2, sd.npad / WAVE_PIX, sd.n, d.ny, sd.nyc, qrow, ys, s);
+    const int64_t nwt2 = (int64_t)sd.n * (sd.npad / WAVE_PIX);
+    const int64_t ntz = nwt2 * d.nzb * 2 * ZB * 8;
+    hipLaunchKernelGGL(twiddle_tz, dim3(grid_for(ntz, B)), dim3(B), 0, s, (float2*)tz, ntz,
+                       (int64_t)sd.n * sd.npad, d.nz, d.nzb, qk, zs);
     return (int)hipGetLastError();
 }
 
@@ -309,16 +341,15 @@ int launch_scan(int precision, const ScanArgs& a, void* stream)
 // W tiles stream through a double-buffered LDS ring shared by the 8 waves.  The
 // order of every sum depends only on the plan, never on the launch.
 // ---------------------------------------------------------------------------
-// C = A . B for one W tile: the wave's A operand (registers) times the tile's
+// C += A . B for one W tile: the wave's A operand (registers) times the tile's
 // column `col` of lane half h (LDS row `row`), over the first `nx` x values.
 // FP32: 4 x values per 16-byte LDS slot, one v_mfma_f32_32x32x2_f32 per x.
 // BF16X3: 8 x values per slot, hi*hi + hi*lo + lo*hi on v_mfma_f32_32x32x16_bf16;
 // BF16 (plain): hi*hi only, from the same tables.
 template <int PREC, int NX>
-__device__ __forceinline__ f32x16 tile_mfma(const uint8_t* row, int col, const f32x4* Af,
+__device__ __forceinline__ f32x16 tile_mfma(f32x16 C, const uint8_t* row, int col, const f32x4* Af,
                                             const bf16x8* Ahi, const bf16x8* Alo)
 {
-    f32x16 C = {};
     const int sw = col & 15;
     if (PREC == MSFT_FP32) {
 #pragma unroll
@@ -346,11 +377,10 @@ __device__ __forceinline__ f32x16 tile_mfma(const uint8_t* row, int col, const f
 
 // The last, partial x chunk: the same products in steps of 8 x values.
 template <int PREC>
-__device__ __forceinline__ f32x16 tile_mfma_partial(const uint8_t* row, int col, int nx,
+__device__ __forceinline__ f32x16 tile_mfma_partial(f32x16 C, const uint8_t* row, int col, int nx,
                                                  const f32x4* Af, const bf16x8* Ahi,
                                                  const bf16x8* Alo)
 {
-    f32x16 C = {};
     const int sw = col & 15;
 #pragma unroll
     for (int s = 0; s < XC / 8; ++s) {
@@ -379,7 +409,28 @@ __device__ __forceinline__ f32x16 tile_mfma_partial(const uint8_t* row, int col,
     return C;
 }
 
+// The wave's A operand for one x chunk (one A tile of the table) into registers.
 template <int PREC>
+__device__ __forceinline__ void load_a(const uint8_t* ta, int lane, f32x4* Af, bf16x8* Ahi,
+                                       bf16x8* Alo)
+{
+    if (PREC == MSFT_FP32) {
+#pragma unroll
+        for (int g = 0; g < 16; ++g) Af[g] = ((const f32x4*)ta)[g * 64 + lane];
+    } else {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            Ahi[s] = ((const bf16x8*)ta)[s * 128 + lane];
+            if (PREC == MSFT_BF16X3) Alo[s] = ((const bf16x8*)ta)[s * 128 + 64 + lane];
+        }
+    }
+}
+
+// ROT = false is the second stage of the separable detector: the contraction
+// already summed over y, so a tile's product is added to G without a Ty factor.
+// A tile group (one detector column there) reads its own tiles and shares the A
+// operand of its position within the group.
+template <int PREC, bool ROT>
 __device__ __forceinline__ void fwd_block(const FwdArgs& a, int64_t block, uint8_t* lds)
 {
     const int tid = threadIdx.x;
@@ -387,7 +438,9 @@ __device__ __forceinline__ void fwd_block(const FwdArgs& a, int64_t block, uint8
     const int h = lane >> 5, col = lane & 31;
     const int64_t wt = block * WAVES + wave;
     const int64_t ntiles = (int64_t)a.nxc * a.nzb * a.ny;
-    const uint4* gw = (const uint4*)a.wtiles;
+    const int64_t group = a.group_blocks ? block / a.group_blocks : 0;
+    const int64_t wa = a.a_waves ? wt % a.a_waves : wt;
+    const uint4* gw = (const uint4*)(a.wtiles + (size_t)group * a.group_tiles * TILE_BYTES);
 
     // tile 0 -> LDS buffer 0
     {
@@ -407,17 +460,7 @@ __device__ __forceinline__ void fwd_block(const FwdArgs& a, int64_t block, uint8
         // A operand of this wave for the chunk
         f32x4 Af[16];
         bf16x8 Ahi[8], Alo[8];
-        const uint8_t* ta = a.txa + (size_t)(wt * a.nxc + xc) * TILE_BYTES;
-        if (PREC == MSFT_FP32) {
-#pragma unroll
-            for (int g = 0; g < 16; ++g) Af[g] = ((const f32x4*)ta)[g * 64 + lane];
-        } else {
-#pragma unroll
-            for (int s = 0; s < 8; ++s) {
-                Ahi[s] = ((const bf16x8*)ta)[s * 128 + lane];
-                if (PREC == MSFT_BF16X3) Alo[s] = ((const bf16x8*)ta)[s * 128 + 64 + lane];
-            }
-        }
+        load_a<PREC>(a.txa + (size_t)(wa * a.nxc + xc) * TILE_BYTES, lane, Af, Ahi, Alo);
         // Wait for the A operand here, once per chunk.  The memory counter is in
         // order, so without this the waits the compiler places for A inside the
         // tile loop would also wait for the next tile's prefetch, mid-chain.
@@ -433,12 +476,16 @@ __device__ __forceinline__ void fwd_block(const FwdArgs& a, int64_t block, uint8
                     n0 = gw[(t + 1) * (TILE_BYTES / 16) + tid];
                     n1 = gw[(t + 1) * (TILE_BYTES / 16) + 512 + tid];
                 }
-                const f32x4* typ = (const f32x4*)(a.ty + 2 * ((wt * a.ny + y) * WAVE_PIX + h * 8));
-                const f32x4 ty0 = typ[0], ty1 = typ[1], ty2 = typ[2], ty3 = typ[3];
+                f32x4 ty0 = {}, ty1 = {}, ty2 = {}, ty3 = {};
+                if (ROT) {
+                    const f32x4* typ = (const f32x4*)(a.ty + 2 * ((wt * a.ny + y) * WAVE_PIX + h * 8));
+                    ty0 = typ[0], ty1 = typ[1], ty2 = typ[2], ty3 = typ[3];
+                }
 
                 const uint8_t* row = lds + (t & 1) * TILE_BYTES + (h * ZB + col) * ROW_BYTES;
-                const f32x16 C = (xlen == XC) ? tile_mfma<PREC, XC>(row, col, Af, Ahi, Alo)
-                                              : tile_mfma_partial<PREC>(row, col, xlen, Af, Ahi, Alo);
+                const f32x16 zero = {};
+                const f32x16 C = (xlen == XC) ? tile_mfma<PREC, XC>(zero, row, col, Af, Ahi, Alo)
+                                              : tile_mfma_partial<PREC>(zero, row, col, xlen, Af, Ahi, Alo);
                 // G[m] += Ty[m] * C[m], slot m = 2j + u: C rows 4j + 2u (re), 4j + 2u + 1 (im)
                 const float tyv[16] = {ty0[0], ty0[1], ty0[2], ty0[3], ty1[0], ty1[1], ty1[2], ty1[3],
                                        ty2[0], ty2[1], ty2[2], ty2[3], ty3[0], ty3[1], ty3[2], ty3[3]};
@@ -446,9 +493,14 @@ __device__ __forceinline__ void fwd_block(const FwdArgs& a, int64_t block, uint8
                 for (int m = 0; m < 8; ++m) {
                     const int r = 4 * (m >> 1) + 2 * (m & 1);
                     const float cr = C[r], ci = C[r + 1];
-                    const float tr = tyv[2 * m], ti = tyv[2 * m + 1];
-                    G[2 * m] += tr * cr - ti * ci;
-                    G[2 * m + 1] += tr * ci + ti * cr;
+                    if (ROT) {
+                        const float tr = tyv[2 * m], ti = tyv[2 * m + 1];
+                        G[2 * m] += tr * cr - ti * ci;
+                        G[2 * m + 1] += tr * ci + ti * cr;
+                    } else {
+                        G[2 * m] += cr;
+                        G[2 * m + 1] += ci;
+                    }
                 }
                 if (has_next) {
                     uint4* nb = (uint4*)(lds + ((t + 1) & 1) * TILE_BYTES);
@@ -488,20 +540,27 @@ __device__ __forceinline__ void fwd_block(const FwdArgs& a, int64_t block, uint8
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
             const int64_t pix = slot_pixel(wt, h, m);
-            if (pix < a.npix) {
+            int64_t out = pix;
+            bool valid = pix < a.npix;
+            if (a.out_n) {   // kernel pixel (i, j) of the separable detector -> p = j N + i
+                const int64_t i = pix / a.out_npad, j = pix - i * a.out_npad;
+                valid = valid && j < a.out_n;
+                out = j * a.out_n + i;
+            }
+            if (valid) {
                 const float re = acc[2 * m], im = acc[2 * m + 1];
-                a.intensity[pix] = re * re + im * im;
-                if (a.amplitude) ((float2*)a.amplitude)[pix] = make_float2(re, im);
+                a.intensity[out] = re * re + im * im;
+                if (a.amplitude) ((float2*)a.amplitude)[out] = make_float2(re, im);
             }
         }
     }
 }
 
-template <int PREC>
+template <int PREC, bool ROT>
 __global__ __launch_bounds__(512) void fwd_kernel(FwdArgs a, int64_t block_begin)
 {
     __shared__ __attribute__((aligned(16))) uint8_t lds[2 * TILE_BYTES];
-    fwd_block<PREC>(a, block_begin + blockIdx.x, lds);
+    fwd_block<PREC, ROT>(a, block_begin + blockIdx.x, lds);
 }
 
 // Persistent form: workgroups pull (request, pixel block) items from a counter
@@ -520,26 +579,33 @@ __global__ __launch_bounds__(512) void fwd_batch_kernel(BatchArgs b)
         if (it >= nitems) break;
         int r = 0;
         while (r + 1 < b.nreq && b.item_begin[r + 1] <= it) ++r;
-        fwd_block<PREC>(b.req[r], (int64_t)b.block_begin[r] + (it - b.item_begin[r]), lds);
+        fwd_block<PREC, true>(b.req[r], (int64_t)b.block_begin[r] + (it - b.item_begin[r]), lds);
     }
 }
 
 __global__ void zero_counter(int32_t* c) { *c = 0; }
 
-int launch_forward(int precision, const FwdArgs& a, int64_t block_begin, int64_t nblocks,
-                   void* stream)
+template <bool ROT>
+static void launch_fwd(int precision, const FwdArgs& a, int64_t block_begin, int64_t nblocks,
+                       hipStream_t s)
 {
-    hipStream_t s = (hipStream_t)stream;
-    if (nblocks <= 0) return 0;
     if (precision == MSFT_FP32)
-        hipLaunchKernelGGL(fwd_kernel<MSFT_FP32>, dim3((unsigned)nblocks), dim3(512), 0, s, a,
+        hipLaunchKernelGGL((fwd_kernel<MSFT_FP32, ROT>), dim3((unsigned)nblocks), dim3(512), 0, s, a,
                            block_begin);
     else if (precision == MSFT_BF16X3)
-        hipLaunchKernelGGL(fwd_kernel<MSFT_BF16X3>, dim3((unsigned)nblocks), dim3(512), 0, s, a,
+        hipLaunchKernelGGL((fwd_kernel<MSFT_BF16X3, ROT>), dim3((unsigned)nblocks), dim3(512), 0, s, a,
                            block_begin);
     else
-        hipLaunchKernelGGL(fwd_kernel<MSFT_BF16>, dim3((unsigned)nblocks), dim3(512), 0, s, a,
+        hipLaunchKernelGGL((fwd_kernel<MSFT_BF16, ROT>), dim3((unsigned)nblocks), dim3(512), 0, s, a,
                            block_begin);
+}
+
+int launch_forward(int precision, const FwdArgs& a, int64_t block_begin, int64_t nblocks,
+                   bool rotate, void* stream)
+{
+    if (nblocks <= 0) return 0;
+    if (rotate) launch_fwd<true>(precision, a, block_begin, nblocks, (hipStream_t)stream);
+    else launch_fwd<false>(precision, a, block_begin, nblocks, (hipStream_t)stream);
     return (int)hipGetLastError();
 }
 
@@ -554,6 +620,66 @@ int launch_forward_batch(int precision, const BatchArgs& b, int32_t grid, void* 
         hipLaunchKernelGGL(fwd_batch_kernel<MSFT_BF16X3>, dim3(grid), dim3(512), 0, s, b);
     else
         hipLaunchKernelGGL(fwd_batch_kernel<MSFT_BF16>, dim3(grid), dim3(512), 0, s, b);
+    return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// First stage of the separable detector (Sec. 3, Blocks 6-7 with q_x a function
+// of the column i alone):  H[i][y][z] = sum_x exp(-i q_x(i) x) w(x, y, z).
+// Workgroup (block of 128 columns i, y, z block): the x chunks are summed in the
+// MFMA accumulator, then each lane stores its 8 columns' values into the H tiles
+// the second stage streams, tile (i, y chunk, z block) in the W tile layout with
+// y in place of x.  Workgroups with y beyond ny write the zero padding rows.
+// ---------------------------------------------------------------------------
+template <int PREC>
+__global__ __launch_bounds__(512) void sep_stage1_kernel(Stage1Args a)
+{
+    __shared__ __attribute__((aligned(16))) uint8_t lds[TILE_BYTES];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int h = lane >> 5, col = lane & 31;
+    const int y = blockIdx.y, zb = blockIdx.z;
+    const int64_t wt = (int64_t)blockIdx.x * WAVES + wave;
+    f32x16 C = {};
+    if (y < a.ny) {
+        for (int xc = 0; xc < a.nxc; ++xc) {
+            const uint4* gw = (const uint4*)(a.wtiles + ((size_t)(xc * a.nzb + zb) * a.ny + y) * TILE_BYTES);
+            const uint4 r0 = gw[tid], r1 = gw[tid + 512];
+            f32x4 Af[16];
+            bf16x8 Ahi[8], Alo[8];
+            load_a<PREC>(a.txa + (size_t)(wt * a.nxc + xc) * TILE_BYTES, lane, Af, Ahi, Alo);
+            __syncthreads();   // every wave is done with the previous chunk's tile
+            ((uint4*)lds)[tid] = r0;
+            ((uint4*)lds)[tid + 512] = r1;
+            __syncthreads();
+            const int xlen = min(XC, a.x_pad - xc * XC);
+            const uint8_t* row = lds + (h * ZB + col) * ROW_BYTES;
+            C = (xlen == XC) ? tile_mfma<PREC, XC>(C, row, col, Af, Ahi, Alo)
+                             : tile_mfma_partial<PREC>(C, row, col, xlen, Af, Ahi, Alo);
+        }
+    }
+    const int yc = y / XC, yl = y - yc * XC;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        const int64_t i = slot_pixel(wt, h, m);
+        if (i < a.n) {
+            const int r = 4 * (m >> 1) + 2 * (m & 1);
+            uint8_t* tile = a.htiles + ((size_t)(i * a.nyc + yc) * a.nzb + zb) * TILE_BYTES;
+            store_w<PREC>(tile, yl, col, C[r], C[r + 1]);
+        }
+    }
+}
+
+int launch_sep_stage1(int precision, const Stage1Args& a, int64_t nblk, void* stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    const dim3 grid((unsigned)nblk, (unsigned)(a.nyc * XC), (unsigned)a.nzb);
+    if (precision == MSFT_FP32)
+        hipLaunchKernelGGL(sep_stage1_kernel<MSFT_FP32>, grid, dim3(512), 0, s, a);
+    else if (precision == MSFT_BF16X3)
+        hipLaunchKernelGGL(sep_stage1_kernel<MSFT_BF16X3>, grid, dim3(512), 0, s, a);
+    else
+        hipLaunchKernelGGL(sep_stage1_kernel<MSFT_BF16>, grid, dim3(512), 0, s, a);
     return (int)hipGetLastError();
 }
 

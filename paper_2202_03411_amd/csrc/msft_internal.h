@@ -45,6 +45,11 @@ struct Geometry {
 msft_status validate_geometry(const msft_geometry* g, bool qlist, std::string* why);
 // Pixel -> q of the flat detector, p = j * N + i.
 void detector_qmap(double wavelength, double theta_max_deg, int32_t n, double* q);
+// Pixel -> q of the uniform transverse-q detector, p = j * N + i; q_z is NaN for a
+// pixel beyond the Ewald sphere's rim (q_x^2 + q_y^2 >= k0^2).  qx[N], qy[N] get
+// the per-column and per-row components.
+void uniform_qmap(double wavelength, double theta_max_deg, int32_t n, double* q, double* qx,
+                  double* qy);
 // Voxel centres (2a + 1 - n) d / 2.
 void voxel_centres(int32_t n, double d, double* c);
 // max_p |q_axis| * pitch over the three axes; returns false (and the axis) if > pi.
@@ -72,6 +77,34 @@ struct FwdArgs {
     float* amplitude;       // [npix] complex or null
     int64_t npix;
     int32_t ny, nxc, nzb, x_pad;
+    // Second stage of the separable detector (all zero otherwise): blocks
+    // [g * group_blocks, (g + 1) * group_blocks) read tile group g at
+    // wtiles + g * group_tiles tiles; wave wt uses A tile row wt % a_waves;
+    // kernel pixel i * out_npad + j is written to j * out_n + i when j < out_n.
+    int32_t group_blocks, group_tiles, a_waves, out_n, out_npad;
+};
+
+// Separable (uniform transverse q) detector: q_x depends on the column i only,
+// q_y on the row j only.  Stage 1 forms H = Tx W per column (N x ny x nz); stage 2
+// contracts H over y against Ty per row with the z phase behind it.
+struct SepDims {
+    int32_t n = 0;      // detector side N
+    int32_t npad = 0;   // N rounded up to BLOCK_PIX: rows j per column in stage 2
+    int64_t nblk1 = 0;  // stage-1 blocks of BLOCK_PIX columns
+    int32_t nyc = 0;    // y chunks of 64 in stage 2
+    int32_t y_pad = 0;  // ny padded to XPAD
+    size_t txa1_bytes(int nxc) const { return (size_t)nblk1 * WAVES * nxc * TILE_BYTES; }
+    size_t txa2_bytes() const { return (size_t)(npad / WAVE_PIX) * nyc * TILE_BYTES; }
+    size_t h_bytes(int nzb) const { return (size_t)n * nyc * nzb * TILE_BYTES; }
+    size_t tz_bytes(int nzb) const { return (size_t)n * (npad / WAVE_PIX) * nzb * 2 * ZB * 8 * 8; }
+};
+SepDims make_sep_dims(int32_t n, int ny);
+
+struct Stage1Args {
+    const uint8_t* wtiles;  // W tiles of the scan
+    const uint8_t* txa;     // A tiles [column wave][xc]
+    uint8_t* htiles;        // H tiles [i][y chunk][z block]
+    int32_t n, ny, nxc, nzb, x_pad, nyc;
 };
 
 // Arguments of the column scan producing the W tiles.
@@ -138,7 +171,11 @@ int launch_twiddles(int precision, const Dims& d, const double* q_dev, const dou
                     float* tz, void* stream);
 int launch_scan(int precision, const ScanArgs& a, void* stream);
 int launch_forward(int precision, const FwdArgs& a, int64_t block_begin, int64_t nblocks,
-                   void* stream);
+                   bool rotate, void* stream);
+int launch_sep_twiddles(int precision, const Dims& d, const SepDims& sd, const double* qcol,
+                        const double* qrow, const double* qk, const double* xs, const double* ys,
+                        const double* zs, uint8_t* txa1, uint8_t* txa2, float* tz, void* stream);
+int launch_sep_stage1(int precision, const Stage1Args& a, int64_t nblk, void* stream);
 int launch_forward_batch(int precision, const BatchArgs& b, int32_t grid, void* stream);
 
 }  // namespace msft
@@ -154,9 +191,12 @@ struct msft_plan_s {
     double* xs_dev = nullptr;
     double* ys_dev = nullptr;
     double* zs_dev = nullptr;
-    uint8_t* txa = nullptr;
+    uint8_t* txa = nullptr;       // separable detector: stage-1 A operand
     float* ty = nullptr;
-    float* tz = nullptr;
+    float* tz = nullptr;          // separable detector: over stage 2's pixel order
+    uint8_t* txa2 = nullptr;      // separable detector: stage-2 A operand
+    bool separable = false;
+    msft::SepDims sep;
     size_t resident_bytes = 0;
     size_t workspace_bytes = 0;
 };

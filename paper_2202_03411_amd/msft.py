@@ -21,6 +21,8 @@ MSFT_ERR_NOMEM, MSFT_ERR_DEVICE, MSFT_ERR_BUSY, MSFT_ERR_UNSUPPORTED = 3, 4, 5, 
 MSFT_FP32, MSFT_BF16X3, MSFT_BF16 = 0, 1, 2
 MSFT_STRENGTH_MSFT, MSFT_STRENGTH_BORN, MSFT_STRENGTH_DENSITY = 0, 1, 2
 MSFT_ALLOW_ALIAS = 1
+MSFT_DETECTOR_UNIFORM_Q = 2
+DETECTORS = {"flat": 0, "uniform_q": MSFT_DETECTOR_UNIFORM_Q}
 
 PRECISIONS = {"fp32": MSFT_FP32, "bf16x3": MSFT_BF16X3, "bf16": MSFT_BF16}
 STRENGTHS = {"msft": MSFT_STRENGTH_MSFT, "born": MSFT_STRENGTH_BORN, "density": MSFT_STRENGTH_DENSITY}
@@ -132,8 +134,9 @@ def _stream(stream):
 
 
 def make_geometry(wavelength, theta_max_deg, det_n, grid, pitch, precision="fp32",
-                  strength="msft", allow_alias=False) -> msft_geometry:
-    """Fill an msft_geometry from Python values (grid = (nx, ny, nz), pitch = (dx, dy, dz))."""
+                  strength="msft", allow_alias=False, detector="flat") -> msft_geometry:
+    """Fill an msft_geometry from Python values (grid = (nx, ny, nz), pitch = (dx, dy, dz));
+    detector is "flat" or "uniform_q" (MSFT_DETECTOR_UNIFORM_Q)."""
     g = msft_geometry()
     g.struct_size = ctypes.sizeof(msft_geometry)
     g.wavelength = float(wavelength)
@@ -143,7 +146,7 @@ def make_geometry(wavelength, theta_max_deg, det_n, grid, pitch, precision="fp32
     g.dx, g.dy, g.dz = (float(v) for v in pitch)
     g.precision = PRECISIONS.get(precision, precision)
     g.strength = STRENGTHS.get(strength, strength)
-    g.flags = MSFT_ALLOW_ALIAS if allow_alias else 0
+    g.flags = (MSFT_ALLOW_ALIAS if allow_alias else 0) | DETECTORS[detector]
     return g
 
 
@@ -250,9 +253,9 @@ class Plan:
     """Owning wrapper of an msft plan; simulate() allocates outputs with torch."""
 
     def __init__(self, wavelength, theta_max_deg, det_n, grid, pitch, precision="fp32",
-                 strength="msft", device=0, allow_alias=False, q=None):
+                 strength="msft", device=0, allow_alias=False, q=None, detector="flat"):
         self.geometry = make_geometry(wavelength, theta_max_deg, det_n, grid, pitch, precision,
-                                      strength, allow_alias)
+                                      strength, allow_alias, detector)
         self.grid = tuple(int(v) for v in grid)
         self.device_index = int(device)
         if q is None:

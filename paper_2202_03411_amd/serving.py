@@ -127,14 +127,19 @@ class Scheduler:
         return launched
 
 
-def run_stream(scheduler: Scheduler, requests, poll_sleep: float = 2e-4):
-    """Replay requests at their arrival times (seconds from start) through a scheduler."""
+def run_stream(scheduler: Scheduler, requests, poll_sleep: float = 2e-4, progress=None):
+    """Replay requests at their arrival times (seconds from start) through a scheduler.
+    `progress(done, total)` is called whenever another 512 requests have completed."""
     pending = sorted(requests, key=lambda r: r.arrival)
     t0 = scheduler.clock()
     for r in pending:
         r.arrival += t0
     i = 0
+    reported = 0
     while i < len(pending) or not scheduler.idle():
+        if progress is not None and len(scheduler.completed) >= reported + 512:
+            reported = len(scheduler.completed) // 512 * 512
+            progress(reported, len(pending))
         now = scheduler.clock()
         while i < len(pending) and pending[i].arrival <= now:
             scheduler.submit(pending[i])
@@ -338,12 +343,13 @@ def make_requests(pool, count, seed, rate=None, wavelength=45.0, theta=60.0,
     return out
 
 
-def serve(torch, msft, plans, requests, batched=True, hbm_budget=16 << 30, slots=3, max_batch=24):
+def serve(torch, msft, plans, requests, batched=True, hbm_budget=16 << 30, slots=3, max_batch=24,
+          progress=None):
     """Run a request list through the server; returns (summary, requests)."""
     ex = GpuExecutor(plans, torch, nstreams=slots, batched=batched)
     sched = Scheduler(ex, hbm_budget, max_inflight=slots if batched else 1 << 30,
                       max_batch=max_batch if batched else 1)
-    t0 = run_stream(sched, requests)
+    t0 = run_stream(sched, requests, progress=progress)
     torch.cuda.synchronize()
     t_end = max(r.done for r in sched.completed) if sched.completed else t0
     s = summarize(sched.completed, t0, t_end)
@@ -352,35 +358,44 @@ def serve(torch, msft, plans, requests, batched=True, hbm_budget=16 << 30, slots
     return s, sched.completed
 
 
-def service_estimate_s(key, tflops):
-    """Rough contraction time of one request at a given algorithmic TFLOP/s."""
-    _, _, det, grid, _, _ = key
-    n = grid[0]
-    return 8.0 * det * det * n ** 3 / (tflops * 1e12)
-
-
-def benchmark(count=96, precision="fp32", load=0.8, seed=20220205, device=0):
-    """Offline (all requests at t = 0) and Poisson (offered load `load` of the
-    estimated capacity) streams, batched against one pattern per launch."""
+def benchmark(count=96, precision="fp32", loads=(0.8,), seed=20220205, device=0, plain=True,
+              log=None):
+    """The mixed-size stream served three ways: offline (all requests at t = 0),
+    whose batched throughput is the measured capacity, then Poisson arrivals at
+    each offered load rho * capacity.  Every stream runs batched and, if `plain`,
+    as one pattern per launch on one stream."""
     import torch
 
     from . import msft
     pool = ShapePool(torch, seed=seed)
     plans = PlanCache(msft, precision, device)
-    tf = 126.0 if precision == "fp32" else 440.0
     probe = make_requests(pool, count, seed, None)
     for r in probe:
         plans.get(r.key)          # plans and twiddles resident before the clock starts
-    mean_s = sum(service_estimate_s(r.key, tf) for r in probe) / len(probe)
-    rate = load / mean_s
     out = {"precision": precision, "requests": count, "resident_plans": len(plans.plans),
-           "resident_bytes": plans.resident_bytes(), "offered_rate_per_s": rate,
-           "mean_service_estimate_ms": 1e3 * mean_s}
-    for name, r8 in (("offline", None), ("poisson", rate)):
-        for batched in (True, False):
-            reqs = make_requests(pool, count, seed, r8)
-            s, _ = serve(torch, msft, plans, reqs, batched=batched)
-            out[f"{name}_{s['mode']}"] = s
+           "resident_bytes": plans.resident_bytes()}
+
+    def run(name, rate, batched):
+        reqs = make_requests(pool, count, seed, rate)
+        mode = "batched" if batched else "plain"
+        prog = (lambda d, n: log(f"{name} {mode}: {d}/{n} done")) if log else None
+        s, _ = serve(torch, msft, plans, reqs, batched=batched, progress=prog)
+        out[f"{name}_{s['mode']}"] = s
+        if log:
+            log(f"{name} {mode}: {s['patterns_per_s']:.2f} patterns/s, p50 {s['p50_ms']:.1f} ms, "
+                f"p99 {s['p99_ms']:.1f} ms")
+        return s
+
+    cap = run("offline", None, True)["patterns_per_s"]
+    out["capacity_patterns_per_s"] = cap
+    if plain:
+        run("offline", None, False)
+    for rho in loads:
+        rate = rho * cap
+        out[f"offered_rate_rho{rho:g}_per_s"] = rate
+        run(f"poisson_rho{rho:g}", rate, True)
+        if plain:
+            run(f"poisson_rho{rho:g}", rate, False)
     plans.close()
     return out
 
@@ -388,9 +403,14 @@ def benchmark(count=96, precision="fp32", load=0.8, seed=20220205, device=0):
 if __name__ == "__main__":
     import argparse
     import json
+    import sys
     ap = argparse.ArgumentParser(description="serve a seeded stream of MSFT requests")
     ap.add_argument("--requests", type=int, default=96)
     ap.add_argument("--precision", choices=["fp32", "bf16x3"], default="fp32")
-    ap.add_argument("--load", type=float, default=0.8)
+    ap.add_argument("--loads", type=float, nargs="+", default=[0.8],
+                    help="offered loads as fractions of the measured batched capacity")
+    ap.add_argument("--no-plain", action="store_true", help="skip the one-pattern-per-launch runs")
     args = ap.parse_args()
-    print(json.dumps(benchmark(args.requests, args.precision, args.load)))
+    res = benchmark(args.requests, args.precision, tuple(args.loads), plain=not args.no_plain,
+                    log=lambda m: print(f"[serving] {m}", file=sys.stderr, flush=True))
+    print(json.dumps(res))

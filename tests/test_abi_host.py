@@ -40,6 +40,32 @@ def test_qmap_bit_exact(lam, theta, n):
         msft.msft_plan_destroy(h)
 
 
+@pytest.mark.parametrize("lam,theta,n", [(45.0, 60.0, 64), (13.5, 80.0, 33), (40.0, 30.0, 1),
+                                         (45.0, 44.0, 128)])
+def test_uniform_qmap_bit_exact(lam, theta, n):
+    g = msft.make_geometry(lam, theta, n, (4, 4, 4), (1e-3, 1e-3, 1e-3), detector="uniform_q")
+    h = msft.msft_plan(g, -1)
+    try:
+        assert np.array_equal(msft.msft_plan_qmap(h), oracle.qmap_uniform(lam, theta, n),
+                              equal_nan=True)
+    finally:
+        msft.msft_plan_destroy(h)
+
+
+def test_uniform_plan_sizes():
+    # 150 x 70 x 40 grid, N = 23: W tiles 3 x-chunks * 2 z blocks * 70 y; H tiles
+    # 23 columns * 2 y chunks * 2 z blocks; adjoint as for any plan of 529 pixels
+    g = msft.make_geometry(45.0, 60.0, 23, (150, 70, 40), (3.0, 3.0, 3.0), detector="uniform_q")
+    h = msft.msft_plan(g, -1)
+    try:
+        npix, ws, _ = msft.msft_plan_query(h)
+        assert npix == 529
+        fwd = 3 * 2 * 70 * 16384 + 23 * 2 * 2 * 16384
+        assert ws >= fwd
+    finally:
+        msft.msft_plan_destroy(h)
+
+
 def test_grid_bit_exact():
     g = msft.make_geometry(45.0, 30.0, 8, (7, 10, 13), (4.7, 3.3, 2.9))
     h = msft.msft_plan(g, -1)
@@ -90,6 +116,9 @@ def test_validation_errors():
     g = geo()
     g.flags = 0x80
     assert _status(g) == msft.MSFT_ERR_INVALID
+    g = geo()
+    g.flags = msft.MSFT_DETECTOR_UNIFORM_Q
+    assert _status(g) == msft.MSFT_OK
     assert "struct_size" in msft.msft_last_error() or True
 
 

@@ -73,6 +73,42 @@ def test_qmap_corner_angle():
     assert 39.1 < math.degrees(math.acos(cos_t.min())) < 39.3
 
 
+# ---------------------------------------------------------------------------
+# uniform transverse-q virtual detector (Sec. 3, Blocks 3 and 6; reading in the
+# header of oracle_qmap_uniform)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,theta", [(16, 30.0), (17, 60.0), (33, 80.0), (5, 10.0)])
+def test_uniform_qmap_grid_and_ewald(n, theta):
+    q = oracle.qmap_uniform(LAM, theta, n).reshape(n, n, 3)  # [j][i]
+    qmax = K0 * math.sin(math.radians(theta))
+    # q_x depends on the column only, q_y on the row only, on a uniform grid of step
+    # 2 qmax / N whose edge-pixel edge is at qmax (the theta_max direction on an axis)
+    assert np.all(q[:, :, 0] == q[0:1, :, 0]) and np.all(q[:, :, 1] == q[:, 0:1, 1])
+    qx = q[0, :, 0]
+    assert np.allclose(np.diff(qx), 2.0 * qmax / n, rtol=1e-12, atol=0)
+    assert math.isclose(qx[-1] + qmax / n, qmax, rel_tol=1e-14)
+    assert math.isclose(math.degrees(math.asin((qx[-1] + qmax / n) / K0)), theta, rel_tol=1e-12)
+    assert np.array_equal(q[0, ::-1, 0], -qx) and np.array_equal(q[::-1, 0, 1], -q[:, 0, 1])
+    # elastic where an outgoing wave exists; NaN exactly where q_x^2 + q_y^2 >= k0^2
+    s = q[..., 0] ** 2 + q[..., 1] ** 2
+    ok = ~np.isnan(q[..., 2])
+    assert np.array_equal(ok, s < K0 * K0)
+    kout = q[ok] + np.array([0.0, 0.0, K0])
+    assert np.allclose(np.linalg.norm(kout, axis=1), K0, rtol=1e-14, atol=0)
+    assert np.all(q[ok][:, 2] <= 0.0) and np.all(kout[:, 2] >= 0.0)
+
+
+def test_uniform_qmap_rim():
+    # all pixels propagate for sin(theta_max) < 1/sqrt(2); beyond, the corners do not
+    assert not np.isnan(oracle.qmap_uniform(LAM, 44.0, 64)[:, 2]).any()
+    q = oracle.qmap_uniform(LAM, 60.0, 64).reshape(64, 64, 3)
+    assert np.isnan(q[0, 0, 2]) and np.isnan(q[-1, -1, 2]) and not np.isnan(q[32, 0, 2])
+    # at odd N the centre pixel looks along the beam
+    qc = oracle.qmap_uniform(LAM, 60.0, 65).reshape(65, 65, 3)[32, 32]
+    assert np.all(qc == 0.0)
+
+
 def test_grid_centred():
     for n, d in [(1, 3.0), (8, 2.5), (9, 4.7)]:
         c = oracle.grid(n, d)
