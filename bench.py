@@ -195,6 +195,11 @@ def time_uniform(msft, torch, wl, d, b, prec, steps, warmup):
     flops = 8.0 * n * nx * ny * nz + 8.0 * n * n * ny * nz   # stage 1 + stage 2
     ms = sum(r["step_ms"]) / len(r["step_ms"])
     cms = sum(r["contract_ms"]) / len(r["contract_ms"])
+    bms = None
+    if prec == "fp32":
+        with msft.Plan(wl.wavelength, wl.theta_max_deg, wl.det_n, wl.grid, wl.pitch, prec, "msft",
+                       detector="uniform_q") as plan:
+            bms = time_backward(msft, torch, plan, d, b, max(3, steps), 1)
     pix = inputs.random_pixels(n, 256, seed=83)
     q = oracle.qmap_uniform(wl.wavelength, wl.theta_max_deg, n)[pix]
     ok = ~np.isnan(q[:, 2])
@@ -207,6 +212,7 @@ def time_uniform(msft, torch, wl, d, b, prec, steps, warmup):
             "contract_ms": cms, "separable_flops": flops,
             "contract_tflops": flops / (cms * 1e-3) / 1e12,
             "direct_equivalent_terms_per_s": n * n * nx * ny * nz / (ms * 1e-3),
+            "backward_ms": bms,
             "error_vs_fp64_oracle": {"rel_l2_intensity": err, "pixels": int(ok.sum())}}
 
 
@@ -316,7 +322,8 @@ def main():
         prec = args.only.split("_", 1)[1]
         u = time_uniform(msft, torch, wl, d, b, prec, args.steps, args.warmup)
         print(f"[bench] uniform-q {prec}: {u['ms_per_step']:.3f} ms/pattern, "
-              f"{u['contract_tflops']:.1f} TFLOP/s", file=sys.stderr, flush=True)
+              f"{u['contract_tflops']:.1f} TFLOP/s, backward {u['backward_ms']} ms",
+              file=sys.stderr, flush=True)
         print(json.dumps({"metric": "MSFT patterns/s, uniform-q detector, 128³ grid, 512²",
                           "value": u["patterns_per_s"], "unit": "patterns/s", "n_gpus": 1,
                           "steps": args.steps, "warmup": args.warmup, "dtype": "f32",

@@ -91,8 +91,10 @@ typedef enum {
  * A = sum_z exp(-i q_z z) sum_y exp(-i q_y(j) y) H(i, y, z) (a contraction over y
  * with the z phase behind it): about N (nx + N) ny nz complex products instead of
  * N^2 nx ny nz.  Same pixel order p = j * N + i and the same sum as the flat form
- * for these q.  Not accepted by msft_plan_qlist or msft_simulate_batch;
- * msft_backward uses the general adjoint.
+ * for these q.  Not accepted by msft_plan_qlist or msft_simulate_batch.
+ * msft_backward runs the same two contractions transposed: with h = g conj(A),
+ * K(i, y, z) = sum_j exp(-i q_y(j) y) h(i, j) exp(-i q_z(i, j) z), then
+ * R = sum_i exp(-i q_x(i) x) K, then the column walk of the general adjoint.
  */
 #define MSFT_DETECTOR_UNIFORM_Q 2u
 

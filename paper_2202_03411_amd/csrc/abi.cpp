@@ -62,11 +62,12 @@ void free_device(msft_plan_s* p)
 {
     if (p->device < 0) return;
     DeviceScope ds(p->device);
-    void* ptrs[] = {p->q_dev, p->xs_dev, p->ys_dev, p->zs_dev, p->txa, p->ty, p->tz, p->txa2};
+    void* ptrs[] = {p->q_dev, p->xs_dev, p->ys_dev, p->zs_dev, p->txa, p->ty, p->tz, p->txa2,
+                    p->txT, p->tyT};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     p->q_dev = p->xs_dev = p->ys_dev = p->zs_dev = nullptr;
-    p->txa = p->txa2 = nullptr;
+    p->txa = p->txa2 = p->txT = p->tyT = nullptr;
     p->ty = p->tz = nullptr;
 }
 
@@ -113,6 +114,8 @@ msft_status build_device_tables(msft_plan_s* p)
         MSFT_TRY(dev_alloc(&p->txa, p->sep.txa1_bytes(d.nxc), &total), "hipMalloc Tx");
         MSFT_TRY(dev_alloc(&p->txa2, p->sep.txa2_bytes(), &total), "hipMalloc Ty");
         MSFT_TRY(dev_alloc(&p->tz, p->sep.tz_bytes(d.nzb), &total), "hipMalloc Tz");
+        MSFT_TRY(dev_alloc(&p->txT, p->sep.txT_bytes(d.nx), &total), "hipMalloc adjoint Tx");
+        MSFT_TRY(dev_alloc(&p->tyT, p->sep.tyT_bytes(d.ny), &total), "hipMalloc adjoint Ty");
     } else {
         MSFT_TRY(dev_alloc(&p->txa, d.txa_bytes(), &total), "hipMalloc Tx");
         MSFT_TRY(dev_alloc(&p->ty, d.ty_bytes(), &total), "hipMalloc Ty");
@@ -131,31 +134,36 @@ msft_status build_device_tables(msft_plan_s* p)
         const SepDims& sd = p->sep;
         std::vector<double> qcol(3 * (size_t)sd.n, 0.0), qrow(3 * (size_t)sd.n, 0.0);
         std::vector<double> qk(3 * (size_t)sd.n * sd.npad, std::nan(""));
+        std::vector<double> qxv(sd.n), qyv(sd.n), xq3(3 * (size_t)d.nx, 0.0), yq3(3 * (size_t)d.ny, 0.0);
         for (int32_t a = 0; a < sd.n; ++a) {
-            qcol[3 * a] = geo.q[3 * (size_t)a];                 // pixel (i = a, j = 0)
-            qrow[3 * a] = geo.q[3 * ((size_t)a * sd.n) + 1];    // pixel (i = 0, j = a)
+            qcol[3 * a] = qxv[a] = geo.q[3 * (size_t)a];              // pixel (i = a, j = 0)
+            qrow[3 * a] = qyv[a] = geo.q[3 * ((size_t)a * sd.n) + 1]; // pixel (i = 0, j = a)
         }
+        for (int a = 0; a < d.nx; ++a) xq3[3 * a] = geo.xs[a];
+        for (int a = 0; a < d.ny; ++a) yq3[3 * a] = geo.ys[a];
         for (int32_t i = 0; i < sd.n; ++i)
             for (int32_t j = 0; j < sd.n; ++j)
                 qk[3 * ((size_t)i * sd.npad + j) + 2] = geo.q[3 * ((size_t)j * sd.n + i) + 2];
-        double *qcol_dev = nullptr, *qrow_dev = nullptr, *qk_dev = nullptr;
+        std::vector<const std::vector<double>*> host = {&qcol, &qrow, &qk, &qxv, &qyv, &xq3, &yq3};
+        std::vector<double*> dev(host.size(), nullptr);
         size_t scratch = 0;
-        e = dev_alloc(&qcol_dev, sizeof(double) * qcol.size(), &scratch);
-        if (e == hipSuccess) e = dev_alloc(&qrow_dev, sizeof(double) * qrow.size(), &scratch);
-        if (e == hipSuccess) e = dev_alloc(&qk_dev, sizeof(double) * qk.size(), &scratch);
+        e = hipSuccess;
+        for (size_t k = 0; k < host.size() && e == hipSuccess; ++k) {
+            e = dev_alloc(&dev[k], sizeof(double) * host[k]->size(), &scratch);
+            if (e == hipSuccess)
+                e = hipMemcpy(dev[k], host[k]->data(), sizeof(double) * host[k]->size(),
+                              hipMemcpyHostToDevice);
+        }
         if (e == hipSuccess)
-            e = hipMemcpy(qcol_dev, qcol.data(), sizeof(double) * qcol.size(), hipMemcpyHostToDevice);
-        if (e == hipSuccess)
-            e = hipMemcpy(qrow_dev, qrow.data(), sizeof(double) * qrow.size(), hipMemcpyHostToDevice);
-        if (e == hipSuccess)
-            e = hipMemcpy(qk_dev, qk.data(), sizeof(double) * qk.size(), hipMemcpyHostToDevice);
-        if (e == hipSuccess)
-            e = (hipError_t)launch_sep_twiddles(p->geo.g.precision, d, sd, qcol_dev, qrow_dev, qk_dev,
+            e = (hipError_t)launch_sep_twiddles(p->geo.g.precision, d, sd, dev[0], dev[1], dev[2],
                                                 p->xs_dev, p->ys_dev, p->zs_dev, p->txa, p->txa2,
                                                 p->tz, s);
+        if (e == hipSuccess)
+            e = (hipError_t)launch_sep_adj_tables(sd, d.nx, d.ny, dev[5], dev[3], dev[6], dev[4],
+                                                  p->txT, p->tyT, s);
         hipError_t e2 = hipStreamSynchronize(s);
         if (e == hipSuccess) e = e2;
-        for (double* t : {qcol_dev, qrow_dev, qk_dev})
+        for (double* t : dev)
             if (t) (void)hipFree(t);
     } else {
         e = (hipError_t)launch_twiddles(p->geo.g.precision, d, p->q_dev, p->xs_dev, p->ys_dev,
@@ -171,6 +179,19 @@ msft_status build_device_tables(msft_plan_s* p)
 #undef MSFT_TRY
     p->resident_bytes = total;
     return MSFT_OK;
+}
+
+// Workspace of the separable adjoint: h [P] complex, K tiles, R [nxc*64][ny][nzb*32]
+// complex; returns the total and the offsets of K and R.
+size_t sep_adj_layout(const msft_plan_s* p, size_t* k_off, size_t* r_off)
+{
+    const Dims& d = p->dims;
+    const size_t hb = align256((size_t)d.npix * 8);
+    const size_t kb = align256(p->sep.k_bytes(d.ny, d.nzb));
+    const size_t rb = align256((size_t)d.nxc * XC * d.ny * d.nzb * ZB * 8);
+    if (k_off) *k_off = hb;
+    if (r_off) *r_off = hb + kb;
+    return hb + kb + rb;
 }
 
 msft_status make_plan(const msft_geometry* g, const double* q_host, int64_t npix, int device,
@@ -233,11 +254,13 @@ msft_status make_plan(const msft_geometry* g, const double* q_host, int64_t npix
     }
     p->dims = make_dims(p->geo.npix, g->nx, g->ny, g->nz);
     size_t fwd_ws = align256(p->dims.wtile_bytes());
+    size_t adj_ws = align256(make_adj_dims(p->dims).bytes());
     if (p->separable) {
         p->sep = make_sep_dims(g->det_n, g->ny);
         fwd_ws += align256(p->sep.h_bytes(p->dims.nzb));
+        adj_ws = sep_adj_layout(p, nullptr, nullptr);
     }
-    p->workspace_bytes = std::max(fwd_ws, align256(make_adj_dims(p->dims).bytes()));
+    p->workspace_bytes = std::max(fwd_ws, adj_ws);
     p->device = device;
     if (device >= 0) {
         int count = 0;
@@ -612,6 +635,42 @@ msft_status msft_backward(msft_plan_t plan, const float* delta, const float* bet
     f.k0dz = (2.0 * 3.14159265358979323846) / g.wavelength * g.dz;
     DeviceScope ds(plan->device);
     if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice");
+    if (plan->separable) {
+        // the two transposed contractions of the separable detector, then the same
+        // column walk as the general adjoint (one pixel group)
+        size_t k_off = 0, r_off = 0;
+        sep_adj_layout(plan, &k_off, &r_off);
+        const SepDims& sd = plan->sep;
+        SepAdjArgs ka;
+        ka.h = (const float*)ws;
+        ka.tz = plan->tz;
+        ka.tyT = plan->tyT;
+        ka.ktiles = ws + k_off;
+        ka.n = sd.n;
+        ka.npad = sd.npad;
+        ka.ny = d.ny;
+        ka.nzb = d.nzb;
+        ka.njc = sd.njc;
+        Stage1Args ra;
+        ra.wtiles = ws + k_off;
+        ra.txa = plan->txT;
+        ra.htiles = nullptr;
+        ra.rplain = (float*)(ws + r_off);
+        ra.n = d.nx;
+        ra.ny = d.ny;
+        ra.nxc = sd.nic;
+        ra.nzb = d.nzb;
+        ra.x_pad = sd.nic * XC;
+        ra.nyc = 0;
+        ra.nz2 = d.nzb * ZB;
+        f.rpart = ra.rplain;
+        f.nsplit = 1;
+        int e = launch_adj_prep(amplitude, grad_intensity, (float*)ws, d.npix, d.npix, stream);
+        if (!e) e = launch_sep_adjoint(ka, ra, ceil_div(d.nx, BLOCK_PIX), stream);
+        if (!e) e = launch_adj_finalize(f, stream);
+        if (e) return hip_fail((hipError_t)e, "backward launch");
+        return ok();
+    }
     int e = launch_backward(a, f, amplitude, grad_intensity, stream);
     if (e) return hip_fail((hipError_t)e, "backward launch");
     return ok();

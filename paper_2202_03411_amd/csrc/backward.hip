@@ -239,6 +239,23 @@ __global__ void adj_finalize(FinArgs a)
     }
 }
 
+int launch_adj_prep(const float* amplitude, const float* grad_intensity, float* h, int64_t npix,
+                    int64_t npix_pad, void* stream)
+{
+    hipLaunchKernelGGL(adj_prep, dim3((unsigned)ceil_div(npix_pad, 256)), dim3(256), 0,
+                       (hipStream_t)stream, (const float2*)amplitude, grad_intensity, (float2*)h,
+                       npix, npix_pad);
+    return (int)hipGetLastError();
+}
+
+int launch_adj_finalize(const FinArgs& fin, void* stream)
+{
+    const int64_t ncol = (int64_t)fin.nx * fin.ny;
+    hipLaunchKernelGGL(adj_finalize, dim3((unsigned)ceil_div(ncol, 128)), dim3(128), 0,
+                       (hipStream_t)stream, fin);
+    return (int)hipGetLastError();
+}
+
 int launch_backward(const AdjArgs& adj, const FinArgs& fin, const float* amplitude,
                     const float* grad_intensity, void* stream)
 {

@@ -104,6 +104,8 @@ SepDims make_sep_dims(int32_t n, int ny)
     s.nblk1 = ceil_div(n, BLOCK_PIX);
     s.y_pad = (int32_t)(ceil_div(ny, XPAD) * XPAD);
     s.nyc = (int32_t)ceil_div(ny, XC);
+    s.njc = s.npad / XC;
+    s.nic = (int32_t)ceil_div(n, XC);
     return s;
 }
 

@@ -469,6 +469,14 @@ __device__ __forceinline__ void fwd_block(const FwdArgs& a, int64_t block, uint8
             float G[16];
 #pragma unroll
             for (int k = 0; k < 16; ++k) G[k] = 0.0f;
+            // Tz of this z block: without the rotation a z block is a single tile, so
+            // the loads are issued here and complete under the tile's MFMA chain
+            const f32x4* tzp = (const f32x4*)(a.tz + 2 * ((((wt * a.nzb + zb) * 2 + h) * ZB + col) * 8));
+            f32x4 tzv[4];
+            if (!ROT) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) tzv[k] = tzp[k];
+            }
             for (int y = 0; y < a.ny; ++y, ++t) {
                 const bool has_next = (t + 1) < ntiles;
                 uint4 n0, n1;
@@ -510,10 +518,9 @@ __device__ __forceinline__ void fwd_block(const FwdArgs& a, int64_t block, uint8
                 __syncthreads();
             }
             // acc[m] += Tz[m] * G[m]
-            const f32x4* tzp = (const f32x4*)(a.tz + 2 * ((((wt * a.nzb + zb) * 2 + h) * ZB + col) * 8));
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const f32x4 v = tzp[k];
+                const f32x4 v = ROT ? tzp[k] : tzv[k];
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
                     const int m = 2 * k + u;
@@ -626,60 +633,251 @@ int launch_forward_batch(int precision, const BatchArgs& b, int32_t grid, void* 
 // ---------------------------------------------------------------------------
 // First stage of the separable detector (Sec. 3, Blocks 6-7 with q_x a function
 // of the column i alone):  H[i][y][z] = sum_x exp(-i q_x(i) x) w(x, y, z).
-// Workgroup (block of 128 columns i, y, z block): the x chunks are summed in the
-// MFMA accumulator, then each lane stores its 8 columns' values into the H tiles
-// the second stage streams, tile (i, y chunk, z block) in the W tile layout with
-// y in place of x.  Workgroups with y beyond ny write the zero padding rows.
+// Workgroup (block of 128 columns i, S1_Y consecutive y, z block): the wave
+// loads its A operand once per x chunk and multiplies the S1_Y tiles of that
+// chunk (double-buffered in LDS) into S1_Y accumulators, so the x chunks are
+// summed in the MFMA accumulators.  Each lane then holds, for its 8 columns,
+// S1_Y consecutive y of one z: one 16-byte slot (FP32) or two 8-byte runs (BF16
+// hi, lo) of an H tile row, written with vector stores into the tile group of
+// column i (the W tile layout with y in place of x).  Workgroups beyond ny store
+// the zero padding rows.
 // ---------------------------------------------------------------------------
+constexpr int S1_Y = 4;
+
+__device__ __forceinline__ uint2 pack_bf16x4(__bf16 a, __bf16 b, __bf16 c, __bf16 d)
+{
+    union { __bf16 h[4]; uint2 u; } v;
+    v.h[0] = a;
+    v.h[1] = b;
+    v.h[2] = c;
+    v.h[3] = d;
+    return v.u;
+}
+
+// Row (h, zl) of an H tile, y = yl .. yl + 3 (yl a multiple of 4).
 template <int PREC>
+__device__ __forceinline__ void store_h4(uint8_t* tile, int h, int zl, int yl, const float* v)
+{
+    if (PREC == MSFT_FP32) {
+        *(float4*)(tile + tile_slot_offset(h, zl, yl >> 2)) = make_float4(v[0], v[1], v[2], v[3]);
+    } else {
+        __bf16 hi[4], lo[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            hi[u] = (__bf16)v[u];
+            lo[u] = (__bf16)(v[u] - (float)hi[u]);
+        }
+        const int sub = (yl & 7) * 2;
+        *(uint2*)(tile + tile_slot_offset(h, zl, yl >> 3) + sub) = pack_bf16x4(hi[0], hi[1], hi[2], hi[3]);
+        *(uint2*)(tile + tile_slot_offset(h, zl, 8 + (yl >> 3)) + sub) = pack_bf16x4(lo[0], lo[1], lo[2], lo[3]);
+    }
+}
+
+template <int PREC, bool PLAIN>
 __global__ __launch_bounds__(512) void sep_stage1_kernel(Stage1Args a)
 {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[TILE_BYTES];
+    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * TILE_BYTES];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int h = lane >> 5, col = lane & 31;
-    const int y = blockIdx.y, zb = blockIdx.z;
+    const int y0 = blockIdx.y * S1_Y, zb = blockIdx.z;
     const int64_t wt = (int64_t)blockIdx.x * WAVES + wave;
-    f32x16 C = {};
-    if (y < a.ny) {
+    const int nyh = max(0, min(S1_Y, a.ny - y0));   // y of this workgroup inside the grid
+    const uint4* wbase = (const uint4*)a.wtiles;
+    // tile (xc, y0 + u) of this z block, in uint4 units
+    auto tile_at = [&](int xc, int u) {
+        return wbase + ((size_t)(xc * a.nzb + zb) * a.ny + y0 + u) * (TILE_BYTES / 16);
+    };
+    f32x16 C[S1_Y];
+#pragma unroll
+    for (int u = 0; u < S1_Y; ++u) C[u] = f32x16{};
+    if (nyh > 0) {
+        {
+            const uint4* g0 = tile_at(0, 0);
+            const uint4 r0 = g0[tid], r1 = g0[tid + 512];
+            ((uint4*)lds)[tid] = r0;
+            ((uint4*)lds)[tid + 512] = r1;
+        }
+        __syncthreads();
+        int k = 0;   // tiles consumed so far; tile k sits in LDS buffer k & 1
         for (int xc = 0; xc < a.nxc; ++xc) {
-            const uint4* gw = (const uint4*)(a.wtiles + ((size_t)(xc * a.nzb + zb) * a.ny + y) * TILE_BYTES);
-            const uint4 r0 = gw[tid], r1 = gw[tid + 512];
             f32x4 Af[16];
             bf16x8 Ahi[8], Alo[8];
             load_a<PREC>(a.txa + (size_t)(wt * a.nxc + xc) * TILE_BYTES, lane, Af, Ahi, Alo);
-            __syncthreads();   // every wave is done with the previous chunk's tile
-            ((uint4*)lds)[tid] = r0;
-            ((uint4*)lds)[tid + 512] = r1;
-            __syncthreads();
+            __builtin_amdgcn_s_waitcnt(0);
             const int xlen = min(XC, a.x_pad - xc * XC);
-            const uint8_t* row = lds + (h * ZB + col) * ROW_BYTES;
-            C = (xlen == XC) ? tile_mfma<PREC, XC>(C, row, col, Af, Ahi, Alo)
-                             : tile_mfma_partial<PREC>(C, row, col, xlen, Af, Ahi, Alo);
+#pragma unroll
+            for (int u = 0; u < S1_Y; ++u) {
+                if (u < nyh) {
+                    // next tile: (xc, u + 1) or (xc + 1, 0)
+                    const int nxc_ = (u + 1 < nyh) ? xc : xc + 1;
+                    const int nu = (u + 1 < nyh) ? u + 1 : 0;
+                    const bool has_next = nxc_ < a.nxc;
+                    uint4 n0, n1;
+                    if (has_next) {
+                        const uint4* g = tile_at(nxc_, nu);
+                        n0 = g[tid];
+                        n1 = g[tid + 512];
+                    }
+                    const uint8_t* row = lds + (k & 1) * TILE_BYTES + (h * ZB + col) * ROW_BYTES;
+                    C[u] = (xlen == XC) ? tile_mfma<PREC, XC>(C[u], row, col, Af, Ahi, Alo)
+                                        : tile_mfma_partial<PREC>(C[u], row, col, xlen, Af, Ahi, Alo);
+                    if (has_next) {
+                        uint4* nb = (uint4*)(lds + ((k + 1) & 1) * TILE_BYTES);
+                        nb[tid] = n0;
+                        nb[tid + 512] = n1;
+                    }
+                    __syncthreads();
+                    ++k;
+                }
+            }
         }
     }
-    const int yc = y / XC, yl = y - yc * XC;
+    const int yc = y0 / XC, yl = y0 - yc * XC;
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
         const int64_t i = slot_pixel(wt, h, m);
         if (i < a.n) {
             const int r = 4 * (m >> 1) + 2 * (m & 1);
-            uint8_t* tile = a.htiles + ((size_t)(i * a.nyc + yc) * a.nzb + zb) * TILE_BYTES;
-            store_w<PREC>(tile, yl, col, C[r], C[r + 1]);
+            if (PLAIN) {
+                // rows of the adjoint's R: 32 lanes write 32 consecutive z
+#pragma unroll
+                for (int u = 0; u < S1_Y; ++u)
+                    if (u < nyh)
+                        ((float2*)a.rplain)[((size_t)i * a.ny + y0 + u) * a.nz2 + zb * ZB + col] =
+                            make_float2(C[u][r], C[u][r + 1]);
+            } else {
+                float re[S1_Y], im[S1_Y];
+#pragma unroll
+                for (int u = 0; u < S1_Y; ++u) {
+                    re[u] = C[u][r];
+                    im[u] = C[u][r + 1];
+                }
+                uint8_t* tile = a.htiles + ((size_t)(i * a.nyc + yc) * a.nzb + zb) * TILE_BYTES;
+                store_h4<PREC>(tile, 0, col, yl, re);
+                store_h4<PREC>(tile, 1, col, yl, im);
+            }
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of the separable detector.  With h = g conj(A) the strength gradient
+// needs R(x, y, z) = sum_{i,j} h(i, j) exp(-i (q_x(i) x + q_y(j) y + q_z(i, j) z)),
+// the transposed two-stage sum:
+//   K(i, y, z) = sum_j exp(-i q_y(j) y) [h(i, j) exp(-i q_z(i, j) z)]   (this kernel)
+//   R(x, y, z) = sum_i exp(-i q_x(i) x) K(i, y, z)          (sep_stage1_kernel, PLAIN)
+// Workgroup (128 rows y, S1_Y consecutive columns i, z block).  Per chunk of 64
+// detector rows j the wave loads its A operand (one table shared by every column),
+// the workgroup forms the S1_Y B tiles h Tz in LDS in the W tile layout (j in
+// place of x) from the plan's Tz table, and the wave multiplies them into S1_Y
+// accumulators.  K is stored in tiles (i chunk, z block, y) with i in place of x
+// (columns beyond N store zeros), ready to be the B operand of the second sum.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(512) void sepadj_rows_kernel(SepAdjArgs a)
+{
+    __shared__ __attribute__((aligned(16))) uint8_t lds[S1_Y * TILE_BYTES];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int h = lane >> 5, col = lane & 31;
+    const int64_t wt = (int64_t)blockIdx.x * WAVES + wave;   // 16 rows y
+    const int i0 = blockIdx.y * S1_Y, zb = blockIdx.z;
+    const int nih = max(0, min(S1_Y, a.n - i0));               // columns inside the detector
+    // this thread's 4 consecutive entries of one Tz block (16 pixels x 32 z of a z block)
+    const int w4 = tid >> 7, e0 = (tid & 127) * 4;
+    const int hh = e0 >> 8, z = (e0 >> 3) & 31, m0 = e0 & 7;
+    f32x16 C[S1_Y];
+#pragma unroll
+    for (int u = 0; u < S1_Y; ++u) C[u] = f32x16{};
+    if (nih > 0) {
+        for (int jc = 0; jc < a.njc; ++jc) {
+            f32x4 Af[16];
+            bf16x8 Ahi[8], Alo[8];
+            load_a<MSFT_FP32>(a.tyT + (size_t)(wt * a.njc + jc) * TILE_BYTES, lane, Af, Ahi, Alo);
+            __syncthreads();   // every wave is done with the previous chunk's tiles
+#pragma unroll
+            for (int u = 0; u < S1_Y; ++u) {
+                if (u < nih) {
+                    const int64_t i = i0 + u;
+                    const int64_t wt2 = i * (a.npad / WAVE_PIX) + jc * (XC / WAVE_PIX) + w4;
+                    const f32x4* tzp = (const f32x4*)(a.tz + 2 * ((wt2 * a.nzb + zb) * (2 * ZB * 8) + e0));
+                    const f32x4 t01 = tzp[0], t23 = tzp[1];
+                    const float tz[8] = {t01[0], t01[1], t01[2], t01[3], t23[0], t23[1], t23[2], t23[3]};
+                    uint8_t* tile = lds + u * TILE_BYTES;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int m = m0 + v;
+                        const int jl = w4 * WAVE_PIX + 4 * (m >> 1) + 2 * hh + (m & 1);
+                        const int64_t j = (int64_t)jc * XC + jl;
+                        float2 hv = make_float2(0.0f, 0.0f);
+                        if (j < a.n) hv = ((const float2*)a.h)[j * a.n + i];
+                        const float tr = tz[2 * v], ti = tz[2 * v + 1];
+                        *(float*)(tile + tile_slot_offset(0, z, jl >> 2) + (jl & 3) * 4) = hv.x * tr - hv.y * ti;
+                        *(float*)(tile + tile_slot_offset(1, z, jl >> 2) + (jl & 3) * 4) = hv.x * ti + hv.y * tr;
+                    }
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < S1_Y; ++u)
+                if (u < nih)
+                    C[u] = tile_mfma<MSFT_FP32, XC>(C[u], lds + u * TILE_BYTES + (h * ZB + col) * ROW_BYTES,
+                                                    col, Af, Ahi, Alo);
+        }
+    }
+    const int ic = i0 / XC, il = i0 - ic * XC;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        const int64_t y = slot_pixel(wt, h, m);
+        if (y < a.ny) {
+            const int r = 4 * (m >> 1) + 2 * (m & 1);
+            float re[S1_Y], im[S1_Y];
+#pragma unroll
+            for (int u = 0; u < S1_Y; ++u) {
+                re[u] = C[u][r];
+                im[u] = C[u][r + 1];
+            }
+            uint8_t* tile = a.ktiles + ((size_t)(ic * a.nzb + zb) * a.ny + y) * TILE_BYTES;
+            store_h4<MSFT_FP32>(tile, 0, col, il, re);
+            store_h4<MSFT_FP32>(tile, 1, col, il, im);
+        }
+    }
+}
+
+// Both contractions of the separable adjoint; R goes to ra.rplain.
+int launch_sep_adjoint(const SepAdjArgs& ka, const Stage1Args& ra, int64_t nblk_rows, void* stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    const int nic = (int)ceil_div(ka.n, XC);
+    const dim3 g1((unsigned)ceil_div(ka.ny, BLOCK_PIX), (unsigned)(nic * XC / S1_Y), (unsigned)ka.nzb);
+    hipLaunchKernelGGL(sepadj_rows_kernel, g1, dim3(512), 0, s, ka);
+    const dim3 g2((unsigned)nblk_rows, (unsigned)ceil_div(ra.ny, S1_Y), (unsigned)ra.nzb);
+    hipLaunchKernelGGL((sep_stage1_kernel<MSFT_FP32, true>), g2, dim3(512), 0, s, ra);
+    return (int)hipGetLastError();
+}
+
+// A tables of the adjoint (FP32): rows y against rows j, rows x against columns i;
+// xq3 / yq3 hold the voxel coordinates in slot 0 of [n][3] arrays.
+int launch_sep_adj_tables(const SepDims& sd, int nx, int ny, const double* xq3, const double* qx,
+                          const double* yq3, const double* qy, uint8_t* txT, uint8_t* tyT,
+                          void* stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    launch_txa(MSFT_FP32, tyT, ceil_div(ny, BLOCK_PIX) * WAVES, ny, sd.n, sd.njc, yq3, qy, s);
+    launch_txa(MSFT_FP32, txT, ceil_div(nx, BLOCK_PIX) * WAVES, nx, sd.n, sd.nic, xq3, qx, s);
+    return (int)hipGetLastError();
 }
 
 int launch_sep_stage1(int precision, const Stage1Args& a, int64_t nblk, void* stream)
 {
     hipStream_t s = (hipStream_t)stream;
-    const dim3 grid((unsigned)nblk, (unsigned)(a.nyc * XC), (unsigned)a.nzb);
+    const dim3 grid((unsigned)nblk, (unsigned)(a.nyc * XC / S1_Y), (unsigned)a.nzb);
     if (precision == MSFT_FP32)
-        hipLaunchKernelGGL(sep_stage1_kernel<MSFT_FP32>, grid, dim3(512), 0, s, a);
+        hipLaunchKernelGGL((sep_stage1_kernel<MSFT_FP32, false>), grid, dim3(512), 0, s, a);
     else if (precision == MSFT_BF16X3)
-        hipLaunchKernelGGL(sep_stage1_kernel<MSFT_BF16X3>, grid, dim3(512), 0, s, a);
+        hipLaunchKernelGGL((sep_stage1_kernel<MSFT_BF16X3, false>), grid, dim3(512), 0, s, a);
     else
-        hipLaunchKernelGGL(sep_stage1_kernel<MSFT_BF16>, grid, dim3(512), 0, s, a);
+        hipLaunchKernelGGL((sep_stage1_kernel<MSFT_BF16, false>), grid, dim3(512), 0, s, a);
     return (int)hipGetLastError();
 }
 

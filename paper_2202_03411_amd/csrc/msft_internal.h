@@ -97,14 +97,33 @@ struct SepDims {
     size_t txa2_bytes() const { return (size_t)(npad / WAVE_PIX) * nyc * TILE_BYTES; }
     size_t h_bytes(int nzb) const { return (size_t)n * nyc * nzb * TILE_BYTES; }
     size_t tz_bytes(int nzb) const { return (size_t)n * (npad / WAVE_PIX) * nzb * 2 * ZB * 8 * 8; }
+    // Adjoint: K(i, y, z) = sum_j Ty(j, y) h(i, j) Tz(i, j, z) in tiles (i chunk, z block, y)
+    // of 64 i x 32 z, then R = sum_i Tx(i, x) K(i, y, z).
+    int32_t njc = 0;    // chunks of 64 rows j (npad / 64)
+    int32_t nic = 0;    // chunks of 64 columns i
+    size_t tyT_bytes(int ny) const { return (size_t)ceil_div(ny, BLOCK_PIX) * WAVES * njc * TILE_BYTES; }
+    size_t txT_bytes(int nx) const { return (size_t)ceil_div(nx, BLOCK_PIX) * WAVES * nic * TILE_BYTES; }
+    size_t k_bytes(int ny, int nzb) const { return (size_t)nic * nzb * ny * TILE_BYTES; }
 };
 SepDims make_sep_dims(int32_t n, int ny);
 
+// Stage 1 of the separable detector (TILE output: H tiles), and the adjoint's
+// contraction over the columns i (PLAIN output: R[row][y][z] complex).
 struct Stage1Args {
-    const uint8_t* wtiles;  // W tiles of the scan
-    const uint8_t* txa;     // A tiles [column wave][xc]
-    uint8_t* htiles;        // H tiles [i][y chunk][z block]
-    int32_t n, ny, nxc, nzb, x_pad, nyc;
+    const uint8_t* wtiles;  // B tiles, index (xc * nzb + zb) * ny + y
+    const uint8_t* txa;     // A tiles [row wave][xc]
+    uint8_t* htiles;        // TILE: H tiles [i][y chunk][z block]
+    float* rplain;          // PLAIN: [row][ny][nz2] complex
+    int32_t n, ny, nxc, nzb, x_pad, nyc, nz2;
+};
+
+// The adjoint's contraction over the detector rows j (see SepDims).
+struct SepAdjArgs {
+    const float* h;        // [N * N] complex, h_p = g_p conj(A_p), p = j * N + i
+    const float* tz;       // the plan's Tz over stage 2's pixel order
+    const uint8_t* tyT;    // A tiles exp(-i q_y(j) y): [wave of 16 y][j chunk]
+    uint8_t* ktiles;       // K tiles, index (i chunk * nzb + zb) * ny + y
+    int32_t n, npad, ny, nzb, njc;
 };
 
 // Arguments of the column scan producing the W tiles.
@@ -176,6 +195,13 @@ int launch_sep_twiddles(int precision, const Dims& d, const SepDims& sd, const d
                         const double* qrow, const double* qk, const double* xs, const double* ys,
                         const double* zs, uint8_t* txa1, uint8_t* txa2, float* tz, void* stream);
 int launch_sep_stage1(int precision, const Stage1Args& a, int64_t nblk, void* stream);
+int launch_sep_adjoint(const SepAdjArgs& ka, const Stage1Args& ra, int64_t nblk_rows, void* stream);
+int launch_sep_adj_tables(const SepDims& sd, int nx, int ny, const double* xq3, const double* qx,
+                          const double* yq3, const double* qy, uint8_t* txT, uint8_t* tyT,
+                          void* stream);
+int launch_adj_prep(const float* amplitude, const float* grad_intensity, float* h, int64_t npix,
+                    int64_t npix_pad, void* stream);
+int launch_adj_finalize(const FinArgs& fin, void* stream);
 int launch_forward_batch(int precision, const BatchArgs& b, int32_t grid, void* stream);
 
 }  // namespace msft
@@ -195,6 +221,8 @@ struct msft_plan_s {
     float* ty = nullptr;
     float* tz = nullptr;          // separable detector: over stage 2's pixel order
     uint8_t* txa2 = nullptr;      // separable detector: stage-2 A operand
+    uint8_t* txT = nullptr;       // separable detector, adjoint: exp(-i q_x(i) x), rows x
+    uint8_t* tyT = nullptr;       // separable detector, adjoint: exp(-i q_y(j) y), rows y
     bool separable = false;
     msft::SepDims sep;
     size_t resident_bytes = 0;

@@ -31,6 +31,7 @@ class Request:
     admitted: float = math.nan
     done: float = math.nan
     footprint: int = 0
+    cost: float = 0.0              # executor's work estimate (voxel-pixel terms on the GPU)
     result: object = None
 
     @property
@@ -54,16 +55,23 @@ class Scheduler:
       launch(list[Request]) -> handle        (asynchronous)
       poll(handle) -> bool                    (True once finished)
       finish(handle, list[Request])          (collect results, free buffers)
+    and may provide cost(req) -> work estimate, used with max_batch_cost.
+
+    Every request of a launch completes when the launch does, so a launch groups
+    queued requests only up to max_batch_cost of work (at least one request):
+    cheap requests share a launch, an expensive one runs in its own, and the
+    launches in flight share the device.
     """
 
     def __init__(self, executor, hbm_budget: int, max_inflight: int = 3, max_batch: int = 24,
-                 clock: Callable[[], float] = time.perf_counter):
+                 clock: Callable[[], float] = time.perf_counter, max_batch_cost=None):
         if max_inflight < 1 or max_batch < 1:
             raise ValueError("max_inflight and max_batch must be >= 1")
         self.ex = executor
         self.budget = int(hbm_budget)
         self.max_inflight = max_inflight
         self.max_batch = max_batch
+        self.max_batch_cost = max_batch_cost
         self.clock = clock
         self.queue: collections.deque = collections.deque()
         self.inflight: list = []
@@ -73,6 +81,7 @@ class Scheduler:
 
     def submit(self, req: Request):
         req.footprint = int(self.ex.footprint(req))
+        req.cost = float(self.ex.cost(req)) if hasattr(self.ex, "cost") else 0.0
         if req.footprint > self.budget:
             # could never be admitted: refuse instead of blocking the queue
             self.rejected.append(req)
@@ -98,13 +107,16 @@ class Scheduler:
         """Form at most one batch from the head of the queue (FIFO, no overtaking)."""
         if len(self.inflight) >= self.max_inflight or not self.queue:
             return None
-        batch, foot = [], 0
+        batch, foot, cost = [], 0, 0.0
         while self.queue and len(batch) < self.max_batch:
             r = self.queue[0]
             if self.used + foot + r.footprint > self.budget:
                 break
+            if batch and self.max_batch_cost is not None and cost + r.cost > self.max_batch_cost:
+                break
             batch.append(self.queue.popleft())
             foot += r.footprint
+            cost += r.cost
         if not batch:
             return None
         now = self.clock()
@@ -226,6 +238,10 @@ class GpuExecutor:
         self.streams = [torch.cuda.Stream() for _ in range(n)]
         self.free = list(range(n))
 
+    def cost(self, req):
+        p = self.plans.get(req.key)
+        return float(p.npix) * p.grid[0] * p.grid[1] * p.grid[2]
+
     def footprint(self, req):
         p = self.plans.get(req.key)
         out = 4 * p.npix
@@ -343,12 +359,19 @@ def make_requests(pool, count, seed, rate=None, wavelength=45.0, theta=60.0,
     return out
 
 
-def serve(torch, msft, plans, requests, batched=True, hbm_budget=16 << 30, slots=3, max_batch=24,
-          progress=None):
-    """Run a request list through the server; returns (summary, requests)."""
+# Voxel-pixel terms per second of the contraction (measured, 128^3 / 512^2), used
+# only to turn a launch's time quantum into a work limit.
+TERMS_PER_S = {"fp32": 1.66e13, "bf16x3": 5.8e13, "bf16": 8.3e13}
+
+
+def serve(torch, msft, plans, requests, batched=True, hbm_budget=16 << 30, slots=4, max_batch=24,
+          quantum_s=0.005, progress=None):
+    """Run a request list through the server; returns (summary, requests).  A batched
+    launch holds at most quantum_s of estimated work (None: no limit)."""
     ex = GpuExecutor(plans, torch, nstreams=slots, batched=batched)
+    limit = None if quantum_s is None else quantum_s * TERMS_PER_S[plans.precision]
     sched = Scheduler(ex, hbm_budget, max_inflight=slots if batched else 1 << 30,
-                      max_batch=max_batch if batched else 1)
+                      max_batch=max_batch if batched else 1, max_batch_cost=limit)
     t0 = run_stream(sched, requests, progress=progress)
     torch.cuda.synchronize()
     t_end = max(r.done for r in sched.completed) if sched.completed else t0

@@ -16,17 +16,21 @@ class Clock:
 
 
 class FakeExecutor:
-    """Launch of a batch takes sum(cost) seconds; footprint from the request key."""
+    """Launch of a batch takes the sum of its requests' durations; footprint and
+    duration (also the work estimate) from the request key."""
 
-    def __init__(self, clock, foot, cost):
-        self.clock, self.foot, self.cost = clock, foot, cost
+    def __init__(self, clock, foot, dur):
+        self.clock, self.foot, self.dur = clock, foot, dur
         self.launches = []
 
     def footprint(self, req):
         return self.foot[req.key]
 
+    def cost(self, req):
+        return self.dur[req.key]
+
     def launch(self, batch):
-        h = {"end": self.clock() + sum(self.cost[r.key] for r in batch), "ids": [r.rid for r in batch]}
+        h = {"end": self.clock() + sum(self.dur[r.key] for r in batch), "ids": [r.rid for r in batch]}
         self.launches.append(h)
         return h
 
@@ -114,6 +118,20 @@ def test_oversize_request_refused_not_blocking():
     _drive(sched, clock, reqs)
     assert [r.rid for r in sched.rejected] == [1]
     assert sorted(r.rid for r in sched.completed) == [0, 2]
+
+
+def test_work_quantum_keeps_expensive_requests_apart():
+    # launches group cheap requests up to the work limit; an expensive request gets a
+    # launch of its own (and is never split or skipped: FIFO still holds)
+    clock = Clock()
+    ex = FakeExecutor(clock, {"s": 1, "l": 1}, {"s": 0.01, "l": 0.5})
+    sched = Scheduler(ex, hbm_budget=1000, max_inflight=8, max_batch=24, clock=clock,
+                      max_batch_cost=0.045)
+    keys = ["s"] * 6 + ["l"] + ["s"] * 3
+    for r in _reqs(keys, [0.0] * len(keys)):
+        sched.submit(r)
+    sched.step()
+    assert [h["ids"] for h in ex.launches] == [[0, 1, 2, 3], [4, 5], [6], [7, 8, 9]]
 
 
 def test_invalid_limits():
