@@ -127,7 +127,7 @@ def time_backward(msft, torch, plan, d, b, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
-def time_fit(torch, batch, steps, warmup, log):
+def time_fit(torch, batch, steps, warmup, log, detector="flat"):
     """One iteration of the differentiable fit: `batch` l <= 8 soft-voxelized
     shapes (81 coefficients, edge width one pitch) in a 680 nm box on 128^3,
     512^2 detector to 60 deg at 45 nm; loss = mean squared log-intensity error
@@ -139,7 +139,8 @@ def time_fit(torch, batch, steps, warmup, log):
     from paper_2202_03411_amd import fit, inputs, msft
     n, det, box, lmax, r0 = 128, 512, 680.0, 8, 200.0
     star = fit.SoftStar(n, box, lmax, r0)
-    plan = msft.Plan(45.0, 60.0, det, (n, n, n), (star.pitch,) * 3, "fp32", "msft")
+    plan = msft.Plan(45.0, 60.0, det, (n, n, n), (star.pitch,) * 3, "fp32", "msft",
+                     detector=detector)
     rng = np.random.default_rng(inputs.SEED_BASE + 4)
     ncoef = (lmax + 1) ** 2
     tc = rng.normal(0.0, 0.08, size=(batch, ncoef))
@@ -175,9 +176,10 @@ def time_fit(torch, batch, steps, warmup, log):
     plan.close()
     s = sum(times) / len(times)
     P, V = det * det, n ** 3
-    return {"batch": batch, "iterations": steps, "s_per_iteration": s,
+    return {"batch": batch, "detector": detector, "iterations": steps, "s_per_iteration": s,
             "shapes_per_s": batch / s,
-            "tflops_fwd_plus_bwd": 2 * 8.0 * P * V * batch / s / 1e12}
+            "tflops_fwd_plus_bwd": 2 * 8.0 * P * V * batch / s / 1e12,
+            "flops_basis": "direct sum" if detector == "flat" else "direct-sum equivalent"}
 
 
 def time_uniform(msft, torch, wl, d, b, prec, steps, warmup):
@@ -287,6 +289,7 @@ def main():
     ap.add_argument("--fit", type=int, default=0, metavar="B",
                     help="also time iterations of the differentiable fit with batch B")
     ap.add_argument("--fit-steps", type=int, default=1)
+    ap.add_argument("--fit-detector", choices=["flat", "uniform_q"], default="flat")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 256 MiB device-to-device copy, the reference for "
                          "scaling hardware byte counters")
@@ -441,7 +444,8 @@ def main():
                   f"{u['error_vs_fp64_oracle']['rel_l2_intensity']:.2e}", file=sys.stderr, flush=True)
     if args.fit > 0:
         line["fit"] = time_fit(torch, args.fit, args.fit_steps, 1 if args.fit_steps else 0,
-                               lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
+                               lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True),
+                               args.fit_detector)
     if not args.no_cpu_baseline and not args.only:
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(line))

@@ -9,7 +9,8 @@
 //                twiddles are regenerated per pixel chunk into LDS from FP64
 //                phases, not read from the plan.
 //  adj_finalize  sums the pixel groups in a fixed order and applies the chain
-//                rule through w = dV (n^2 - 1) T and the column scan (Eqs. (7)-(9)).
+//                rule through w = dV (n^2 - 1) T and the column scan (Eqs. (7)-(9)),
+//                one wave per column.
 #include <hip/hip_runtime.h>
 
 #include "msft_internal.h"
@@ -176,39 +177,62 @@ __global__ __launch_bounds__(512) void adj_contract(AdjArgs a)
 // One thread per (x, y) column.  Reverse pass over z with FP64 running sums:
 // the exclusive prefix S_c of (beta + i delta) is the column total minus the
 // suffix, and sum_{c'>c} R_c' w_c' accumulates on the way down.
-__global__ void adj_finalize(FinArgs a)
+// Inclusive suffix sum over the 64 lanes of a wave: lane l gets sum_{l' >= l} v.
+__device__ __forceinline__ double suffix_sum(double v, int lane)
 {
-    const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (col >= (int64_t)a.nx * a.ny) return;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double o = __shfl_down(v, off, 64);
+        if (lane + off < 64) v += o;
+    }
+    return v;
+}
+
+// One wave per (x, y) column, lanes along z, segments of 64 slices from the exit
+// face back to the entrance.  S_s = sum_{s'<s} (beta + i delta) is the column total
+// minus the inclusive suffix, T = exp(-k0 dz S), and the propagation term needs the
+// exclusive suffix sum_{s'>s} R_s' w_s'; both suffixes come from wave scans plus
+// the carry of the segments already done.  FP64 throughout.
+__global__ __launch_bounds__(256) void adj_finalize(FinArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t col = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (col >= (int64_t)a.nx * a.ny) return;   // wave-uniform
     const int x = (int)(col / a.ny), y = (int)(col % a.ny);
     const float* dcol = a.delta + col * a.nz;
     const float* bcol = a.beta + col * a.nz;
-    double tot_b = 0.0, tot_d = 0.0;
-    for (int c = 0; c < a.nz; ++c) {
-        tot_b += (double)bcol[c];
-        tot_d += (double)dcol[c];
+    double tb = 0.0, td = 0.0;
+    for (int c = lane; c < a.nz; c += 64) {
+        tb += (double)bcol[c];
+        td += (double)dcol[c];
     }
+    const double tot_b = __shfl(suffix_sum(tb, lane), 0, 64);
+    const double tot_d = __shfl(suffix_sum(td, lane), 0, 64);
     const int64_t X2 = (int64_t)a.nxc * XC, NZ2 = (int64_t)a.nzb * ZB;
     const int64_t part_stride = X2 * a.ny * NZ2;
     const float2* rp = (const float2*)a.rpart + ((int64_t)x * a.ny + y) * NZ2;
-    double suf_b = 0.0, suf_d = 0.0, srw_r = 0.0, srw_i = 0.0;
     const double dV = a.dV, k0dz = a.k0dz;
-    for (int c = a.nz - 1; c >= 0; --c) {
-        const double d = dcol[c], bt = bcol[c];
+    double carry_b = 0.0, carry_d = 0.0, carry_r = 0.0, carry_i = 0.0;
+    for (int seg = (a.nz + 63) / 64 - 1; seg >= 0; --seg) {
+        const int c = seg * 64 + lane;
+        const bool in = c < a.nz;
+        const double d = in ? (double)dcol[c] : 0.0, bt = in ? (double)bcol[c] : 0.0;
         double rr = 0.0, ri = 0.0;
-        for (int s = 0; s < a.nsplit; ++s) {
-            const float2 v = rp[s * part_stride + c];
-            rr += v.x;
-            ri += v.y;
-        }
-        double gd, gb;
+        if (in)
+            for (int s = 0; s < a.nsplit; ++s) {
+                const float2 v = rp[s * part_stride + c];
+                rr += v.x;
+                ri += v.y;
+            }
+        const double sufb = suffix_sum(bt, lane), sufd = suffix_sum(d, lane);
+        double gd = 0.0, gb = 0.0, rwr = 0.0, rwi = 0.0;
         if (a.strength == MSFT_STRENGTH_DENSITY) {
             gd = 2.0 * dV * rr;
             gb = -2.0 * dV * ri;
         } else {
             double tr = 1.0, ti = 0.0;
             if (a.strength == MSFT_STRENGTH_MSFT) {
-                const double sb = tot_b - suf_b - bt, sd = tot_d - suf_d - d;
+                const double sb = tot_b - (carry_b + sufb), sd = tot_d - (carry_d + sufd);
                 const double mag = exp(-k0dz * sb);
                 double sn, cs;
                 sincos(-k0dz * sd, &sn, &cs);
@@ -224,18 +248,26 @@ __global__ void adj_finalize(FinArgs a)
             gd = 2.0 * (rr * dd_r - ri * dd_i);
             gb = 2.0 * (rr * db_r - ri * db_i);
             if (a.strength == MSFT_STRENGTH_MSFT) {
-                gd += 2.0 * k0dz * srw_i;
-                gb -= 2.0 * k0dz * srw_r;
                 const double chr = d * (d - 2.0) - bt * bt, chi = 2.0 * bt * (1.0 - d);
                 const double wr = dV * (chr * tr - chi * ti), wi = dV * (chr * ti + chi * tr);
-                srw_r += rr * wr - ri * wi;
-                srw_i += rr * wi + ri * wr;
+                rwr = rr * wr - ri * wi;
+                rwi = rr * wi + ri * wr;
             }
         }
-        a.grad_delta[col * a.nz + c] = (float)gd;
-        a.grad_beta[col * a.nz + c] = (float)gb;
-        suf_b += bt;
-        suf_d += d;
+        if (a.strength == MSFT_STRENGTH_MSFT) {
+            const double sr = suffix_sum(rwr, lane), si = suffix_sum(rwi, lane);
+            // sum over s' > s: this segment's part without the own term, plus later segments
+            gd += 2.0 * k0dz * (carry_i + (si - rwi));
+            gb -= 2.0 * k0dz * (carry_r + (sr - rwr));
+            carry_r += __shfl(sr, 0, 64);
+            carry_i += __shfl(si, 0, 64);
+        }
+        if (in) {
+            a.grad_delta[col * a.nz + c] = (float)gd;
+            a.grad_beta[col * a.nz + c] = (float)gb;
+        }
+        carry_b += __shfl(sufb, 0, 64);
+        carry_d += __shfl(sufd, 0, 64);
     }
 }
 
@@ -251,7 +283,7 @@ int launch_adj_prep(const float* amplitude, const float* grad_intensity, float* 
 int launch_adj_finalize(const FinArgs& fin, void* stream)
 {
     const int64_t ncol = (int64_t)fin.nx * fin.ny;
-    hipLaunchKernelGGL(adj_finalize, dim3((unsigned)ceil_div(ncol, 128)), dim3(128), 0,
+    hipLaunchKernelGGL(adj_finalize, dim3((unsigned)ceil_div(ncol, 4)), dim3(256), 0,
                        (hipStream_t)stream, fin);
     return (int)hipGetLastError();
 }
@@ -266,7 +298,7 @@ int launch_backward(const AdjArgs& adj, const FinArgs& fin, const float* amplitu
     const int64_t nblocks = (int64_t)adj.nsplit * adj.nxc * adj.nzb * adj.nyb;
     hipLaunchKernelGGL(adj_contract, dim3((unsigned)nblocks), dim3(512), 0, s, adj);
     const int64_t ncol = (int64_t)fin.nx * fin.ny;
-    hipLaunchKernelGGL(adj_finalize, dim3((unsigned)ceil_div(ncol, 128)), dim3(128), 0, s, fin);
+    hipLaunchKernelGGL(adj_finalize, dim3((unsigned)ceil_div(ncol, 4)), dim3(256), 0, s, fin);
     return (int)hipGetLastError();
 }
 
