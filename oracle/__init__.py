@@ -49,9 +49,16 @@ def _load():
         lib.oracle_amplitude.argtypes = [i32, p, i64, i32, i32, i32, d, d, d, p, p]
         lib.oracle_backward.argtypes = [i32, p, i64, p, p, i32, i32, i32, d, d, d, d,
                                         p, p, p, i64, p, p]
+        lib.oracle_ylm.argtypes = [i32, i32, d, d]
+        lib.oracle_ylm.restype = ctypes.c_double
+        lib.oracle_render_sh.argtypes = [i32, i32, i32, d, d, d, i32, p, d, d, d, d, p, p]
+        lib.oracle_render_sh_backward.argtypes = [i32, i32, i32, d, d, d, i32, p, d, d, d, d,
+                                                  p, p, p]
+        lib.oracle_render_ellipsoid.argtypes = [i32, i32, i32, d, d, d, p, p, d, d, d, p, p]
         lib.oracle_threads.argtypes = []
         lib.oracle_threads.restype = ctypes.c_int
-        for f in (lib.oracle_qmap, lib.oracle_qmap_uniform, lib.oracle_grid, lib.oracle_strength,
+        for f in (lib.oracle_render_sh, lib.oracle_render_sh_backward, lib.oracle_render_ellipsoid,
+                  lib.oracle_qmap, lib.oracle_qmap_uniform, lib.oracle_grid, lib.oracle_strength,
                   lib.oracle_amplitude, lib.oracle_backward):
             f.restype = None
         _lib = lib
@@ -153,3 +160,49 @@ def simulate(mode: int, wavelength: float, theta_max_deg: float, n: int, delta, 
     w = strength(mode, delta, beta, pitch, wavelength)
     A = amplitude(q, w, pitch, method)
     return np.abs(A) ** 2, A
+
+
+def ylm(l: int, m: int, cos_theta: float, phi: float) -> float:
+    """Real orthonormal spherical harmonic (m > 0: cos(m phi), m < 0: sin(|m| phi))."""
+    return float(_load().oracle_ylm(int(l), int(m), float(cos_theta), float(phi)))
+
+
+def render_sh(grid, pitch, coeffs, r0: float, edge: float, delta0: float, beta0: float):
+    """Star body r0 (1 + sum c_lm Y_lm) as (delta, beta) on the centred grid; coeffs is a
+    vector of (lmax + 1)^2 values at l*l + l + m; edge = 0 gives hard voxels."""
+    c = _f64(coeffs).reshape(-1)
+    lmax = int(round(np.sqrt(c.size))) - 1
+    assert (lmax + 1) ** 2 == c.size
+    nx, ny, nz = (int(v) for v in grid)
+    dx, dy, dz = (float(v) for v in pitch)
+    d = np.empty((nx, ny, nz), np.float64)
+    b = np.empty((nx, ny, nz), np.float64)
+    _load().oracle_render_sh(nx, ny, nz, dx, dy, dz, lmax, _ptr(c), float(r0), float(edge),
+                             float(delta0), float(beta0), _ptr(d), _ptr(b))
+    return d, b
+
+
+def render_sh_backward(grid, pitch, coeffs, r0, edge, delta0, beta0, grad_delta, grad_beta):
+    """dL/dc for a loss with dL/d delta = grad_delta, dL/d beta = grad_beta (edge > 0)."""
+    c = _f64(coeffs).reshape(-1)
+    lmax = int(round(np.sqrt(c.size))) - 1
+    nx, ny, nz = (int(v) for v in grid)
+    dx, dy, dz = (float(v) for v in pitch)
+    gd, gb = _f64(grad_delta), _f64(grad_beta)
+    out = np.empty(c.size, np.float64)
+    _load().oracle_render_sh_backward(nx, ny, nz, dx, dy, dz, lmax, _ptr(c), float(r0), float(edge),
+                                      float(delta0), float(beta0), _ptr(gd), _ptr(gb), _ptr(out))
+    return out
+
+
+def render_ellipsoid(grid, pitch, axes, rot, edge: float, delta0: float, beta0: float):
+    """Ellipsoid with semi-axes along the columns of rot (3 x 3) as (delta, beta)."""
+    nx, ny, nz = (int(v) for v in grid)
+    dx, dy, dz = (float(v) for v in pitch)
+    ax = _f64(axes).reshape(3)
+    R = _f64(rot).reshape(9)
+    d = np.empty((nx, ny, nz), np.float64)
+    b = np.empty((nx, ny, nz), np.float64)
+    _load().oracle_render_ellipsoid(nx, ny, nz, dx, dy, dz, _ptr(ax), _ptr(R), float(edge),
+                                    float(delta0), float(beta0), _ptr(d), _ptr(b))
+    return d, b

@@ -6,8 +6,8 @@
  * benchmark may load this library.  The product path never calls it and shares
  * no code, header or table with it.  Every routine is plain, slow, double
  * precision C written from the paper's equations (Sec. 2 of "The Scatman",
- * arXiv 2202.03411); OpenMP only splits independent pixels or columns over
- * threads, it does not reorder any single sum.
+ * arXiv 2202.03411) and its shape descriptions (Sec. 5.2); OpenMP only splits
+ * independent pixels or columns over threads, it does not reorder any single sum.
  *
  * Equation numbers follow the paper: (1) first Born approximation, (2) slicing
  * of the z integral, (3) Ewald-sphere q_z, (4) MSFT with the Ewald phase,
@@ -347,4 +347,159 @@ void oracle_backward(int32_t mode, const double* q, int64_t npix,
     free(xs);
     free(ys);
     free(zs);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Shape rendering (Sec. 5.2): the sample's occupancy on the voxel grid.      */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * Real orthonormal spherical harmonic Y_lm(cos theta, phi), theta polar from +z:
+ * m > 0 carries cos(m phi), m < 0 carries sin(|m| phi), no Condon-Shortley sign
+ * (the reading of the paper's complex Y for a real radius).  Built from the
+ * unnormalised associated Legendre function, P_m^m = (2m-1)!! sin^m theta and the
+ * upward three-term recurrence in l, times sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!).
+ */
+double oracle_ylm(int32_t l, int32_t m, double ct, double phi)
+{
+    const int am = m < 0 ? -m : m;
+    const double st = sqrt(fmax(0.0, 1.0 - ct * ct));
+    double pmm = 1.0;
+    for (int k = 1; k <= am; ++k) pmm *= (2.0 * k - 1.0) * st;
+    double p = pmm;
+    if (l > am) {
+        double a = pmm, b = ct * (2.0 * am + 1.0) * pmm;
+        for (int ll = am + 2; ll <= l; ++ll) {
+            const double c = ((2.0 * ll - 1.0) * ct * b - (ll + am - 1.0) * a) / (double)(ll - am);
+            a = b;
+            b = c;
+        }
+        p = b;
+    }
+    double ratio = 1.0;
+    for (int k = l - am + 1; k <= l + am; ++k) ratio /= (double)k;
+    const double nrm = sqrt((2.0 * l + 1.0) / (4.0 * ORACLE_PI) * ratio);
+    if (m == 0) return nrm * p;
+    if (m > 0) return sqrt(2.0) * nrm * p * cos(m * phi);
+    return sqrt(2.0) * nrm * p * sin(am * phi);
+}
+
+/* Direction of voxel centre (x, y, z): cos theta and phi; +z at the origin. */
+static void oracle_direction(double x, double y, double z, double* r, double* ct, double* phi)
+{
+    *r = sqrt(x * x + y * y + z * z);
+    if (*r > 0.0) {
+        *ct = z / *r;
+        *phi = atan2(y, x);
+    } else {
+        *ct = 1.0;
+        *phi = 0.0;
+    }
+}
+
+/* Radius of the star body along a direction: r0 (1 + sum_lm c_lm Y_lm), c at l*l + l + m. */
+static double oracle_star_radius(int32_t lmax, const double* c, double r0, double ct, double phi)
+{
+    double s = 0.0;
+    for (int l = 0; l <= lmax; ++l)
+        for (int m = -l; m <= l; ++m) s += c[l * l + l + m] * oracle_ylm(l, m, ct, phi);
+    return r0 * (1.0 + s);
+}
+
+/* Occupancy of a voxel at distance r for a surface at rs: hard (edge = 0, closed) or a
+   sigmoid of (rs - r) / edge. */
+static double oracle_occupancy(double rs, double r, double edge)
+{
+    if (edge <= 0.0) return r <= rs ? 1.0 : 0.0;
+    return 1.0 / (1.0 + exp(-(rs - r) / edge));
+}
+
+/*
+ * Star body r(theta, phi) = r0 (1 + sum c_lm Y_lm) on the centred grid:
+ * delta = delta0 o, beta = beta0 o with o the occupancy above.
+ */
+void oracle_render_sh(int32_t nx, int32_t ny, int32_t nz, double dx, double dy, double dz,
+                      int32_t lmax, const double* c, double r0, double edge, double delta0,
+                      double beta0, double* delta, double* beta)
+{
+#pragma omp parallel for schedule(static)
+    for (int32_t a = 0; a < nx; ++a) {
+        const double x = ((double)(2 * a + 1 - nx) * dx) / 2.0;
+        for (int32_t b = 0; b < ny; ++b) {
+            const double y = ((double)(2 * b + 1 - ny) * dy) / 2.0;
+            for (int32_t k = 0; k < nz; ++k) {
+                const double z = ((double)(2 * k + 1 - nz) * dz) / 2.0;
+                double r, ct, phi;
+                oracle_direction(x, y, z, &r, &ct, &phi);
+                const double o = oracle_occupancy(oracle_star_radius(lmax, c, r0, ct, phi), r, edge);
+                const int64_t v = ((int64_t)a * ny + b) * nz + k;
+                delta[v] = delta0 * o;
+                beta[v] = beta0 * o;
+            }
+        }
+    }
+}
+
+/*
+ * Gradient of a loss through the soft star body (edge > 0):
+ * dL/dc_lm = sum_v (gd_v delta0 + gb_v beta0) o (1 - o) / edge * r0 Y_lm.
+ */
+void oracle_render_sh_backward(int32_t nx, int32_t ny, int32_t nz, double dx, double dy, double dz,
+                               int32_t lmax, const double* c, double r0, double edge, double delta0,
+                               double beta0, const double* gd, const double* gb, double* gc)
+{
+    const int nc = (lmax + 1) * (lmax + 1);
+    for (int k = 0; k < nc; ++k) gc[k] = 0.0;
+    for (int32_t a = 0; a < nx; ++a) {
+        const double x = ((double)(2 * a + 1 - nx) * dx) / 2.0;
+        for (int32_t b = 0; b < ny; ++b) {
+            const double y = ((double)(2 * b + 1 - ny) * dy) / 2.0;
+            for (int32_t k = 0; k < nz; ++k) {
+                const double z = ((double)(2 * k + 1 - nz) * dz) / 2.0;
+                double r, ct, phi;
+                oracle_direction(x, y, z, &r, &ct, &phi);
+                const double o = oracle_occupancy(oracle_star_radius(lmax, c, r0, ct, phi), r, edge);
+                const int64_t v = ((int64_t)a * ny + b) * nz + k;
+                const double s = (gd[v] * delta0 + gb[v] * beta0) * o * (1.0 - o) / edge * r0;
+                for (int l = 0; l <= lmax; ++l)
+                    for (int m = -l; m <= l; ++m) gc[l * l + l + m] += s * oracle_ylm(l, m, ct, phi);
+            }
+        }
+    }
+}
+
+/*
+ * Ellipsoid with semi-axes ax[3] along the columns of the rotation rot (row-major
+ * 3 x 3): body coordinates p = rot^T r, inside iff sum (p_k / a_k)^2 <= 1.  The soft
+ * form uses the radius along the voxel's direction, r_e = r / rho with
+ * rho = sqrt(sum (p_k / a_k)^2), so o = sigmoid((r_e - r) / edge) = sigmoid(r_e (1 - rho) / edge).
+ */
+void oracle_render_ellipsoid(int32_t nx, int32_t ny, int32_t nz, double dx, double dy, double dz,
+                             const double* ax, const double* rot, double edge, double delta0,
+                             double beta0, double* delta, double* beta)
+{
+#pragma omp parallel for schedule(static)
+    for (int32_t a = 0; a < nx; ++a) {
+        const double x = ((double)(2 * a + 1 - nx) * dx) / 2.0;
+        for (int32_t b = 0; b < ny; ++b) {
+            const double y = ((double)(2 * b + 1 - ny) * dy) / 2.0;
+            for (int32_t k = 0; k < nz; ++k) {
+                const double z = ((double)(2 * k + 1 - nz) * dz) / 2.0;
+                const double r = sqrt(x * x + y * y + z * z);
+                double rho2 = 0.0, e2 = 0.0;   /* e2: the same for the unit direction (+z at 0) */
+                for (int j = 0; j < 3; ++j) {
+                    const double pj = x * rot[0 * 3 + j] + y * rot[1 * 3 + j] + z * rot[2 * 3 + j];
+                    rho2 += (pj / ax[j]) * (pj / ax[j]);
+                    const double uj = r > 0.0 ? pj / r : rot[2 * 3 + j];
+                    e2 += (uj / ax[j]) * (uj / ax[j]);
+                }
+                double o;
+                if (edge <= 0.0) o = rho2 <= 1.0 ? 1.0 : 0.0;
+                else o = oracle_occupancy(1.0 / sqrt(e2), r, edge);
+                const int64_t v = ((int64_t)a * ny + b) * nz + k;
+                delta[v] = delta0 * o;
+                beta[v] = beta0 * o;
+            }
+        }
+    }
 }

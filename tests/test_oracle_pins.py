@@ -432,3 +432,91 @@ def test_backward_log_loss_fd_and_columns():
     for k, col in enumerate(cols):
         assert np.array_equal(cd[k], gd[col // ny, col % ny])
         assert np.array_equal(cb[k], gb[col // ny, col % ny])
+
+
+# ---------------------------------------------------------------------------
+# shape rendering (Sec. 5.2 shapes; real harmonics reading)
+# ---------------------------------------------------------------------------
+
+def test_ylm_matches_scipy():
+    import scipy.special as sp
+    rng = np.random.default_rng(11)
+    for _ in range(40):
+        th, ph = rng.uniform(0, np.pi), rng.uniform(-np.pi, np.pi)
+        for l in range(9):
+            for m in range(-l, l + 1):
+                y = sp.sph_harm_y(l, abs(m), th, ph)
+                ref = y.real if m == 0 else math.sqrt(2) * (-1) ** m * (y.real if m > 0 else y.imag)
+                assert math.isclose(oracle.ylm(l, m, math.cos(th), ph), ref, rel_tol=1e-11,
+                                    abs_tol=1e-13)
+
+
+def _centres(grid, pitch):
+    return np.meshgrid(*[oracle.grid(n, d) for n, d in zip(grid, pitch)], indexing="ij")
+
+
+def test_render_sphere_hard_and_soft():
+    grid, pitch, r0 = (17, 20, 23), (6.0, 5.0, 4.0), 35.0
+    X, Y, Z = _centres(grid, pitch)
+    r = np.sqrt(X * X + Y * Y + Z * Z)
+    c = np.zeros(81)
+    d, b = oracle.render_sh(grid, pitch, c, r0, 0.0, 0.01, 0.02)
+    assert np.array_equal(d, 0.01 * (r <= r0)) and np.array_equal(b, 0.02 * (r <= r0))
+    d, _ = oracle.render_sh(grid, pitch, c, r0, 2.5, 1.0, 0.0)
+    assert np.allclose(d, 1.0 / (1.0 + np.exp(-(r0 - r) / 2.5)), rtol=1e-14, atol=1e-15)
+    # c_00 alone scales the radius by 1 + c_00 / sqrt(4 pi)
+    c[0] = 0.3
+    d, _ = oracle.render_sh(grid, pitch, c, r0, 0.0, 1.0, 0.0)
+    assert np.array_equal(d, 1.0 * (r <= r0 * (1 + 0.3 / math.sqrt(4 * math.pi))))
+
+
+def test_render_sh_single_harmonic_direction():
+    # c_10 alone: r = r0 (1 + c sqrt(3 / 4 pi) cos theta), a body longer along +z than -z
+    grid, pitch, r0 = (21, 21, 41), (4.0, 4.0, 4.0), 40.0
+    c = np.zeros(4)
+    c[2] = 0.5   # (l, m) = (1, 0) at l*l + l + m = 2
+    d, _ = oracle.render_sh(grid, pitch, c, r0, 0.0, 1.0, 0.0)
+    X, Y, Z = _centres(grid, pitch)
+    r = np.sqrt(X * X + Y * Y + Z * Z)
+    ct = np.where(r > 0, Z / np.where(r > 0, r, 1.0), 1.0)
+    assert np.array_equal(d, 1.0 * (r <= r0 * (1 + 0.5 * math.sqrt(3 / (4 * math.pi)) * ct)))
+    # z = +48 lies inside (r = 49.8 along +z), z = -48 outside (r = 30.2 along -z)
+    assert d[10, 10, 20 + 12] == 1.0 and d[10, 10, 20 - 12] == 0.0
+
+
+def test_render_sh_backward_finite_differences():
+    grid, pitch, r0, edge = (9, 8, 10), (7.0, 7.0, 7.0), 22.0, 3.0
+    rng = np.random.default_rng(12)
+    c = rng.normal(0, 0.1, 16)
+    c[0] = 0.0
+    gd, gb = rng.normal(size=grid), rng.normal(size=grid)
+
+    def loss(cc):
+        d, b = oracle.render_sh(grid, pitch, cc, r0, edge, 0.01, 0.02)
+        return float(np.sum(gd * d) + np.sum(gb * b))
+
+    g = oracle.render_sh_backward(grid, pitch, c, r0, edge, 0.01, 0.02, gd, gb)
+    eps = 1e-6
+    for k in range(16):
+        e = np.zeros(16)
+        e[k] = eps
+        fd = (loss(c + e) - loss(c - e)) / (2 * eps)
+        assert math.isclose(g[k], fd, rel_tol=1e-6, abs_tol=1e-12), k
+
+
+def test_render_ellipsoid_quadric_and_sphere_limit():
+    grid, pitch = (24, 19, 27), (5.0, 6.0, 4.0)
+    X, Y, Z = _centres(grid, pitch)
+    rng = np.random.default_rng(13)
+    # a rotation from a QR factorisation
+    R, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    ax = np.array([50.0, 30.0, 20.0])
+    d, b = oracle.render_ellipsoid(grid, pitch, ax, R, 0.0, 0.01, 0.02)
+    P = np.stack([X, Y, Z], -1) @ R
+    inside = np.sum((P / ax) ** 2, axis=-1) <= 1.0
+    assert np.array_equal(d, 0.01 * inside) and np.array_equal(b, 0.02 * inside)
+    # equal axes: the sphere of the harmonic renderer, hard and soft
+    for edge in (0.0, 2.0):
+        e, _ = oracle.render_ellipsoid(grid, pitch, [33.0] * 3, R, edge, 1.0, 0.0)
+        s, _ = oracle.render_sh(grid, pitch, np.zeros(1), 33.0, edge, 1.0, 0.0)
+        assert np.allclose(e, s, rtol=1e-13, atol=1e-15)
