@@ -218,6 +218,35 @@ def time_uniform(msft, torch, wl, d, b, prec, steps, warmup):
             "error_vs_fp64_oracle": {"rel_l2_intensity": err, "pixels": int(ok.sum())}}
 
 
+def time_render(msft, torch, steps):
+    """The fit's star-body renderer on 128^3 (l <= 8, soft edge of one pitch) and its
+    coefficient gradient."""
+    import numpy as np
+    n, box, lmax = 128, 680.0, 8
+    g = msft.make_shape_grid((n, n, n), (box / n,) * 3, box / n, 0.01, 0.02)
+    c = torch.tensor(np.random.default_rng(3).normal(0, 0.08, 81), dtype=torch.float32, device="cuda")
+    d = torch.empty((n, n, n), device="cuda")
+    b = torch.empty_like(d)
+    gc = torch.empty_like(c)
+    ws = msft.workspace_tensor(msft.msft_render_sh_query(lmax), "cuda")
+    out = {}
+    for name, call in (("render_ms", lambda: msft.msft_render_sh(g, lmax, 200.0, c, d, b)),
+                       ("gradient_ms", lambda: msft.msft_render_sh_backward(g, lmax, 200.0, c, d, b,
+                                                                           gc, ws))):
+        call()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            call()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = e0.elapsed_time(e1) / steps
+    out["voxels"] = n ** 3
+    out["voxels_per_s"] = n ** 3 / (out["render_ms"] * 1e-3)
+    return out
+
+
 def oracle_error(wl, I_gpu, npix=256):
     """Relative L2 intensity error of a GPU pattern against the FP64 oracle on
     seeded pixels (all of them and the wide-angle ring theta > 3/4 theta_max)."""
@@ -442,6 +471,10 @@ def main():
             print(f"[bench] uniform-q {prec}: {u['ms_per_step']:.3f} ms/pattern, "
                   f"{u['contract_tflops']:.1f} TFLOP/s (two stages), error "
                   f"{u['error_vs_fp64_oracle']['rel_l2_intensity']:.2e}", file=sys.stderr, flush=True)
+    if not args.only:
+        line["render"] = time_render(msft, torch, args.steps)
+        print(f"[bench] render l<=8 soft star 128^3: {line['render']['render_ms'] * 1e3:.1f} us, "
+              f"gradient {line['render']['gradient_ms'] * 1e3:.1f} us", file=sys.stderr, flush=True)
     if args.fit > 0:
         line["fit"] = time_fit(torch, args.fit, args.fit_steps, 1 if args.fit_steps else 0,
                                lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True),

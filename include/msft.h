@@ -224,6 +224,58 @@ msft_status msft_backward(msft_plan_t plan, const float* delta, const float* bet
                           const float* amplitude, const float* grad_intensity,
                           float* grad_delta, float* grad_beta, void* workspace, void* stream);
 
+/*
+ * Shape rendering (Sec. 5.2): delta and beta of a sample on a voxel grid centred
+ * on the origin (the grid of msft_geometry), produced on the device ahead of
+ * msft_simulate.  For a voxel centre at distance r from the origin, with r_s the
+ * body's surface radius along the centre's direction (+z at the origin), the
+ * occupancy is o = 1 if r <= r_s else 0 (edge = 0), or the soft form
+ * o = 1 / (1 + exp(-(r_s - r) / edge)) (edge > 0, a width in the grid's length
+ * unit); then delta = delta0 o and beta = beta0 o.  struct_size must be
+ * sizeof(msft_shape_grid).
+ */
+typedef struct {
+    uint32_t struct_size;
+    int32_t nx, ny, nz;     /* voxel counts >= 1 */
+    double dx, dy, dz;      /* pitch > 0 */
+    double edge;            /* >= 0 */
+    double delta0, beta0;   /* optical constants inside the body */
+} msft_shape_grid;
+
+/*
+ * Star body r_s(theta, phi) = r0 (1 + sum_{l <= lmax, |m| <= l} c_lm Y_lm(theta, phi))
+ * with real orthonormal harmonics, theta polar from +z, m > 0 carrying cos(m phi) and
+ * m < 0 sin(|m| phi), no Condon-Shortley sign (the reading of the paper's complex
+ * harmonics for a real radius).  coeffs: device float32 [(lmax + 1)^2], c_lm at
+ * l*l + l + m, 0 <= lmax <= 12.  delta, beta: device float32 [nx][ny][nz] (written).
+ */
+msft_status msft_render_sh(const msft_shape_grid* g, int32_t lmax, double r0, const float* coeffs,
+                           float* delta, float* beta, void* stream);
+
+/* Device workspace bytes msft_render_sh_backward needs (independent of the grid). */
+msft_status msft_render_sh_query(int32_t lmax, size_t* workspace_bytes);
+
+/*
+ * Gradient of a loss through the soft star body (edge > 0): given dL/d delta and
+ * dL/d beta (device float32 [nx][ny][nz]), write
+ *   dL/dc_lm = sum_v (dL/d delta_v delta0 + dL/d beta_v beta0) o_v (1 - o_v) / edge r0 Y_lm
+ * into grad_coeffs (device float32 [(lmax + 1)^2]).  Partial sums per workgroup are
+ * added in a fixed order: the result does not depend on the launch.
+ */
+msft_status msft_render_sh_backward(const msft_shape_grid* g, int32_t lmax, double r0,
+                                    const float* coeffs, const float* grad_delta,
+                                    const float* grad_beta, float* grad_coeffs, void* workspace,
+                                    size_t ws_bytes, void* stream);
+
+/*
+ * Ellipsoid with semi-axes axes[3] (host, > 0) along the columns of the rotation
+ * rot[9] (host, row-major, orthonormal): body coordinates p = rot^T r, inside iff
+ * sum (p_k / a_k)^2 <= 1; the soft form uses r_s = 1 / sqrt(sum (u_k / a_k)^2) for
+ * the unit direction u = rot^T r / r.
+ */
+msft_status msft_render_ellipsoid(const msft_shape_grid* g, const double* axes, const double* rot,
+                                  float* delta, float* beta, void* stream);
+
 /* Static description of a status code. */
 const char* msft_status_str(msft_status s);
 

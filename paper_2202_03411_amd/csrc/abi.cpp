@@ -384,9 +384,122 @@ msft_status check_runnable(const msft_plan_s* p)
     return MSFT_OK;
 }
 
+msft_status shape_grid_args(const msft_shape_grid* g, RenderGrid* out)
+{
+    if (!g) return fail(MSFT_ERR_INVALID, "shape grid is NULL");
+    if (g->struct_size != sizeof(msft_shape_grid))
+        return fail(MSFT_ERR_INVALID, "struct_size != sizeof(msft_shape_grid)");
+    if (g->nx < 1 || g->ny < 1 || g->nz < 1 || g->nx > 4096 || g->ny > 4096 || g->nz > 4096)
+        return fail(MSFT_ERR_INVALID, "nx, ny, nz must lie in [1, 4096]");
+    if (!(g->dx > 0.0 && g->dy > 0.0 && g->dz > 0.0) || !std::isfinite(g->dx) ||
+        !std::isfinite(g->dy) || !std::isfinite(g->dz))
+        return fail(MSFT_ERR_INVALID, "voxel pitch must be finite and > 0");
+    if (!(g->edge >= 0.0) || !std::isfinite(g->edge)) return fail(MSFT_ERR_INVALID, "edge must be >= 0");
+    if (!std::isfinite(g->delta0) || !std::isfinite(g->beta0))
+        return fail(MSFT_ERR_INVALID, "delta0 and beta0 must be finite");
+    out->nx = g->nx;
+    out->ny = g->ny;
+    out->nz = g->nz;
+    out->dx = g->dx;
+    out->dy = g->dy;
+    out->dz = g->dz;
+    out->edge = g->edge;
+    out->delta0 = g->delta0;
+    out->beta0 = g->beta0;
+    return MSFT_OK;
+}
+
+// Recurrence constants of the normalised Legendre values, FP64 on the host.
+msft_status sh_args(const msft_shape_grid* g, int32_t lmax, double r0, ShArgs* s)
+{
+    msft_status st = shape_grid_args(g, &s->g);
+    if (st != MSFT_OK) return st;
+    if (lmax < 0 || lmax > MAX_SH_L) return fail(MSFT_ERR_INVALID, "lmax must lie in [0, 12]");
+    if (!(r0 > 0.0) || !std::isfinite(r0)) return fail(MSFT_ERR_INVALID, "r0 must be finite and > 0");
+    s->lmax = lmax;
+    s->r0 = r0;
+    for (int m = 0; m < SH_TABLE; ++m) {
+        s->diag[m] = m > 0 ? std::sqrt((2.0 * m + 1.0) / (2.0 * m)) : 1.0;
+        s->sub[m] = std::sqrt(2.0 * m + 3.0);
+    }
+    for (int l = 0; l < SH_TABLE; ++l)
+        for (int m = 0; m < SH_TABLE; ++m) {
+            double a = 0.0, b = 0.0;
+            if (l >= m + 2) {
+                const double ll = l, mm = m;
+                a = std::sqrt((4.0 * ll * ll - 1.0) / (ll * ll - mm * mm));
+                b = std::sqrt(((ll - 1.0) * (ll - 1.0) - mm * mm) / (4.0 * (ll - 1.0) * (ll - 1.0) - 1.0));
+            }
+            s->ra[l * SH_TABLE + m] = a;
+            s->rb[l * SH_TABLE + m] = b;
+        }
+    return MSFT_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+msft_status msft_render_sh(const msft_shape_grid* g, int32_t lmax, double r0, const float* coeffs,
+                           float* delta, float* beta, void* stream)
+{
+    ShArgs s;
+    msft_status st = sh_args(g, lmax, r0, &s);
+    if (st != MSFT_OK) return st;
+    if (!coeffs || !delta || !beta) return fail(MSFT_ERR_INVALID, "NULL argument");
+    int e = launch_render_sh(s, coeffs, delta, beta, stream);
+    if (e) return hip_fail((hipError_t)e, "render launch");
+    return ok();
+}
+
+msft_status msft_render_sh_query(int32_t lmax, size_t* workspace_bytes)
+{
+    if (lmax < 0 || lmax > MAX_SH_L) return fail(MSFT_ERR_INVALID, "lmax must lie in [0, 12]");
+    if (workspace_bytes) *workspace_bytes = (size_t)SH_GRAD_BLOCKS * MAX_SH_COEFFS * sizeof(double);
+    return ok();
+}
+
+msft_status msft_render_sh_backward(const msft_shape_grid* g, int32_t lmax, double r0,
+                                    const float* coeffs, const float* grad_delta,
+                                    const float* grad_beta, float* grad_coeffs, void* workspace,
+                                    size_t ws_bytes, void* stream)
+{
+    ShArgs s;
+    msft_status st = sh_args(g, lmax, r0, &s);
+    if (st != MSFT_OK) return st;
+    if (!(g->edge > 0.0)) return fail(MSFT_ERR_INVALID, "the gradient needs a soft edge (edge > 0)");
+    if (!coeffs || !grad_delta || !grad_beta || !grad_coeffs || !workspace)
+        return fail(MSFT_ERR_INVALID, "NULL argument");
+    if (!aligned256(workspace)) return fail(MSFT_ERR_INVALID, "workspace must be 256-byte aligned");
+    if (ws_bytes < (size_t)SH_GRAD_BLOCKS * MAX_SH_COEFFS * sizeof(double))
+        return fail(MSFT_ERR_BUSY, "workspace smaller than msft_render_sh_query");
+    int e = launch_render_sh_grad(s, coeffs, grad_delta, grad_beta, grad_coeffs, (double*)workspace,
+                                  SH_GRAD_BLOCKS, stream);
+    if (e) return hip_fail((hipError_t)e, "render gradient launch");
+    return ok();
+}
+
+msft_status msft_render_ellipsoid(const msft_shape_grid* g, const double* axes, const double* rot,
+                                  float* delta, float* beta, void* stream)
+{
+    EllArgs a;
+    msft_status st = shape_grid_args(g, &a.g);
+    if (st != MSFT_OK) return st;
+    if (!axes || !rot || !delta || !beta) return fail(MSFT_ERR_INVALID, "NULL argument");
+    for (int k = 0; k < 3; ++k) {
+        if (!(axes[k] > 0.0) || !std::isfinite(axes[k]))
+            return fail(MSFT_ERR_INVALID, "semi-axes must be finite and > 0");
+        a.ax[k] = axes[k];
+    }
+    for (int k = 0; k < 9; ++k) {
+        if (!std::isfinite(rot[k])) return fail(MSFT_ERR_INVALID, "rotation must be finite");
+        a.rot[k] = rot[k];
+    }
+    int e = launch_render_ellipsoid(a, delta, beta, stream);
+    if (e) return hip_fail((hipError_t)e, "render launch");
+    return ok();
+}
+
 
 msft_status msft_plan(const msft_geometry* g, int device, msft_plan_t* out)
 {

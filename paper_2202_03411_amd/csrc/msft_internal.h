@@ -182,6 +182,34 @@ struct FinArgs {
     double dV, k0dz;
 };
 
+// Shape rendering.  Real harmonics up to MAX_SH_L; the l-recurrence constants
+// Q_lm = ra (cos(theta) Q_{l-1,m} - rb Q_{l-2,m}) at [l * SH_TABLE + m], the
+// diagonal Q_mm = diag[m] sin(theta) Q_{m-1,m-1}, the first step Q_{m+1,m} =
+// sub[m] cos(theta) Q_mm, all made on the host in FP64.
+constexpr int MAX_SH_L = 12;
+constexpr int SH_TABLE = MAX_SH_L + 1;
+constexpr int MAX_SH_COEFFS = SH_TABLE * SH_TABLE;
+constexpr int SH_GRAD_BLOCKS = 512;   // workgroups of the coefficient gradient (its partials)
+
+struct RenderGrid {
+    int32_t nx, ny, nz;
+    double dx, dy, dz, edge, delta0, beta0;
+};
+
+struct ShArgs {
+    RenderGrid g;
+    int32_t lmax;
+    double r0;
+    double diag[SH_TABLE], sub[SH_TABLE];
+    double ra[SH_TABLE * SH_TABLE], rb[SH_TABLE * SH_TABLE];
+};
+
+struct EllArgs {
+    RenderGrid g;
+    double ax[3];
+    double rot[9];   // row-major; its columns are the body axes
+};
+
 // Kernel launchers (defined in the .hip sources); return a HIP error code.
 int launch_backward(const AdjArgs& adj, const FinArgs& fin, const float* amplitude,
                     const float* grad_intensity, void* stream);
@@ -202,6 +230,10 @@ int launch_sep_adj_tables(const SepDims& sd, int nx, int ny, const double* xq3, 
 int launch_adj_prep(const float* amplitude, const float* grad_intensity, float* h, int64_t npix,
                     int64_t npix_pad, void* stream);
 int launch_adj_finalize(const FinArgs& fin, void* stream);
+int launch_render_sh(const ShArgs& s, const float* coeffs, float* delta, float* beta, void* stream);
+int launch_render_sh_grad(const ShArgs& s, const float* coeffs, const float* gd, const float* gb,
+                          float* grad, double* partial, int nblocks, void* stream);
+int launch_render_ellipsoid(const EllArgs& e, float* delta, float* beta, void* stream);
 int launch_forward_batch(int precision, const BatchArgs& b, int32_t grid, void* stream);
 
 }  // namespace msft

@@ -5,13 +5,12 @@ forward saves the amplitudes A, the backward hands dL/dI to the library's
 adjoint kernels and returns dL/d delta and dL/d beta.  ``SoftStar`` renders a
 star-shaped body r(theta, phi) = R0 (1 + sum c_lm Y_lm) (the spherical-harmonic
 shapes of Sec. 5.2, real harmonics, theta polar from +z) as a sigmoid-soft voxel
-map so torch can carry the gradient on to the coefficients.  Torch only does
-the shape rendering and the loss; every step of the scattering model runs in
+map with msft_render_sh, and ``SHRenderFunction`` carries the gradient on to the
+coefficients with msft_render_sh_backward.  Torch only holds the tensors and
+computes the loss; the rendering, the scattering model and both adjoints run in
 the library.
 """
 from __future__ import annotations
-
-import math
 
 import torch
 
@@ -50,55 +49,53 @@ def log_mse_loss(I, target, eps=1e-6):
     return torch.mean((torch.log(I + eps) - torch.log(target + eps)) ** 2)
 
 
-def real_sh_torch(lmax, theta, phi):
-    """Real orthonormal spherical harmonics, rows ordered l = 0..lmax, m = -l..l."""
-    x, s = torch.cos(theta), torch.sin(theta)
-    qbar = {(0, 0): torch.full_like(x, 1.0 / math.sqrt(4.0 * math.pi))}
-    for m in range(1, lmax + 1):
-        qbar[(m, m)] = math.sqrt((2.0 * m + 1.0) / (2.0 * m)) * s * qbar[(m - 1, m - 1)]
-    for m in range(0, lmax):
-        qbar[(m + 1, m)] = math.sqrt(2.0 * m + 3.0) * x * qbar[(m, m)]
-    for m in range(0, lmax + 1):
-        for l in range(m + 2, lmax + 1):
-            a = math.sqrt((4.0 * l * l - 1.0) / (l * l - m * m))
-            b = math.sqrt(((l - 1.0) ** 2 - m * m) / (4.0 * (l - 1.0) ** 2 - 1.0))
-            qbar[(l, m)] = a * (x * qbar[(l - 1, m)] - b * qbar[(l - 2, m)])
-    rows = []
-    for l in range(lmax + 1):
-        for m in range(-l, l + 1):
-            if m == 0:
-                rows.append(qbar[(l, 0)])
-            elif m > 0:
-                rows.append(math.sqrt(2.0) * qbar[(l, m)] * torch.cos(m * phi))
-            else:
-                rows.append(math.sqrt(2.0) * qbar[(l, -m)] * torch.sin(-m * phi))
-    return torch.stack(rows, dim=0)
+class SHRenderFunction(torch.autograd.Function):
+    """(delta, beta) of a SoftStar from its coefficients; differentiable in the coefficients."""
+
+    @staticmethod
+    def forward(ctx, coeffs, star):
+        coeffs = coeffs.detach().float().contiguous()
+        delta = torch.empty(star.shape, dtype=torch.float32, device=coeffs.device)
+        beta = torch.empty_like(delta)
+        msft.msft_render_sh(star.grid, star.lmax, star.r0, coeffs, delta, beta)
+        ctx.star = star
+        ctx.save_for_backward(coeffs)
+        return delta, beta
+
+    @staticmethod
+    def backward(ctx, grad_delta, grad_beta):
+        (coeffs,) = ctx.saved_tensors
+        star = ctx.star
+        gd = torch.zeros(star.shape, device=coeffs.device) if grad_delta is None else grad_delta
+        gb = torch.zeros(star.shape, device=coeffs.device) if grad_beta is None else grad_beta
+        grad = torch.empty_like(coeffs)
+        msft.msft_render_sh_backward(star.grid, star.lmax, star.r0, coeffs,
+                                     gd.detach().float().contiguous(), gb.detach().float().contiguous(),
+                                     grad, star.workspace())
+        return grad, None
 
 
 class SoftStar:
-    """Sigmoid-soft voxelization of R0 (1 + sum c_lm Y_lm) on an n^3 grid of a box."""
+    """Sigmoid-soft voxelization of R0 (1 + sum c_lm Y_lm) on an n^3 grid of a box centred on
+    the origin; edge width eps (default one pitch); coefficients at l*l + l + m."""
 
-    def __init__(self, n, extent, lmax, r0, eps=None, delta0=0.01, beta0=0.02,
-                 device="cuda", dtype=torch.float32):
+    def __init__(self, n, extent, lmax, r0, eps=None, delta0=0.01, beta0=0.02, device="cuda"):
         self.n, self.extent, self.lmax, self.r0 = n, float(extent), lmax, float(r0)
         self.pitch = self.extent / n
         self.eps = float(eps) if eps is not None else self.pitch
         self.delta0, self.beta0 = float(delta0), float(beta0)
-        c = (torch.arange(n, dtype=torch.float64, device=device) * 2.0 + 1.0 - n) * self.pitch / 2.0
-        X, Y, Z = torch.meshgrid(c, c, c, indexing="ij")
-        rr = torch.sqrt(X * X + Y * Y + Z * Z)
-        theta = torch.arccos(torch.clamp(Z / torch.where(rr > 0, rr, torch.ones_like(rr)), -1.0, 1.0))
-        phi = torch.atan2(Y, X)
-        self.radius = rr.to(dtype).reshape(-1)
-        self.basis = real_sh_torch(lmax, theta, phi).to(dtype).reshape((lmax + 1) ** 2, -1)
+        self.device = torch.device(device)
+        self.shape = (n, n, n)
         self.ncoef = (lmax + 1) ** 2
+        self.grid = msft.make_shape_grid(self.shape, (self.pitch,) * 3, self.eps, self.delta0,
+                                         self.beta0)
+        self._ws = None
 
-    def occupancy(self, coeffs):
-        """coeffs [..., ncoef] -> soft occupancy [..., n, n, n]."""
-        r = self.r0 * (1.0 + coeffs.to(self.basis.dtype) @ self.basis)
-        o = torch.sigmoid((r - self.radius) / self.eps)
-        return o.reshape(*coeffs.shape[:-1], self.n, self.n, self.n)
+    def workspace(self):
+        if self._ws is None:
+            self._ws = msft.workspace_tensor(msft.msft_render_sh_query(self.lmax), self.device)
+        return self._ws
 
     def voxelize(self, coeffs):
-        o = self.occupancy(coeffs)
-        return self.delta0 * o, self.beta0 * o
+        """coeffs [ncoef] (device) -> (delta, beta) [n, n, n], differentiable in coeffs."""
+        return SHRenderFunction.apply(coeffs, self)

@@ -52,6 +52,21 @@ class msft_geometry(ctypes.Structure):
     ]
 
 
+class msft_shape_grid(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("nx", ctypes.c_int32),
+        ("ny", ctypes.c_int32),
+        ("nz", ctypes.c_int32),
+        ("dx", ctypes.c_double),
+        ("dy", ctypes.c_double),
+        ("dz", ctypes.c_double),
+        ("edge", ctypes.c_double),
+        ("delta0", ctypes.c_double),
+        ("beta0", ctypes.c_double),
+    ]
+
+
 class msft_request(ctypes.Structure):
     _fields_ = [
         ("plan", ctypes.c_void_p),
@@ -83,13 +98,20 @@ def _load():
     lib.msft_batch_query.argtypes = [P(msft_request), I32, P(S)]
     lib.msft_simulate_batch.argtypes = [P(msft_request), I32, VP, S, VP]
     lib.msft_backward.argtypes = [VP, VP, VP, VP, VP, VP, VP, VP, VP]
+    D = ctypes.c_double
+    lib.msft_render_sh.argtypes = [P(msft_shape_grid), I32, D, VP, VP, VP, VP]
+    lib.msft_render_sh_query.argtypes = [I32, P(S)]
+    lib.msft_render_sh_backward.argtypes = [P(msft_shape_grid), I32, D, VP, VP, VP, VP, VP, S, VP]
+    lib.msft_render_ellipsoid.argtypes = [P(msft_shape_grid), VP, VP, VP, VP, VP]
     lib.msft_status_str.argtypes = [ctypes.c_int]
     lib.msft_status_str.restype = ctypes.c_char_p
     lib.msft_last_error.argtypes = []
     lib.msft_last_error.restype = ctypes.c_char_p
     for name in ("msft_plan", "msft_plan_qlist", "msft_plan_destroy", "msft_plan_query",
                  "msft_plan_qmap", "msft_plan_grid", "msft_simulate", "msft_simulate_scan",
-                 "msft_simulate_contract", "msft_pixel_block", "msft_batch_query", "msft_simulate_batch", "msft_backward"):
+                 "msft_simulate_contract", "msft_pixel_block", "msft_batch_query", "msft_simulate_batch",
+                 "msft_backward", "msft_render_sh", "msft_render_sh_query", "msft_render_sh_backward",
+                 "msft_render_ellipsoid"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -101,7 +123,8 @@ LIBRARY_PATH = _build.LIB
 EXPORTS = ("msft_plan", "msft_plan_qlist", "msft_plan_destroy", "msft_plan_query", "msft_plan_qmap",
            "msft_plan_grid", "msft_simulate", "msft_simulate_scan", "msft_simulate_contract", "msft_pixel_block",
            "msft_batch_query",
-           "msft_simulate_batch", "msft_backward", "msft_status_str", "msft_last_error")
+           "msft_simulate_batch", "msft_backward", "msft_render_sh", "msft_render_sh_query",
+           "msft_render_sh_backward", "msft_render_ellipsoid", "msft_status_str", "msft_last_error")
 
 
 def msft_status_str(status: int) -> str:
@@ -316,3 +339,40 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def make_shape_grid(grid, pitch, edge=0.0, delta0=0.01, beta0=0.02) -> msft_shape_grid:
+    """Fill an msft_shape_grid (grid = (nx, ny, nz), pitch = (dx, dy, dz))."""
+    g = msft_shape_grid()
+    g.struct_size = ctypes.sizeof(msft_shape_grid)
+    g.nx, g.ny, g.nz = (int(v) for v in grid)
+    g.dx, g.dy, g.dz = (float(v) for v in pitch)
+    g.edge, g.delta0, g.beta0 = float(edge), float(delta0), float(beta0)
+    return g
+
+
+def msft_render_sh(shape_grid, lmax, r0, coeffs, delta, beta, stream=None) -> None:
+    _check(_lib.msft_render_sh(ctypes.byref(shape_grid), int(lmax), float(r0), _ptr(coeffs),
+                               _ptr(delta), _ptr(beta), _stream(stream)), "msft_render_sh")
+
+
+def msft_render_sh_query(lmax) -> int:
+    n = ctypes.c_size_t()
+    _check(_lib.msft_render_sh_query(int(lmax), ctypes.byref(n)), "msft_render_sh_query")
+    return n.value
+
+
+def msft_render_sh_backward(shape_grid, lmax, r0, coeffs, grad_delta, grad_beta, grad_coeffs,
+                            workspace, stream=None) -> None:
+    _check(_lib.msft_render_sh_backward(ctypes.byref(shape_grid), int(lmax), float(r0), _ptr(coeffs),
+                                        _ptr(grad_delta), _ptr(grad_beta), _ptr(grad_coeffs),
+                                        _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                        _stream(stream)), "msft_render_sh_backward")
+
+
+def msft_render_ellipsoid(shape_grid, axes, rot, delta, beta, stream=None) -> None:
+    ax = np.ascontiguousarray(axes, dtype=np.float64).reshape(3)
+    R = np.ascontiguousarray(rot, dtype=np.float64).reshape(9)
+    _check(_lib.msft_render_ellipsoid(ctypes.byref(shape_grid), ax.ctypes.data_as(ctypes.c_void_p),
+                                      R.ctypes.data_as(ctypes.c_void_p), _ptr(delta), _ptr(beta),
+                                      _stream(stream)), "msft_render_ellipsoid")

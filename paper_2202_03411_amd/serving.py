@@ -294,34 +294,29 @@ SERVE_DETS = (256, 512, 1024)
 
 
 class ShapePool:
-    """A few hard-voxel shapes per grid size, rendered on the GPU from seeds:
-    ellipsoids (semi-axes U[80, 250] nm, Haar-random orientation) and l <= 8
-    harmonic bodies (R0 ~ U[80, 170] nm, c ~ N(0, 0.08^2), r_max <= 340 nm),
+    """A few hard-voxel shapes per grid size, rendered on the GPU by the library
+    from seeds: ellipsoids (semi-axes U[80, 250] nm, Haar-random orientation) and
+    l <= 8 harmonic bodies (R0 ~ U[80, 170] nm, c ~ N(0, 0.08^2), r_max <= 340 nm),
     all in one fixed box so that a (grid, detector) pair shares one plan."""
 
     def __init__(self, torch, grids=SERVE_GRIDS, per_kind=2, box=700.0, delta0=0.01, beta0=0.02,
                  seed=0, device="cuda"):
         import numpy as np
 
-        from . import inputs
-        from .fit import real_sh_torch
+        from . import inputs, msft
         self.box = box
         self.shapes = {}
         rng = np.random.default_rng(seed)
         for n in grids:
-            c = (torch.arange(n, dtype=torch.float32, device=device) * 2.0 + 1.0 - n) * (box / n) / 2.0
-            X, Y, Z = torch.meshgrid(c, c, c, indexing="ij")
-            rr = torch.sqrt(X * X + Y * Y + Z * Z)
-            theta = torch.arccos(torch.clamp(Z / torch.where(rr > 0, rr, torch.ones_like(rr)), -1, 1))
-            phi = torch.atan2(Y, X)
-            basis = real_sh_torch(8, theta, phi).reshape(81, -1)
+            g = msft.make_shape_grid((n, n, n), (box / n,) * 3, 0.0, delta0, beta0)
             lst = []
             for _ in range(per_kind):
                 axes = rng.uniform(80.0, 250.0, size=3)
-                R = torch.tensor(inputs.haar_rotation(rng), dtype=torch.float32, device=device)
-                P = torch.stack([X, Y, Z], dim=-1) @ R
-                s = sum((P[..., k] / float(axes[k])) ** 2 for k in range(3))
-                lst.append((s <= 1.0).float())
+                R = inputs.haar_rotation(rng)
+                d = torch.empty((n, n, n), dtype=torch.float32, device=device)
+                b = torch.empty_like(d)
+                msft.msft_render_ellipsoid(g, axes, R, d, b)
+                lst.append((d, b))
             for _ in range(per_kind):
                 while True:
                     r0 = float(rng.uniform(80.0, 170.0))
@@ -329,13 +324,15 @@ class ShapePool:
                     _, rmax = inputs.sh_radius_range(coeffs, r0, 91, 181)
                     if rmax <= 340.0:
                         break
-                cvec = torch.zeros(81, dtype=torch.float32, device=device)
+                cvec = np.zeros(81, np.float32)
                 for l, m, v in coeffs:
                     cvec[l * l + l + m] = v
-                rs = r0 * (1.0 + cvec @ basis)
-                lst.append((rr.reshape(-1) <= rs).float().reshape(n, n, n))
-            self.shapes[n] = [((o * delta0).contiguous(), (o * beta0).contiguous()) for o in lst]
-            del basis
+                c = torch.from_numpy(cvec).to(device)
+                d = torch.empty((n, n, n), dtype=torch.float32, device=device)
+                b = torch.empty_like(d)
+                msft.msft_render_sh(g, 8, r0, c, d, b)
+                lst.append((d, b))
+            self.shapes[n] = lst
 
     def pick(self, n, k):
         return self.shapes[n][k % len(self.shapes[n])]

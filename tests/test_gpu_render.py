@@ -1,0 +1,147 @@
+"""GPU shape renderers against the FP64 oracle's renderers (Sec. 5.2 shapes).
+
+Soft occupancies: the library evaluates directions and harmonic sums in FP64
+and writes FP32, so delta and beta agree to FP32 rounding (bound 1e-6 of the
+optical constant).  Hard occupancies agree voxel for voxel.  The coefficient
+gradient is summed in FP32 per thread and FP64 across workgroups: relative L2
+1e-4 against the oracle's FP64 sum.
+"""
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2202_03411_amd import fit, msft
+    return torch, msft, fit
+
+
+def _coeffs(lmax, seed, sigma=0.08):
+    c = np.random.default_rng(seed).normal(0.0, sigma, (lmax + 1) ** 2)
+    c[0] = 0.0
+    return c
+
+
+def _render(env, grid, pitch, lmax, r0, c, edge, d0=0.01, b0=0.02):
+    torch, msft, _ = env
+    g = msft.make_shape_grid(grid, pitch, edge, d0, b0)
+    d = torch.full(grid, float("nan"), device="cuda")
+    b = torch.full(grid, float("nan"), device="cuda")
+    msft.msft_render_sh(g, lmax, r0, torch.tensor(c, dtype=torch.float32, device="cuda"), d, b)
+    torch.cuda.synchronize()
+    return d.cpu().numpy().astype(np.float64), b.cpu().numpy().astype(np.float64)
+
+
+CASES = [
+    # (grid, pitch, lmax, r0, edge, seed)
+    ((33, 30, 37), (6.0, 6.5, 5.5), 8, 70.0, 6.0, 1),
+    ((40, 40, 40), (5.0, 5.0, 5.0), 12, 60.0, 2.5, 2),
+    ((17, 9, 50), (8.0, 9.0, 3.0), 3, 45.0, 4.0, 3),
+    ((1, 1, 1), (5.0, 5.0, 5.0), 0, 10.0, 1.0, 4),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"l{c[2]}_{c[0][0]}" for c in CASES])
+def test_render_sh_soft_and_hard(env, case):
+    grid, pitch, lmax, r0, edge, seed = case
+    c = _coeffs(lmax, seed)
+    # the coefficients the library sees are float32: give the oracle the same values
+    c32 = c.astype(np.float32).astype(np.float64)
+    print(f"[gpu] render_sh grid={grid} lmax={lmax}", flush=True)
+    for e in (edge, 0.0):
+        d, b = _render(env, grid, pitch, lmax, r0, c32, e)
+        od, ob = oracle.render_sh(grid, pitch, c32, r0, e, 0.01, 0.02)
+        if e > 0.0:
+            assert np.max(np.abs(d - od)) <= 1e-6 * 0.01
+            assert np.max(np.abs(b - ob)) <= 1e-6 * 0.02
+        else:
+            assert np.array_equal(d, od.astype(np.float32)) and np.array_equal(b, ob.astype(np.float32))
+            print(f"  hard: {int((od > 0).sum())} voxels inside, identical")
+
+
+def test_render_ellipsoid(env):
+    torch, msft, _ = env
+    grid, pitch = (36, 31, 40), (6.0, 7.0, 5.0)
+    R, _ = np.linalg.qr(np.random.default_rng(5).normal(size=(3, 3)))
+    ax = np.array([90.0, 60.0, 45.0])
+    for edge in (0.0, 4.0):
+        g = msft.make_shape_grid(grid, pitch, edge, 0.01, 0.02)
+        d = torch.full(grid, float("nan"), device="cuda")
+        b = torch.full(grid, float("nan"), device="cuda")
+        msft.msft_render_ellipsoid(g, ax, R, d, b)
+        torch.cuda.synchronize()
+        d, b = d.cpu().numpy().astype(np.float64), b.cpu().numpy().astype(np.float64)
+        od, ob = oracle.render_ellipsoid(grid, pitch, ax, R, edge, 0.01, 0.02)
+        if edge == 0.0:
+            assert np.array_equal(d, od.astype(np.float32)) and np.array_equal(b, ob.astype(np.float32))
+        else:
+            assert np.max(np.abs(d - od)) <= 1e-8 and np.max(np.abs(b - ob)) <= 2e-8
+
+
+@pytest.mark.parametrize("lmax,seed", [(8, 6), (12, 7), (2, 8)])
+def test_render_sh_backward_matches_oracle(env, lmax, seed):
+    torch, msft, _ = env
+    grid, pitch, r0, edge = (40, 36, 44), (5.0, 5.5, 4.5), 70.0, 5.0
+    c = _coeffs(lmax, seed).astype(np.float32).astype(np.float64)
+    rng = np.random.default_rng(seed + 100)
+    gd = rng.normal(size=grid).astype(np.float32)
+    gb = rng.normal(size=grid).astype(np.float32)
+    g = msft.make_shape_grid(grid, pitch, edge, 0.01, 0.02)
+    ct = torch.tensor(c, dtype=torch.float32, device="cuda")
+    out = torch.full_like(ct, float("nan"))
+    ws = msft.workspace_tensor(msft.msft_render_sh_query(lmax), "cuda")
+    msft.msft_render_sh_backward(g, lmax, r0, ct, torch.from_numpy(gd).cuda(),
+                                 torch.from_numpy(gb).cuda(), out, ws)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64)
+    ref = oracle.render_sh_backward(grid, pitch, c, r0, edge, 0.01, 0.02, gd.astype(np.float64),
+                                    gb.astype(np.float64))
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print(f"  lmax {lmax}: coefficient gradient rel L2 {err:.3e}")
+    assert err <= 1e-4
+    # the sum order is fixed: a second call gives the same bits
+    again = torch.full_like(ct, float("nan"))
+    msft.msft_render_sh_backward(g, lmax, r0, ct, torch.from_numpy(gd).cuda(),
+                                 torch.from_numpy(gb).cuda(), again, ws)
+    assert torch.equal(out, again)
+
+
+def test_softstar_autograd_matches_oracle(env):
+    # SoftStar.voxelize under autograd: d/dc of sum(gd * delta + gb * beta)
+    torch, msft, fit = env
+    star = fit.SoftStar(32, 400.0, 6, r0=120.0)
+    c = torch.tensor(_coeffs(6, 9), dtype=torch.float32, device="cuda", requires_grad=True)
+    rng = np.random.default_rng(10)
+    gd = torch.tensor(rng.normal(size=star.shape), dtype=torch.float32, device="cuda")
+    gb = torch.tensor(rng.normal(size=star.shape), dtype=torch.float32, device="cuda")
+    d, b = star.voxelize(c)
+    (gd * d + gb * b).sum().backward()
+    c64 = c.detach().double().cpu().numpy()
+    ref = oracle.render_sh_backward(star.shape, (star.pitch,) * 3, c64, 120.0, star.eps, 0.01, 0.02,
+                                    gd.double().cpu().numpy(), gb.double().cpu().numpy())
+    err = np.linalg.norm(c.grad.double().cpu().numpy() - ref) / np.linalg.norm(ref)
+    print(f"  autograd through the renderer: rel L2 {err:.3e}")
+    assert err <= 1e-4
+
+
+def test_render_argument_errors(env):
+    torch, msft, _ = env
+    g = msft.make_shape_grid((8, 8, 8), (5.0, 5.0, 5.0), 0.0)
+    d = torch.empty((8, 8, 8), device="cuda")
+    c = torch.zeros(4, device="cuda")
+    with pytest.raises(msft.MSFTError):
+        msft.msft_render_sh(g, 13, 10.0, c, d, d)           # lmax beyond 12
+    with pytest.raises(msft.MSFTError):
+        msft.msft_render_sh(g, 1, -1.0, c, d, d)            # r0 <= 0
+    ws = msft.workspace_tensor(msft.msft_render_sh_query(1), "cuda")
+    with pytest.raises(msft.MSFTError):
+        msft.msft_render_sh_backward(g, 1, 10.0, c, d, d, c, ws)   # hard edge has no gradient
+    with pytest.raises(msft.MSFTError):
+        msft.msft_render_ellipsoid(g, [1.0, -2.0, 3.0], np.eye(3), d, d)
