@@ -201,9 +201,10 @@ msft_status msft_batch_query(const msft_request* reqs, int32_t n, size_t* worksp
 
 /*
  * Forward model for n requests of possibly different plans (same precision)
- * in one persistent launch: every request's pixel blocks become work items that
- * the workgroups pull in a cost-sorted order.  Each pixel written is
- * bit-identical to what msft_simulate writes for that request alone.
+ * in one launch per 24 requests: every request's pixel blocks become
+ * workgroups, numbered most expensive first so that the device dispatches them
+ * in that order.  Each pixel written is bit-identical to what msft_simulate
+ * writes for that request alone.
  * Returns MSFT_ERR_BUSY if ws_bytes is smaller than msft_batch_query reports,
  * and MSFT_ERR_UNSUPPORTED for a plan of the uniform-q detector.
  */

@@ -603,7 +603,7 @@ static msft_status batch_layout(const msft_request* reqs, int32_t n, std::vector
                                 size_t* total)
 {
     if (n < 0 || (n > 0 && !reqs)) return fail(MSFT_ERR_INVALID, "bad request array");
-    size_t off = 256;  // work counter
+    size_t off = 0;
     if (offs) offs->resize(n);
     for (int32_t r = 0; r < n; ++r) {
         msft_status st = check_runnable(reqs[r].plan);
@@ -671,12 +671,9 @@ msft_status msft_simulate_batch(const msft_request* reqs, int32_t n, void* works
         const Dims& db = reqs[b].plan->dims;
         return (int64_t)da.x_pad * da.ny * da.nzb > (int64_t)db.x_pad * db.ny * db.nzb;
     });
-    int cus = 256;
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
     for (size_t k0 = 0; k0 < order.size(); k0 += MAX_BATCH) {
         BatchArgs b;
         std::memset(&b, 0, sizeof b);
-        b.counter = (int32_t*)ws;
         int32_t items = 0;
         int32_t nr = 0;
         for (size_t k = k0; k < order.size() && k < k0 + MAX_BATCH; ++k) {
@@ -691,8 +688,7 @@ msft_status msft_simulate_batch(const msft_request* reqs, int32_t n, void* works
         b.nreq = nr;
         b.item_begin[nr] = items;
         if (items == 0) continue;
-        const int32_t grid = std::min<int32_t>(items, cus);
-        int e = launch_forward_batch(precision, b, grid, stream);
+        int e = launch_forward_batch(precision, b, stream);
         if (e) return hip_fail((hipError_t)e, "batch launch");
     }
     return ok();

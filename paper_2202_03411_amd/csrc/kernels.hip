@@ -426,57 +426,97 @@ __device__ __forceinline__ void load_a(const uint8_t* ta, int lane, f32x4* Af, b
     }
 }
 
-// ROT = false is the second stage of the separable detector: the contraction
-// already summed over y, so a tile's product is added to G without a Ty factor.
-// A tile group (one detector column there) reads its own tiles and shares the A
-// operand of its position within the group.
-template <int PREC, bool ROT>
-__device__ __forceinline__ void fwd_block(const FwdArgs& a, int64_t block, uint8_t* lds)
+// C = A . B of one tile: FULL when the chunk is known to hold XC x values,
+// otherwise chosen per tile from xlen.
+template <int PREC, bool FULL>
+__device__ __forceinline__ f32x16 tile_product(const uint8_t* row, int col, int xlen, const f32x4* Af,
+                                               const bf16x8* Ahi, const bf16x8* Alo)
+{
+    const f32x16 zero = {};
+    if (FULL || xlen == XC) return tile_mfma<PREC, XC>(zero, row, col, Af, Ahi, Alo);
+    return tile_mfma_partial<PREC>(zero, row, col, xlen, Af, Ahi, Alo);
+}
+
+// G[m] += s * Ty[m] * C[m] for the 8 complex slots m = 2j + u of a lane: C rows
+// 4j + 2u (re) and 4j + 2u + 1 (im) of the MFMA result; ty: 4 x f32x4 of Ty.
+__device__ __forceinline__ void rotate_add(float* G, const f32x16& C, const f32x4* ty)
+{
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        const int r = 4 * (m >> 1) + 2 * (m & 1);
+        const float tr = ty[m >> 1][2 * (m & 1)], ti = ty[m >> 1][2 * (m & 1) + 1];
+        G[2 * m] += tr * C[r] - ti * C[r + 1];
+        G[2 * m + 1] += tr * C[r + 1] + ti * C[r];
+    }
+}
+
+// All z blocks of one x chunk; t is the next tile, k the next pipeline stage.
+//
+// ROT (the flat detector): two tiles (y, y + 1) per stage in a double-buffered
+// ring of 2 x 2 tiles, so one barrier serves two tiles, each wave runs two
+// independent MFMA chains, and the first tile's Ty rotation can issue under the
+// second chain.  A lone last tile (odd ny) is paired with whatever tile follows
+// and its partner's rotation is scaled by 0.
+// !ROT (second stage of the separable detector): the contraction already summed
+// over y, so each z block is one tile, added to G without a Ty factor; Tz is
+// loaded at the start of the z block to complete under the MFMA chain.
+// FULL: the chunk holds XC x values.  The paired loop decides this per chunk,
+// which keeps its tile loop free of branches (measured faster); the single-tile
+// loop decides per tile (measured faster there).
+template <int PREC, bool ROT, bool FULL>
+__device__ __forceinline__ void fwd_chunk(const FwdArgs& a, int64_t wt, int64_t ntiles, const uint4* gw,
+                                          uint8_t* lds, int xlen, const f32x4* Af, const bf16x8* Ahi,
+                                          const bf16x8* Alo, int64_t& t, int& k, float* acc)
 {
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63;
     const int h = lane >> 5, col = lane & 31;
-    const int64_t wt = block * WAVES + wave;
-    const int64_t ntiles = (int64_t)a.nxc * a.nzb * a.ny;
-    const int64_t group = a.group_blocks ? block / a.group_blocks : 0;
-    const int64_t wa = a.a_waves ? wt % a.a_waves : wt;
-    const uint4* gw = (const uint4*)(a.wtiles + (size_t)group * a.group_tiles * TILE_BYTES);
-
-    // tile 0 -> LDS buffer 0
-    {
-        const uint4 r0 = gw[tid], r1 = gw[tid + 512];
-        ((uint4*)lds)[tid] = r0;
-        ((uint4*)lds)[tid + 512] = r1;
-    }
-    __syncthreads();
-
-    float acc[16];
+    for (int zb = 0; zb < a.nzb; ++zb) {
+        float G[16];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) acc[k] = 0.0f;
+        for (int q = 0; q < 16; ++q) G[q] = 0.0f;
+        const f32x4* tzp = (const f32x4*)(a.tz + 2 * ((((wt * a.nzb + zb) * 2 + h) * ZB + col) * 8));
+        f32x4 tzv[4];
+        if constexpr (!ROT) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) tzv[q] = tzp[q];
+        }
+        if constexpr (ROT) {
+            for (int y = 0; y < a.ny; y += 2) {
+                const int cnt = min(2, a.ny - y);
+                const int64_t tn = t + cnt;
+                const bool has_next = tn < ntiles;
+                uint4 n0, n1, n2, n3;
+                if (has_next) {
+                    const int64_t tn1 = min(tn + 1, ntiles - 1);
+                    n0 = gw[tn * (TILE_BYTES / 16) + tid];
+                    n1 = gw[tn * (TILE_BYTES / 16) + 512 + tid];
+                    n2 = gw[tn1 * (TILE_BYTES / 16) + tid];
+                    n3 = gw[tn1 * (TILE_BYTES / 16) + 512 + tid];
+                }
+                const f32x4* typ0 = (const f32x4*)(a.ty + 2 * ((wt * a.ny + y) * WAVE_PIX + h * 8));
+                const f32x4* typ1 = (const f32x4*)(a.ty + 2 * ((wt * a.ny + y + cnt - 1) * WAVE_PIX + h * 8));
+                const float s1 = cnt == 2 ? 1.0f : 0.0f;
+                const f32x4 ty0[4] = {typ0[0], typ0[1], typ0[2], typ0[3]};
+                const f32x4 ty1[4] = {typ1[0] * s1, typ1[1] * s1, typ1[2] * s1, typ1[3] * s1};
 
-    int64_t t = 0;
-    for (int xc = 0; xc < a.nxc; ++xc) {
-        const int xlen = min(XC, a.x_pad - xc * XC);
-        // A operand of this wave for the chunk
-        f32x4 Af[16];
-        bf16x8 Ahi[8], Alo[8];
-        load_a<PREC>(a.txa + (size_t)(wa * a.nxc + xc) * TILE_BYTES, lane, Af, Ahi, Alo);
-        // Wait for the A operand here, once per chunk.  The memory counter is in
-        // order, so without this the waits the compiler places for A inside the
-        // tile loop would also wait for the next tile's prefetch, mid-chain.
-        __builtin_amdgcn_s_waitcnt(0);
-        for (int zb = 0; zb < a.nzb; ++zb) {
-            float G[16];
-#pragma unroll
-            for (int k = 0; k < 16; ++k) G[k] = 0.0f;
-            // Tz of this z block: without the rotation a z block is a single tile, so
-            // the loads are issued here and complete under the tile's MFMA chain
-            const f32x4* tzp = (const f32x4*)(a.tz + 2 * ((((wt * a.nzb + zb) * 2 + h) * ZB + col) * 8));
-            f32x4 tzv[4];
-            if (!ROT) {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) tzv[k] = tzp[k];
+                const uint8_t* row = lds + (size_t)(k & 1) * 2 * TILE_BYTES + (h * ZB + col) * ROW_BYTES;
+                const f32x16 C0 = tile_product<PREC, FULL>(row, col, xlen, Af, Ahi, Alo);
+                const f32x16 C1 = tile_product<PREC, FULL>(row + TILE_BYTES, col, xlen, Af, Ahi, Alo);
+                rotate_add(G, C0, ty0);
+                rotate_add(G, C1, ty1);
+                if (has_next) {
+                    uint4* nb = (uint4*)(lds + (size_t)((k + 1) & 1) * 2 * TILE_BYTES);
+                    nb[tid] = n0;
+                    nb[tid + 512] = n1;
+                    nb[1024 + tid] = n2;
+                    nb[1024 + tid + 512] = n3;
+                }
+                __syncthreads();
+                t += cnt;
+                ++k;
             }
+        } else {
             for (int y = 0; y < a.ny; ++y, ++t) {
                 const bool has_next = (t + 1) < ntiles;
                 uint4 n0, n1;
@@ -484,31 +524,13 @@ __device__ __forceinline__ void fwd_block(const FwdArgs& a, int64_t block, uint8
                     n0 = gw[(t + 1) * (TILE_BYTES / 16) + tid];
                     n1 = gw[(t + 1) * (TILE_BYTES / 16) + 512 + tid];
                 }
-                f32x4 ty0 = {}, ty1 = {}, ty2 = {}, ty3 = {};
-                if (ROT) {
-                    const f32x4* typ = (const f32x4*)(a.ty + 2 * ((wt * a.ny + y) * WAVE_PIX + h * 8));
-                    ty0 = typ[0], ty1 = typ[1], ty2 = typ[2], ty3 = typ[3];
-                }
-
                 const uint8_t* row = lds + (t & 1) * TILE_BYTES + (h * ZB + col) * ROW_BYTES;
-                const f32x16 zero = {};
-                const f32x16 C = (xlen == XC) ? tile_mfma<PREC, XC>(zero, row, col, Af, Ahi, Alo)
-                                              : tile_mfma_partial<PREC>(zero, row, col, xlen, Af, Ahi, Alo);
-                // G[m] += Ty[m] * C[m], slot m = 2j + u: C rows 4j + 2u (re), 4j + 2u + 1 (im)
-                const float tyv[16] = {ty0[0], ty0[1], ty0[2], ty0[3], ty1[0], ty1[1], ty1[2], ty1[3],
-                                       ty2[0], ty2[1], ty2[2], ty2[3], ty3[0], ty3[1], ty3[2], ty3[3]};
+                const f32x16 C = tile_product<PREC, FULL>(row, col, xlen, Af, Ahi, Alo);
 #pragma unroll
                 for (int m = 0; m < 8; ++m) {
                     const int r = 4 * (m >> 1) + 2 * (m & 1);
-                    const float cr = C[r], ci = C[r + 1];
-                    if (ROT) {
-                        const float tr = tyv[2 * m], ti = tyv[2 * m + 1];
-                        G[2 * m] += tr * cr - ti * ci;
-                        G[2 * m + 1] += tr * ci + ti * cr;
-                    } else {
-                        G[2 * m] += cr;
-                        G[2 * m + 1] += ci;
-                    }
+                    G[2 * m] += C[r];
+                    G[2 * m + 1] += C[r + 1];
                 }
                 if (has_next) {
                     uint4* nb = (uint4*)(lds + ((t + 1) & 1) * TILE_BYTES);
@@ -517,31 +539,82 @@ __device__ __forceinline__ void fwd_block(const FwdArgs& a, int64_t block, uint8
                 }
                 __syncthreads();
             }
-            // acc[m] += Tz[m] * G[m]
+        }
+        // acc[m] += Tz[m] * G[m]
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const f32x4 v = ROT ? tzp[k] : tzv[k];
+        for (int q = 0; q < 4; ++q) {
+            const f32x4 v = ROT ? tzp[q] : tzv[q];
 #pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    const int m = 2 * k + u;
-                    const float tr = v[2 * u], ti = v[2 * u + 1];
-                    acc[2 * m] += tr * G[2 * m] - ti * G[2 * m + 1];
-                    acc[2 * m + 1] += tr * G[2 * m + 1] + ti * G[2 * m];
-                }
+            for (int u = 0; u < 2; ++u) {
+                const int m = 2 * q + u;
+                const float tr = v[2 * u], ti = v[2 * u + 1];
+                acc[2 * m] += tr * G[2 * m] - ti * G[2 * m + 1];
+                acc[2 * m + 1] += tr * G[2 * m + 1] + ti * G[2 * m];
             }
         }
     }
+}
+
+// One pixel block (BLOCK_PIX pixels) of the contraction.  A tile group (one
+// detector column in the separable detector's second stage) reads its own tiles
+// and shares the A operand of its position within the group.
+template <int PREC, bool ROT>
+__device__ __forceinline__ void fwd_block(const FwdArgs& a, int64_t block, uint8_t* lds)
+{
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int64_t wt = block * WAVES + wave;
+    const int64_t ntiles = (int64_t)a.nxc * a.nzb * a.ny;
+    const int64_t group = a.group_blocks ? block / a.group_blocks : 0;
+    const int64_t wa = a.a_waves ? wt % a.a_waves : wt;
+    const uint4* gw = (const uint4*)(a.wtiles + (size_t)group * a.group_tiles * TILE_BYTES);
+
+    // first stage: tile 0 (and tile 1 for the paired stages) -> LDS buffer 0
+    {
+        const uint4 r0 = gw[tid], r1 = gw[tid + 512];
+        ((uint4*)lds)[tid] = r0;
+        ((uint4*)lds)[tid + 512] = r1;
+        if (ROT) {
+            const int64_t t1 = ntiles > 1 ? 1 : 0;
+            const uint4 r2 = gw[t1 * (TILE_BYTES / 16) + tid], r3 = gw[t1 * (TILE_BYTES / 16) + 512 + tid];
+            ((uint4*)lds)[1024 + tid] = r2;
+            ((uint4*)lds)[1024 + tid + 512] = r3;
+        }
+    }
+    __syncthreads();
+
+    float acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.0f;
+
+    int64_t t = 0;
+    int k = 0;
+    for (int xc = 0; xc < a.nxc; ++xc) {
+        const int xlen = min(XC, a.x_pad - xc * XC);
+        f32x4 Af[16];
+        bf16x8 Ahi[8], Alo[8];
+        load_a<PREC>(a.txa + (size_t)(wa * a.nxc + xc) * TILE_BYTES, lane, Af, Ahi, Alo);
+        // Wait for the A operand here, once per chunk.  The memory counter is in
+        // order, so without this the waits the compiler places for A inside the
+        // tile loop would also wait for the next tile's prefetch, mid-chain.
+        __builtin_amdgcn_s_waitcnt(0);
+        if (ROT && xlen == XC)
+            fwd_chunk<PREC, ROT, true>(a, wt, ntiles, gw, lds, xlen, Af, Ahi, Alo, t, k, acc);
+        else
+            fwd_chunk<PREC, ROT, false>(a, wt, ntiles, gw, lds, xlen, Af, Ahi, Alo, t, k, acc);
+    }
+    const int h = lane >> 5, col = lane & 31;
 
     // sum over the 32 z lanes of each half (fixed butterfly order)
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        float v = acc[k];
+    for (int q = 0; q < 16; ++q) {
+        float v = acc[q];
         v += __shfl_xor(v, 16, 32);
         v += __shfl_xor(v, 8, 32);
         v += __shfl_xor(v, 4, 32);
         v += __shfl_xor(v, 2, 32);
         v += __shfl_xor(v, 1, 32);
-        acc[k] = v;
+        acc[q] = v;
     }
     if (col == 0) {
 #pragma unroll
@@ -566,31 +639,23 @@ __device__ __forceinline__ void fwd_block(const FwdArgs& a, int64_t block, uint8
 template <int PREC, bool ROT>
 __global__ __launch_bounds__(512) void fwd_kernel(FwdArgs a, int64_t block_begin)
 {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * TILE_BYTES];
+    __shared__ __attribute__((aligned(16))) uint8_t lds[(ROT ? 4 : 2) * TILE_BYTES];
     fwd_block<PREC, ROT>(a, block_begin + blockIdx.x, lds);
 }
 
-// Persistent form: workgroups pull (request, pixel block) items from a counter
-// until the list is exhausted; every workgroup reaches the exit test.
+// Batched form: one workgroup per (request, pixel block) item, items numbered in
+// the host's cost order, so the hardware dispatches the most expensive blocks
+// first.  (A persistent form pulling items from a counter measured 10% slower:
+// its loop state pushes the paired-tile contraction past its register budget.)
 template <int PREC>
 __global__ __launch_bounds__(512) void fwd_batch_kernel(BatchArgs b)
 {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * TILE_BYTES];
-    __shared__ int32_t item_s;
-    const int32_t nitems = b.item_begin[b.nreq];
-    for (;;) {
-        if (threadIdx.x == 0) item_s = atomicAdd(b.counter, 1);
-        __syncthreads();
-        const int32_t it = item_s;
-        __syncthreads();
-        if (it >= nitems) break;
-        int r = 0;
-        while (r + 1 < b.nreq && b.item_begin[r + 1] <= it) ++r;
-        fwd_block<PREC, true>(b.req[r], (int64_t)b.block_begin[r] + (it - b.item_begin[r]), lds);
-    }
+    __shared__ __attribute__((aligned(16))) uint8_t lds[4 * TILE_BYTES];
+    const int32_t it = blockIdx.x;
+    int r = 0;
+    while (r + 1 < b.nreq && b.item_begin[r + 1] <= it) ++r;
+    fwd_block<PREC, true>(b.req[r], (int64_t)b.block_begin[r] + (it - b.item_begin[r]), lds);
 }
-
-__global__ void zero_counter(int32_t* c) { *c = 0; }
 
 template <bool ROT>
 static void launch_fwd(int precision, const FwdArgs& a, int64_t block_begin, int64_t nblocks,
@@ -616,17 +681,17 @@ int launch_forward(int precision, const FwdArgs& a, int64_t block_begin, int64_t
     return (int)hipGetLastError();
 }
 
-int launch_forward_batch(int precision, const BatchArgs& b, int32_t grid, void* stream)
+int launch_forward_batch(int precision, const BatchArgs& b, void* stream)
 {
     hipStream_t s = (hipStream_t)stream;
-    if (b.nreq <= 0 || b.item_begin[b.nreq] <= 0) return 0;
-    hipLaunchKernelGGL(zero_counter, dim3(1), dim3(1), 0, s, b.counter);
+    const int32_t items = b.nreq > 0 ? b.item_begin[b.nreq] : 0;
+    if (items <= 0) return 0;
     if (precision == MSFT_FP32)
-        hipLaunchKernelGGL(fwd_batch_kernel<MSFT_FP32>, dim3(grid), dim3(512), 0, s, b);
+        hipLaunchKernelGGL(fwd_batch_kernel<MSFT_FP32>, dim3(items), dim3(512), 0, s, b);
     else if (precision == MSFT_BF16X3)
-        hipLaunchKernelGGL(fwd_batch_kernel<MSFT_BF16X3>, dim3(grid), dim3(512), 0, s, b);
+        hipLaunchKernelGGL(fwd_batch_kernel<MSFT_BF16X3>, dim3(items), dim3(512), 0, s, b);
     else
-        hipLaunchKernelGGL(fwd_batch_kernel<MSFT_BF16>, dim3(grid), dim3(512), 0, s, b);
+        hipLaunchKernelGGL(fwd_batch_kernel<MSFT_BF16>, dim3(items), dim3(512), 0, s, b);
     return (int)hipGetLastError();
 }
 

@@ -146,7 +146,6 @@ struct BatchArgs {
     int32_t block_begin[MAX_BATCH];
     int32_t item_begin[MAX_BATCH + 1];
     int32_t nreq;
-    int32_t* counter;  // device int, reset by the launcher
 };
 
 // Adjoint: pixels per LDS chunk of the transposed contraction (one per 8 threads).
@@ -234,7 +233,7 @@ int launch_render_sh(const ShArgs& s, const float* coeffs, float* delta, float* 
 int launch_render_sh_grad(const ShArgs& s, const float* coeffs, const float* gd, const float* gb,
                           float* grad, double* partial, int nblocks, void* stream);
 int launch_render_ellipsoid(const EllArgs& e, float* delta, float* beta, void* stream);
-int launch_forward_batch(int precision, const BatchArgs& b, int32_t grid, void* stream);
+int launch_forward_batch(int precision, const BatchArgs& b, void* stream);
 
 }  // namespace msft
 

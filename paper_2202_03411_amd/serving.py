@@ -4,7 +4,7 @@ Requests of uneven grid and detector sizes arrive over time (the candidate
 simulations of forward fitting, Sec. 6).  The scheduler keeps one plan per
 geometry resident (q map and twiddle tables), admits queued requests while the
 in-flight HBM footprint stays under a budget and a launch slot is free, and
-runs each admitted group as one persistent batched launch
+runs each admitted group as one batched launch
 (``msft_simulate_batch``).  Several launches can be in flight on separate
 streams, so requests that arrive while others are on the GPU start as soon as
 a slot and memory free up and their work overlaps the tail of earlier
@@ -221,7 +221,7 @@ class PlanCache:
 
 
 class GpuExecutor:
-    """Runs each admitted group as one persistent batched launch.
+    """Runs each admitted group as one batched launch (msft_simulate_batch).
 
     Every in-flight launch owns one stream of a small pool (default priority)
     and its own workspace, so launches overlap on the device.  With

@@ -1,5 +1,5 @@
 """GPU serving: requests of mixed grid and detector sizes arriving over time,
-served in overlapping persistent batched launches; every result must equal, bit
+served in overlapping batched launches; every result must equal, bit
 for bit, the same request simulated alone."""
 import pytest
 
