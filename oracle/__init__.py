@@ -55,9 +55,11 @@ def _load():
         lib.oracle_render_sh_backward.argtypes = [i32, i32, i32, d, d, d, i32, p, d, d, d, d,
                                                   p, p, p]
         lib.oracle_render_ellipsoid.argtypes = [i32, i32, i32, d, d, d, p, p, d, d, d, p, p]
+        lib.oracle_render_volume.argtypes = [i32, i32, i32, d, d, d, i32, i32, i32, d, d, d, p, p, p, p]
         lib.oracle_threads.argtypes = []
         lib.oracle_threads.restype = ctypes.c_int
         for f in (lib.oracle_render_sh, lib.oracle_render_sh_backward, lib.oracle_render_ellipsoid,
+                  lib.oracle_render_volume,
                   lib.oracle_qmap, lib.oracle_qmap_uniform, lib.oracle_grid, lib.oracle_strength,
                   lib.oracle_amplitude, lib.oracle_backward):
             f.restype = None
@@ -205,4 +207,19 @@ def render_ellipsoid(grid, pitch, axes, rot, edge: float, delta0: float, beta0: 
     b = np.empty((nx, ny, nz), np.float64)
     _load().oracle_render_ellipsoid(nx, ny, nz, dx, dy, dz, _ptr(ax), _ptr(R), float(edge),
                                     float(delta0), float(beta0), _ptr(d), _ptr(b))
+    return d, b
+
+
+def render_volume(grid, pitch, src_delta, src_beta, src_pitch):
+    """A (delta, beta) volume map on its own centred grid resampled at the centres of
+    `grid` by trilinear interpolation, zero beyond the source grid."""
+    sd, sb = _f64(src_delta), _f64(src_beta)
+    sx, sy, sz = sd.shape
+    nx, ny, nz = (int(v) for v in grid)
+    dx, dy, dz = (float(v) for v in pitch)
+    sdx, sdy, sdz = (float(v) for v in src_pitch)
+    d = np.empty((nx, ny, nz), np.float64)
+    b = np.empty((nx, ny, nz), np.float64)
+    _load().oracle_render_volume(nx, ny, nz, dx, dy, dz, sx, sy, sz, sdx, sdy, sdz, _ptr(sd),
+                                 _ptr(sb), _ptr(d), _ptr(b))
     return d, b

@@ -503,3 +503,47 @@ void oracle_render_ellipsoid(int32_t nx, int32_t ny, int32_t nz, double dx, doub
         }
     }
 }
+
+/*
+ * Volume map: delta, beta given on a source grid (sx, sy, sz voxels of pitch sd*, centred
+ * on the origin) resampled at the centres of the target grid by trilinear interpolation
+ * between source voxel centres, with zero beyond the source grid.
+ */
+static double oracle_volume_at(const double* src, int32_t sx, int32_t sy, int32_t sz, double fx,
+                               double fy, double fz)
+{
+    const double ax = floor(fx), ay = floor(fy), az = floor(fz);
+    const double wx = fx - ax, wy = fy - ay, wz = fz - az;
+    double v = 0.0;
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int k = 0; k < 2; ++k) {
+                const int64_t a = (int64_t)ax + i, b = (int64_t)ay + j, c = (int64_t)az + k;
+                if (a < 0 || a >= sx || b < 0 || b >= sy || c < 0 || c >= sz) continue;
+                const double w = (i ? wx : 1.0 - wx) * (j ? wy : 1.0 - wy) * (k ? wz : 1.0 - wz);
+                v += w * src[(a * sy + b) * sz + c];
+            }
+    return v;
+}
+
+void oracle_render_volume(int32_t nx, int32_t ny, int32_t nz, double dx, double dy, double dz,
+                          int32_t sx, int32_t sy, int32_t sz, double sdx, double sdy, double sdz,
+                          const double* sd, const double* sb, double* delta, double* beta)
+{
+#pragma omp parallel for schedule(static)
+    for (int32_t a = 0; a < nx; ++a) {
+        const double x = ((double)(2 * a + 1 - nx) * dx) / 2.0;
+        const double fx = x / sdx + (sx - 1) / 2.0;
+        for (int32_t b = 0; b < ny; ++b) {
+            const double y = ((double)(2 * b + 1 - ny) * dy) / 2.0;
+            const double fy = y / sdy + (sy - 1) / 2.0;
+            for (int32_t k = 0; k < nz; ++k) {
+                const double z = ((double)(2 * k + 1 - nz) * dz) / 2.0;
+                const double fz = z / sdz + (sz - 1) / 2.0;
+                const int64_t v = ((int64_t)a * ny + b) * nz + k;
+                delta[v] = oracle_volume_at(sd, sx, sy, sz, fx, fy, fz);
+                beta[v] = oracle_volume_at(sb, sx, sy, sz, fx, fy, fz);
+            }
+        }
+    }
+}

@@ -45,6 +45,7 @@ class Batch:
     handle: object
     footprint: int
     launched: float
+    large: bool = False
 
 
 class Scheduler:
@@ -60,11 +61,15 @@ class Scheduler:
     Every request of a launch completes when the launch does, so a launch groups
     queued requests only up to max_batch_cost of work (at least one request):
     cheap requests share a launch, an expensive one runs in its own, and the
-    launches in flight share the device.
+    launches in flight share the device.  With one_large, at most one launch of
+    an expensive request (cost above max_batch_cost) is in flight: expensive
+    requests run one after another in arrival order instead of slowing each
+    other down, while cheap requests behind a waiting expensive one may start.
     """
 
     def __init__(self, executor, hbm_budget: int, max_inflight: int = 3, max_batch: int = 24,
-                 clock: Callable[[], float] = time.perf_counter, max_batch_cost=None):
+                 clock: Callable[[], float] = time.perf_counter, max_batch_cost=None,
+                 one_large: bool = False):
         if max_inflight < 1 or max_batch < 1:
             raise ValueError("max_inflight and max_batch must be >= 1")
         self.ex = executor
@@ -72,6 +77,7 @@ class Scheduler:
         self.max_inflight = max_inflight
         self.max_batch = max_batch
         self.max_batch_cost = max_batch_cost
+        self.one_large = bool(one_large) and max_batch_cost is not None
         self.clock = clock
         self.queue: collections.deque = collections.deque()
         self.inflight: list = []
@@ -103,18 +109,32 @@ class Scheduler:
                 still.append(b)
         self.inflight = still
 
+    def _large(self, r):
+        return self.max_batch_cost is not None and r.cost > self.max_batch_cost
+
     def admit_and_launch(self):
-        """Form at most one batch from the head of the queue (FIFO, no overtaking)."""
+        """Form at most one batch from the head of the queue (FIFO; with one_large,
+        cheap requests may pass an expensive one that waits for the running one)."""
         if len(self.inflight) >= self.max_inflight or not self.queue:
             return None
+        start = 0
+        large_busy = self.one_large and any(b.large for b in self.inflight)
+        if large_busy:
+            while start < len(self.queue) and self._large(self.queue[start]):
+                start += 1
+            if start == len(self.queue):
+                return None
         batch, foot, cost = [], 0, 0.0
-        while self.queue and len(batch) < self.max_batch:
-            r = self.queue[0]
+        while start < len(self.queue) and len(batch) < self.max_batch:
+            r = self.queue[start]
             if self.used + foot + r.footprint > self.budget:
                 break
             if batch and self.max_batch_cost is not None and cost + r.cost > self.max_batch_cost:
                 break
-            batch.append(self.queue.popleft())
+            if large_busy and self._large(r):
+                break
+            batch.append(r)
+            del self.queue[start]
             foot += r.footprint
             cost += r.cost
         if not batch:
@@ -123,7 +143,7 @@ class Scheduler:
         for r in batch:
             r.admitted = now
         handle = self.ex.launch(batch)
-        b = Batch(batch, handle, foot, now)
+        b = Batch(batch, handle, foot, now, any(self._large(r) for r in batch))
         self.inflight.append(b)
         self.used += foot
         return b
@@ -362,13 +382,14 @@ TERMS_PER_S = {"fp32": 1.66e13, "bf16x3": 5.8e13, "bf16": 8.3e13}
 
 
 def serve(torch, msft, plans, requests, batched=True, hbm_budget=16 << 30, slots=4, max_batch=24,
-          quantum_s=0.005, progress=None):
+          quantum_s=0.005, one_large=False, progress=None):
     """Run a request list through the server; returns (summary, requests).  A batched
     launch holds at most quantum_s of estimated work (None: no limit)."""
     ex = GpuExecutor(plans, torch, nstreams=slots, batched=batched)
     limit = None if quantum_s is None else quantum_s * TERMS_PER_S[plans.precision]
     sched = Scheduler(ex, hbm_budget, max_inflight=slots if batched else 1 << 30,
-                      max_batch=max_batch if batched else 1, max_batch_cost=limit)
+                      max_batch=max_batch if batched else 1, max_batch_cost=limit,
+                      one_large=one_large and batched)
     t0 = run_stream(sched, requests, progress=progress)
     torch.cuda.synchronize()
     t_end = max(r.done for r in sched.completed) if sched.completed else t0

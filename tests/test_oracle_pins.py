@@ -520,3 +520,24 @@ def test_render_ellipsoid_quadric_and_sphere_limit():
         e, _ = oracle.render_ellipsoid(grid, pitch, [33.0] * 3, R, edge, 1.0, 0.0)
         s, _ = oracle.render_sh(grid, pitch, np.zeros(1), 33.0, edge, 1.0, 0.0)
         assert np.allclose(e, s, rtol=1e-13, atol=1e-15)
+
+
+def test_render_volume_identity_linear_and_outside():
+    rng = np.random.default_rng(14)
+    src_d, src_b = rng.uniform(size=(7, 9, 5)), rng.uniform(size=(7, 9, 5))
+    # the same grid: the map itself
+    d, b = oracle.render_volume((7, 9, 5), (3.0, 2.0, 4.0), src_d, src_b, (3.0, 2.0, 4.0))
+    assert np.array_equal(d, src_d) and np.array_equal(b, src_b)
+    # a field linear in x, y, z is reproduced exactly between the source centres
+    sg, sp = (12, 10, 14), (5.0, 6.0, 4.0)
+    X, Y, Z = _centres(sg, sp)
+    lin = 0.3 + 0.01 * X - 0.02 * Y + 0.005 * Z
+    tg, tp = (17, 13, 19), (3.1, 4.3, 2.9)
+    d, _ = oracle.render_volume(tg, tp, lin, lin, sp)
+    Xt, Yt, Zt = _centres(tg, tp)
+    inside = (np.abs(Xt) <= 27.5) & (np.abs(Yt) <= 27.0) & (np.abs(Zt) <= 26.0)
+    ref = 0.3 + 0.01 * Xt - 0.02 * Yt + 0.005 * Zt
+    assert np.allclose(d[inside], ref[inside], rtol=0, atol=1e-13)
+    # one source pitch beyond the outer centres everything is zero
+    far = (np.abs(Xt) >= 32.5) | (np.abs(Yt) >= 33.0) | (np.abs(Zt) >= 30.0)
+    assert np.all(d[far] == 0.0)

@@ -134,6 +134,26 @@ def test_work_quantum_keeps_expensive_requests_apart():
     assert [h["ids"] for h in ex.launches] == [[0, 1, 2, 3], [4, 5], [6], [7, 8, 9]]
 
 
+def test_one_large_runs_expensive_requests_in_order_and_lets_cheap_ones_pass():
+    clock = Clock()
+    ex = FakeExecutor(clock, {"s": 1, "l": 1}, {"s": 0.01, "l": 0.5})
+    sched = Scheduler(ex, hbm_budget=1000, max_inflight=4, max_batch=24, clock=clock,
+                      max_batch_cost=0.045, one_large=True)
+    keys = ["l", "l", "s", "s", "l", "s"]
+    for r in _reqs(keys, [0.0] * len(keys)):
+        sched.submit(r)
+    sched.step()
+    # the first expensive request runs; the second waits, the cheap ones behind it start
+    assert [h["ids"] for h in ex.launches] == [[0], [2, 3], [5]]
+    assert [r.rid for r in sched.queue] == [1, 4]
+    clock.t = 0.6
+    sched.step()
+    assert [h["ids"] for h in ex.launches][3:] == [[1]]
+    clock.t = 1.2
+    sched.step()
+    assert [h["ids"] for h in ex.launches][4:] == [[4]]
+
+
 def test_invalid_limits():
     with pytest.raises(ValueError):
         Scheduler(None, 10, max_inflight=0)
