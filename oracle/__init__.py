@@ -56,10 +56,15 @@ def _load():
                                                   p, p, p]
         lib.oracle_render_ellipsoid.argtypes = [i32, i32, i32, d, d, d, p, p, d, d, d, p, p]
         lib.oracle_render_volume.argtypes = [i32, i32, i32, d, d, d, i32, i32, i32, d, d, d, p, p, p, p]
+        u64 = ctypes.c_uint64
+        lib.oracle_philox.argtypes = [p, p, p]
+        lib.oracle_pixel_solid_angle.argtypes = [d, i32, i32, i32]
+        lib.oracle_pixel_solid_angle.restype = ctypes.c_double
+        lib.oracle_detect_ideal.argtypes = [d, d, i32, p, d, u64, p, p]
         lib.oracle_threads.argtypes = []
         lib.oracle_threads.restype = ctypes.c_int
         for f in (lib.oracle_render_sh, lib.oracle_render_sh_backward, lib.oracle_render_ellipsoid,
-                  lib.oracle_render_volume,
+                  lib.oracle_render_volume, lib.oracle_philox, lib.oracle_detect_ideal,
                   lib.oracle_qmap, lib.oracle_qmap_uniform, lib.oracle_grid, lib.oracle_strength,
                   lib.oracle_amplitude, lib.oracle_backward):
             f.restype = None
@@ -223,3 +228,30 @@ def render_volume(grid, pitch, src_delta, src_beta, src_pitch):
     _load().oracle_render_volume(nx, ny, nz, dx, dy, dz, sx, sy, sz, sdx, sdy, sdz, _ptr(sd),
                                  _ptr(sb), _ptr(d), _ptr(b))
     return d, b
+
+
+def philox(counter, key) -> np.ndarray:
+    """Philox4x64-10 of a 4-word counter under a 2-word key: four uint64 words."""
+    c = np.ascontiguousarray(counter, dtype=np.uint64)
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    out = np.empty(4, np.uint64)
+    _load().oracle_philox(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def pixel_solid_angle(theta_max_deg: float, n: int, i: int, j: int) -> float:
+    """Solid angle of pixel (i, j) of the flat N x N detector."""
+    return float(_load().oracle_pixel_solid_angle(theta_max_deg, n, i, j))
+
+
+def detect_ideal(wavelength: float, theta_max_deg: float, n: int, intensity, fluence: float,
+                 seed: int):
+    """(expected counts, Poisson counts), both [N*N] float64, of an intensity [N*N] on
+    the flat detector for an incident fluence (photons per unit area)."""
+    I = _f64(intensity).reshape(-1)
+    assert I.size == n * n
+    mu = np.empty(n * n, np.float64)
+    counts = np.empty(n * n, np.float64)
+    _load().oracle_detect_ideal(wavelength, theta_max_deg, n, _ptr(I), float(fluence),
+                                int(seed) & 0xFFFFFFFFFFFFFFFF, _ptr(mu), _ptr(counts))
+    return mu, counts

@@ -547,3 +547,146 @@ void oracle_render_volume(int32_t nx, int32_t ny, int32_t nz, double dx, double 
         }
     }
 }
+
+/*
+ * Ideal detector (Sec. 5.2, second example: the detector that adds the photon
+ * statistics of a real recording).  The paper leaves the scaling to its
+ * supplemental material; the reading taken here is the scalar first-Born
+ * scattering cross section: a pixel p of solid angle dOmega_p receives on average
+ *     mu_p = F * (k0^2 / (4 pi))^2 * I_p * dOmega_p
+ * photons for an incident fluence F (photons per unit area; the paper's photon
+ * density), since the far-field amplitude of Eq. (1) is k0^2 / (4 pi) times the
+ * volume sum A that I = |A|^2 squares.  The recorded count is one Poisson draw
+ * of mean mu_p.
+ */
+
+/* Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 64x64->128
+ * multiplies with the key bumped by the Weyl constants between rounds. */
+static void oracle_philox4x64(const uint64_t ctr_in[4], const uint64_t key_in[2], uint64_t out[4])
+{
+    const uint64_t m0 = 0xD2E7470EE14C6C93ULL, m1 = 0xCA5A826395121157ULL;
+    const uint64_t w0 = 0x9E3779B97F4A7C15ULL, w1 = 0xBB67AE8584CAA73BULL;
+    uint64_t c[4] = {ctr_in[0], ctr_in[1], ctr_in[2], ctr_in[3]};
+    uint64_t k[2] = {key_in[0], key_in[1]};
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k[0] += w0;
+            k[1] += w1;
+        }
+        const unsigned __int128 p0 = (unsigned __int128)m0 * c[0];
+        const unsigned __int128 p1 = (unsigned __int128)m1 * c[2];
+        const uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+        const uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+        const uint64_t n0 = hi1 ^ c[1] ^ k[0], n2 = hi0 ^ c[3] ^ k[1];
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+    out[0] = c[0];
+    out[1] = c[1];
+    out[2] = c[2];
+    out[3] = c[3];
+}
+
+/* Exported for the generator's known-answer pin. */
+void oracle_philox(const uint64_t* ctr, const uint64_t* key, uint64_t* out)
+{
+    oracle_philox4x64(ctr, key, out);
+}
+
+/* The stream of uniforms of pixel p: uniform m is word m % 4 of the block with
+ * counter (m / 4, p, 0, 0) under key (seed, 0), mapped to [0, 1) by its top 53 bits. */
+typedef struct {
+    uint64_t key[2];
+    uint64_t pixel;
+    uint64_t m;
+    uint64_t block[4];
+} oracle_stream;
+
+static double oracle_uniform(oracle_stream* s)
+{
+    if ((s->m & 3) == 0) {
+        const uint64_t ctr[4] = {s->m >> 2, s->pixel, 0, 0};
+        oracle_philox4x64(ctr, s->key, s->block);
+    }
+    const uint64_t x = s->block[s->m & 3];
+    s->m += 1;
+    return (double)(x >> 11) * (1.0 / 9007199254740992.0);
+}
+
+/*
+ * One Poisson draw of mean mu.  Below mu = 10: inversion, the smallest k whose
+ * cumulative probability reaches one uniform, the terms built by
+ * p_k = p_{k-1} mu / k.  From mu = 10: the transformed rejection with squeeze of
+ * Hormann (1993, "PTRS"), whose hat is a transformed uniform pair (U, V).
+ */
+static double oracle_poisson(oracle_stream* s, double mu)
+{
+    if (!(mu > 0.0)) return 0.0;
+    if (mu < 10.0) {
+        const double u = oracle_uniform(s);
+        double k = 0.0, p = exp(-mu), f = p;
+        while (u > f && p > 0.0) {
+            k += 1.0;
+            p = (p * mu) / k;
+            f += p;
+        }
+        return k;
+    }
+    const double smu = sqrt(mu), lmu = log(mu);
+    const double b = 0.931 + 2.53 * smu;
+    const double a = -0.059 + 0.02483 * b;
+    const double inv_alpha = 1.1239 + 1.1328 / (b - 3.4);
+    const double vr = 0.9277 - 3.6224 / (b - 2.0);
+    for (;;) {
+        const double u = oracle_uniform(s) - 0.5;
+        const double v = oracle_uniform(s);
+        const double us = 0.5 - fabs(u);
+        const double k = floor((2.0 * a / us + b) * u + mu + 0.43);
+        if (us >= 0.07 && v <= vr) return k;
+        if (k < 0.0 || (us < 0.013 && v > us)) continue;
+        const double lhs = log(v) + log(inv_alpha) - log(a / (us * us) + b);
+        const double rhs = -mu + k * lmu - lgamma(k + 1.0);
+        if (lhs <= rhs) return k;
+    }
+}
+
+/* Solid angle, seen from the origin, of the flat-screen rectangle [0, u] x [0, v]
+ * at unit distance (signed: odd in u and in v). */
+static double oracle_rect_angle(double u, double v)
+{
+    return atan((u * v) / sqrt(1.0 + u * u + v * v));
+}
+
+/* Solid angle of pixel (i, j) of the flat N x N detector whose outer edge is at
+ * tan(theta_max): the pixel spans u in [(2i - N) t / N, (2i + 2 - N) t / N]. */
+double oracle_pixel_solid_angle(double theta_max_deg, int32_t n, int32_t i, int32_t j)
+{
+    const double t = tan((theta_max_deg * ORACLE_PI) / 180.0);
+    const double u0 = ((double)(2 * i - n) * t) / (double)n;
+    const double u1 = ((double)(2 * i + 2 - n) * t) / (double)n;
+    const double v0 = ((double)(2 * j - n) * t) / (double)n;
+    const double v1 = ((double)(2 * j + 2 - n) * t) / (double)n;
+    return oracle_rect_angle(u1, v1) - oracle_rect_angle(u0, v1) - oracle_rect_angle(u1, v0) +
+           oracle_rect_angle(u0, v0);
+}
+
+/* Expected counts mu[p] and one Poisson recording counts[p] of the intensity I[p]
+ * (p = j N + i) on the flat detector, for fluence F and generator seed. */
+void oracle_detect_ideal(double wavelength, double theta_max_deg, int32_t n, const double* intensity,
+                         double fluence, uint64_t seed, double* mu, double* counts)
+{
+    const double k0 = oracle_k0(wavelength);
+    const double f = (k0 * k0) / (4.0 * ORACLE_PI);
+#pragma omp parallel for schedule(static)
+    for (int32_t j = 0; j < n; ++j) {
+        for (int32_t i = 0; i < n; ++i) {
+            const int64_t p = (int64_t)j * n + i;
+            const double m = fluence * (f * f) * intensity[p] * oracle_pixel_solid_angle(theta_max_deg, n, i, j);
+            oracle_stream s = {{seed, 0}, (uint64_t)p, 0, {0, 0, 0, 0}};
+            mu[p] = m;
+            counts[p] = oracle_poisson(&s, m);
+        }
+    }
+}

@@ -541,3 +541,95 @@ def test_render_volume_identity_linear_and_outside():
     # one source pitch beyond the outer centres everything is zero
     far = (np.abs(Xt) >= 32.5) | (np.abs(Yt) >= 33.0) | (np.abs(Zt) >= 30.0)
     assert np.all(d[far] == 0.0)
+
+
+# ---------------------------------------------------------------------------
+# Ideal detector: Philox4x64-10, Poisson draws, pixel solid angles, mean counts
+# ---------------------------------------------------------------------------
+
+def _numpy_stream(seed, pixel):
+    # numpy's Philox generates from counter + 1; the oracle's stream of pixel p starts
+    # at counter (0, p, 0, 0), i.e. the 256-bit integer p * 2^64
+    start = (pixel << 64) - 1 if pixel > 0 else (1 << 256) - 1
+    return np.random.Philox(counter=start, key=[seed, 0])
+
+
+def test_philox_matches_numpy():
+    for ctr, key in (([0, 0, 0, 0], [0, 0]), ([5, 7, 11, 13], [123, 456]),
+                     ([2 ** 64 - 1, 3, 0, 2 ** 63], [2 ** 64 - 1, 2 ** 64 - 1])):
+        c = int(ctr[0]) + (int(ctr[1]) << 64) + (int(ctr[2]) << 128) + (int(ctr[3]) << 192)
+        raw = np.random.Philox(counter=c, key=key).random_raw(4)
+        nxt = c + 1
+        got = oracle.philox([(nxt >> (64 * w)) & (2 ** 64 - 1) for w in range(4)], key)
+        assert np.array_equal(got, raw)
+
+
+def _intensity_for(mu, wl, theta, n, fluence):
+    # an intensity whose expected counts are about mu (the oracle's own mu is used below)
+    f = (2 * math.pi / wl) ** 2 / (4 * math.pi)
+    om = np.array([[oracle.pixel_solid_angle(theta, n, i, j) for i in range(n)] for j in range(n)])
+    return np.asarray(mu).reshape(n, n) / (fluence * f * f * om)
+
+
+def test_poisson_ptrs_matches_numpy():
+    # mean 10 and above: Hormann's transformed rejection, which numpy's Generator uses for
+    # the same means; on the same Philox stream both draw the same counts
+    n, seed = 12, 20220203
+    rng = np.random.default_rng(1)
+    target = np.exp(rng.uniform(math.log(10.0), math.log(1e9), n * n))
+    target[:4] = [10.0, 10.5, 37.0, 1e12]
+    I = _intensity_for(target, 45.0, 60.0, n, 1e2)
+    mu, counts = oracle.detect_ideal(45.0, 60.0, n, I.ravel(), 1e2, seed)
+    assert np.allclose(mu, target, rtol=1e-12)
+    ref = np.array([np.random.Generator(_numpy_stream(seed, p)).poisson(mu[p]) for p in range(n * n)])
+    assert np.array_equal(counts, ref)
+
+
+def test_poisson_inversion_matches_scipy_ppf():
+    # mean below 10: inversion of the cumulative distribution on the pixel's first uniform
+    from scipy.stats import poisson
+    n, seed = 16, 77
+    target = np.random.default_rng(2).uniform(0.0, 10.0, n * n)
+    target[:3] = [1e-9, 9.999, 0.5]
+    I = _intensity_for(target, 13.5, 80.0, n, 3.0)
+    mu, counts = oracle.detect_ideal(13.5, 80.0, n, I.ravel(), 3.0, seed)
+    u = np.array([(int(_numpy_stream(seed, p).random_raw()) >> 11) * 2.0 ** -53 for p in range(n * n)])
+    assert np.array_equal(counts, poisson.ppf(u, mu))
+
+
+def test_detector_solid_angles():
+    from scipy.integrate import dblquad
+    for n, theta in ((1, 30.0), (7, 60.0), (32, 80.0)):
+        t = math.tan(math.radians(theta))
+        om = np.array([[oracle.pixel_solid_angle(theta, n, i, j) for i in range(n)] for j in range(n)])
+        # the whole screen: a square of half-width t at unit distance
+        assert abs(om.sum() - 4.0 * math.atan(t * t / math.sqrt(1.0 + 2.0 * t * t))) <= 1e-13
+        assert np.allclose(om, om[::-1, :], rtol=1e-12) and np.allclose(om, om.T, rtol=1e-12)
+        # one off-axis pixel against a numerical integral of dA cos(theta) / r^2
+        i, j = n - 1, n // 3
+        ref, _ = dblquad(lambda v, u: (1.0 + u * u + v * v) ** -1.5,
+                         (2 * i - n) * t / n, (2 * i + 2 - n) * t / n,
+                         (2 * j - n) * t / n, (2 * j + 2 - n) * t / n, epsabs=0, epsrel=1e-12)
+        assert abs(om[j, i] - ref) <= 1e-10 * ref
+
+
+def test_ideal_point_scatterer_and_mean():
+    # one voxel (Born): I = |dV (n^2 - 1)|^2 on every pixel, and the expected count is the
+    # scalar Rayleigh-Gans cross-section k0^4 |alpha|^2 with alpha = dV (n^2 - 1) / (4 pi)
+    n, pitch, d, b = 9, (2.0, 3.0, 1.5), 0.03, 0.01
+    I, _ = oracle.simulate(oracle.BORN, LAM, 60.0, n, np.full((1, 1, 1), d), np.full((1, 1, 1), b), pitch)
+    dv = pitch[0] * pitch[1] * pitch[2]
+    alpha = dv * ((1 - d + 1j * b) ** 2 - 1) / (4 * math.pi)
+    mu, counts = oracle.detect_ideal(LAM, 60.0, n, I, 5e5, 3)
+    om = np.array([[oracle.pixel_solid_angle(60.0, n, i, j) for i in range(n)] for j in range(n)])
+    assert np.allclose(mu, 5e5 * K0 ** 4 * abs(alpha) ** 2 * om.ravel(), rtol=1e-12)
+    # a large recording: mean and variance of (counts - mu) / sqrt(mu) near 0 and 1
+    n = 256
+    I = _intensity_for(np.exp(np.random.default_rng(4).uniform(-1.0, 12.0, n * n)), LAM, 60.0, n, 1.0)
+    mu, counts = oracle.detect_ideal(LAM, 60.0, n, I.ravel(), 1.0, 5)
+    z = (counts - mu) / np.sqrt(mu)
+    assert abs(z.mean()) < 0.02 and abs(z.var() - 1.0) < 0.03
+    assert np.all(counts == np.floor(counts)) and np.all(counts >= 0)
+    # no light, no counts; a negative or NaN intensity records nothing
+    _, c0 = oracle.detect_ideal(LAM, 60.0, 4, np.array([0.0, -1.0, np.nan] + [0.0] * 13), 1e3, 1)
+    assert np.all(c0 == 0.0)
