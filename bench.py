@@ -219,8 +219,8 @@ def time_uniform(msft, torch, wl, d, b, prec, steps, warmup):
 
 
 def time_render(msft, torch, steps):
-    """The fit's star-body renderer on 128^3 (l <= 8, soft edge of one pitch) and its
-    coefficient gradient."""
+    """The fit's star-body renderer on 128^3 (l <= 8, soft edge of one pitch), its
+    coefficient gradient, and a 96^3 volume map resampled onto the same grid."""
     import numpy as np
     n, box, lmax = 128, 680.0, 8
     g = msft.make_shape_grid((n, n, n), (box / n,) * 3, box / n, 0.01, 0.02)
@@ -229,10 +229,15 @@ def time_render(msft, torch, steps):
     b = torch.empty_like(d)
     gc = torch.empty_like(c)
     ws = msft.workspace_tensor(msft.msft_render_sh_query(lmax), "cuda")
+    rng = torch.Generator(device="cuda").manual_seed(4)
+    vd = torch.rand((96, 96, 96), device="cuda", generator=rng) * 0.03
+    vb = torch.rand((96, 96, 96), device="cuda", generator=rng) * 0.03
     out = {}
     for name, call in (("render_ms", lambda: msft.msft_render_sh(g, lmax, 200.0, c, d, b)),
                        ("gradient_ms", lambda: msft.msft_render_sh_backward(g, lmax, 200.0, c, d, b,
-                                                                           gc, ws))):
+                                                                           gc, ws)),
+                       ("volume_map_ms", lambda: msft.msft_render_volume(g, vd, vb, (box / 96,) * 3,
+                                                                         d, b))):
         call()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

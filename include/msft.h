@@ -277,6 +277,19 @@ msft_status msft_render_sh_backward(const msft_shape_grid* g, int32_t lmax, doub
 msft_status msft_render_ellipsoid(const msft_shape_grid* g, const double* axes, const double* rot,
                                   float* delta, float* beta, void* stream);
 
+/*
+ * Volume map (Sec. 5.2: an arbitrary voxel representation of the refractive
+ * index): delta and beta given on a source grid of sx x sy x sz voxels of pitch
+ * (sdx, sdy, sdz), also centred on the origin, resampled at the centres of g by
+ * trilinear interpolation between source voxel centres, with zero beyond the
+ * source grid (values fall to zero over one source pitch past its outer centres).
+ * g->edge, g->delta0 and g->beta0 are not used.  src_delta, src_beta: device
+ * float32 [sx][sy][sz]; delta, beta: device float32 [nx][ny][nz] (written).
+ */
+msft_status msft_render_volume(const msft_shape_grid* g, int32_t sx, int32_t sy, int32_t sz,
+                               double sdx, double sdy, double sdz, const float* src_delta,
+                               const float* src_beta, float* delta, float* beta, void* stream);
+
 /* Static description of a status code. */
 const char* msft_status_str(msft_status s);
 

@@ -479,6 +479,30 @@ msft_status msft_render_sh_backward(const msft_shape_grid* g, int32_t lmax, doub
     return ok();
 }
 
+msft_status msft_render_volume(const msft_shape_grid* g, int32_t sx, int32_t sy, int32_t sz,
+                               double sdx, double sdy, double sdz, const float* src_delta,
+                               const float* src_beta, float* delta, float* beta, void* stream)
+{
+    VolArgs a;
+    msft_status st = shape_grid_args(g, &a.g);
+    if (st != MSFT_OK) return st;
+    if (sx < 1 || sy < 1 || sz < 1 || sx > 4096 || sy > 4096 || sz > 4096)
+        return fail(MSFT_ERR_INVALID, "source voxel counts must lie in [1, 4096]");
+    if (!(sdx > 0.0 && sdy > 0.0 && sdz > 0.0) || !std::isfinite(sdx) || !std::isfinite(sdy) ||
+        !std::isfinite(sdz))
+        return fail(MSFT_ERR_INVALID, "source pitch must be finite and > 0");
+    if (!src_delta || !src_beta || !delta || !beta) return fail(MSFT_ERR_INVALID, "NULL argument");
+    a.sx = sx;
+    a.sy = sy;
+    a.sz = sz;
+    a.sdx = sdx;
+    a.sdy = sdy;
+    a.sdz = sdz;
+    int e = launch_render_volume(a, src_delta, src_beta, delta, beta, stream);
+    if (e) return hip_fail((hipError_t)e, "render launch");
+    return ok();
+}
+
 msft_status msft_render_ellipsoid(const msft_shape_grid* g, const double* axes, const double* rot,
                                   float* delta, float* beta, void* stream)
 {

@@ -203,6 +203,12 @@ struct ShArgs {
     double ra[SH_TABLE * SH_TABLE], rb[SH_TABLE * SH_TABLE];
 };
 
+struct VolArgs {
+    RenderGrid g;
+    int32_t sx, sy, sz;
+    double sdx, sdy, sdz;
+};
+
 struct EllArgs {
     RenderGrid g;
     double ax[3];
@@ -233,6 +239,8 @@ int launch_render_sh(const ShArgs& s, const float* coeffs, float* delta, float* 
 int launch_render_sh_grad(const ShArgs& s, const float* coeffs, const float* gd, const float* gb,
                           float* grad, double* partial, int nblocks, void* stream);
 int launch_render_ellipsoid(const EllArgs& e, float* delta, float* beta, void* stream);
+int launch_render_volume(const VolArgs& a, const float* sd, const float* sb, float* delta,
+                         float* beta, void* stream);
 int launch_forward_batch(int precision, const BatchArgs& b, void* stream);
 
 }  // namespace msft

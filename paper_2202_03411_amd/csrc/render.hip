@@ -6,6 +6,7 @@
 //  render_sh_grad_kernel   per-workgroup partial sums of dL/dc_lm (FP64 partials)
 //  render_sh_grad_reduce   the partials summed in a fixed order
 //  render_ellipsoid_kernel quadric body, hard or soft
+//  render_volume_kernel    a voxel map on its own grid, resampled (trilinear)
 //
 // One thread per voxel; directions, radii and the harmonic sums in FP64 (a few
 // hundred flops per voxel, microseconds for 128^3), outputs in FP32.
@@ -198,6 +199,47 @@ __global__ __launch_bounds__(256) void render_ellipsoid_kernel(EllArgs e, float*
     else o = occupancy(1.0 / sqrt(e2), d.r, e.g.edge);
     delta[v] = (float)(e.g.delta0 * o);
     beta[v] = (float)(e.g.beta0 * o);
+}
+
+// Volume map: trilinear interpolation between the centres of a source grid
+// (also centred on the origin), zero beyond it; FP64 coordinates and weights.
+__global__ __launch_bounds__(256) void render_volume_kernel(VolArgs a, const float* sd,
+                                                            const float* sb, float* delta, float* beta)
+{
+    const int64_t nv = (int64_t)a.g.nx * a.g.ny * a.g.nz;
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nv) return;
+    const VoxelDir d = voxel_dir(a.g, v);
+    const double fx = d.x / a.sdx + (a.sx - 1) / 2.0;
+    const double fy = d.y / a.sdy + (a.sy - 1) / 2.0;
+    const double fz = d.z / a.sdz + (a.sz - 1) / 2.0;
+    const double ax = floor(fx), ay = floor(fy), az = floor(fz);
+    const double wx = fx - ax, wy = fy - ay, wz = fz - az;
+    double vd = 0.0, vb = 0.0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int64_t x = (int64_t)ax + i, y = (int64_t)ay + j, z = (int64_t)az + k;
+                if (x < 0 || x >= a.sx || y < 0 || y >= a.sy || z < 0 || z >= a.sz) continue;
+                const double w = (i ? wx : 1.0 - wx) * (j ? wy : 1.0 - wy) * (k ? wz : 1.0 - wz);
+                const int64_t s = (x * a.sy + y) * a.sz + z;
+                vd += w * (double)sd[s];
+                vb += w * (double)sb[s];
+            }
+    delta[v] = (float)vd;
+    beta[v] = (float)vb;
+}
+
+int launch_render_volume(const VolArgs& a, const float* sd, const float* sb, float* delta,
+                         float* beta, void* stream)
+{
+    const int64_t nv = (int64_t)a.g.nx * a.g.ny * a.g.nz;
+    hipLaunchKernelGGL(render_volume_kernel, dim3((unsigned)ceil_div(nv, 256)), dim3(256), 0,
+                       (hipStream_t)stream, a, sd, sb, delta, beta);
+    return (int)hipGetLastError();
 }
 
 int launch_render_sh(const ShArgs& s, const float* coeffs, float* delta, float* beta, void* stream)

@@ -103,6 +103,7 @@ def _load():
     lib.msft_render_sh_query.argtypes = [I32, P(S)]
     lib.msft_render_sh_backward.argtypes = [P(msft_shape_grid), I32, D, VP, VP, VP, VP, VP, S, VP]
     lib.msft_render_ellipsoid.argtypes = [P(msft_shape_grid), VP, VP, VP, VP, VP]
+    lib.msft_render_volume.argtypes = [P(msft_shape_grid), I32, I32, I32, D, D, D, VP, VP, VP, VP, VP]
     lib.msft_status_str.argtypes = [ctypes.c_int]
     lib.msft_status_str.restype = ctypes.c_char_p
     lib.msft_last_error.argtypes = []
@@ -111,7 +112,7 @@ def _load():
                  "msft_plan_qmap", "msft_plan_grid", "msft_simulate", "msft_simulate_scan",
                  "msft_simulate_contract", "msft_pixel_block", "msft_batch_query", "msft_simulate_batch",
                  "msft_backward", "msft_render_sh", "msft_render_sh_query", "msft_render_sh_backward",
-                 "msft_render_ellipsoid"):
+                 "msft_render_ellipsoid", "msft_render_volume"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -124,7 +125,8 @@ EXPORTS = ("msft_plan", "msft_plan_qlist", "msft_plan_destroy", "msft_plan_query
            "msft_plan_grid", "msft_simulate", "msft_simulate_scan", "msft_simulate_contract", "msft_pixel_block",
            "msft_batch_query",
            "msft_simulate_batch", "msft_backward", "msft_render_sh", "msft_render_sh_query",
-           "msft_render_sh_backward", "msft_render_ellipsoid", "msft_status_str", "msft_last_error")
+           "msft_render_sh_backward", "msft_render_ellipsoid", "msft_render_volume", "msft_status_str",
+           "msft_last_error")
 
 
 def msft_status_str(status: int) -> str:
@@ -376,3 +378,12 @@ def msft_render_ellipsoid(shape_grid, axes, rot, delta, beta, stream=None) -> No
     _check(_lib.msft_render_ellipsoid(ctypes.byref(shape_grid), ax.ctypes.data_as(ctypes.c_void_p),
                                       R.ctypes.data_as(ctypes.c_void_p), _ptr(delta), _ptr(beta),
                                       _stream(stream)), "msft_render_ellipsoid")
+
+
+def msft_render_volume(shape_grid, src_delta, src_beta, src_pitch, delta, beta, stream=None) -> None:
+    """Resample a (delta, beta) map on its own centred grid (src_pitch) onto shape_grid."""
+    sx, sy, sz = (int(v) for v in src_delta.shape)
+    sdx, sdy, sdz = (float(v) for v in src_pitch)
+    _check(_lib.msft_render_volume(ctypes.byref(shape_grid), sx, sy, sz, sdx, sdy, sdz,
+                                   _ptr(src_delta), _ptr(src_beta), _ptr(delta), _ptr(beta),
+                                   _stream(stream)), "msft_render_volume")

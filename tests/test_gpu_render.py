@@ -145,3 +145,22 @@ def test_render_argument_errors(env):
         msft.msft_render_sh_backward(g, 1, 10.0, c, d, d, c, ws)   # hard edge has no gradient
     with pytest.raises(msft.MSFTError):
         msft.msft_render_ellipsoid(g, [1.0, -2.0, 3.0], np.eye(3), d, d)
+
+
+def test_render_volume_matches_oracle(env):
+    torch, msft, _ = env
+    rng = np.random.default_rng(15)
+    sg, sp = (20, 17, 23), (6.0, 7.0, 5.0)
+    sd = rng.uniform(0, 0.03, sg).astype(np.float32)
+    sb = rng.uniform(0, 0.03, sg).astype(np.float32)
+    for tg, tp in (((33, 29, 41), (4.0, 4.5, 3.1)), (sg, sp), ((9, 50, 8), (13.0, 2.0, 15.0))):
+        g = msft.make_shape_grid(tg, tp)
+        d = torch.full(tg, float("nan"), device="cuda")
+        b = torch.full(tg, float("nan"), device="cuda")
+        msft.msft_render_volume(g, torch.from_numpy(sd).cuda(), torch.from_numpy(sb).cuda(), sp, d, b)
+        torch.cuda.synchronize()
+        od, ob = oracle.render_volume(tg, tp, sd.astype(np.float64), sb.astype(np.float64), sp)
+        d, b = d.cpu().numpy().astype(np.float64), b.cpu().numpy().astype(np.float64)
+        assert np.max(np.abs(d - od)) <= 3e-9 and np.max(np.abs(b - ob)) <= 3e-9
+        if tg == sg:
+            assert np.array_equal(d, sd) and np.array_equal(b, sb)
