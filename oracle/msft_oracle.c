@@ -623,7 +623,7 @@ static double oracle_uniform(oracle_stream* s)
  */
 static double oracle_poisson(oracle_stream* s, double mu)
 {
-    if (!(mu > 0.0)) return 0.0;
+    if (!(mu > 0.0) || !isfinite(mu)) return 0.0;
     if (mu < 10.0) {
         const double u = oracle_uniform(s);
         double k = 0.0, p = exp(-mu), f = p;

@@ -630,6 +630,6 @@ def test_ideal_point_scatterer_and_mean():
     z = (counts - mu) / np.sqrt(mu)
     assert abs(z.mean()) < 0.02 and abs(z.var() - 1.0) < 0.03
     assert np.all(counts == np.floor(counts)) and np.all(counts >= 0)
-    # no light, no counts; a negative or NaN intensity records nothing
-    _, c0 = oracle.detect_ideal(LAM, 60.0, 4, np.array([0.0, -1.0, np.nan] + [0.0] * 13), 1e3, 1)
+    # no light, no counts; a negative, NaN or infinite intensity records nothing
+    _, c0 = oracle.detect_ideal(LAM, 60.0, 4, np.array([0.0, -1.0, np.nan, np.inf] + [0.0] * 12), 1e3, 1)
     assert np.all(c0 == 0.0)
