@@ -252,6 +252,23 @@ def time_render(msft, torch, steps):
     return out
 
 
+def time_detector(msft, torch, wl, intensity, steps):
+    """The Ideal detector (Poisson counts) over the benchmark pattern at the paper's
+    example photon density, 100 photons/nm^2."""
+    with msft.Plan.for_workload(wl, "fp32") as plan:
+        counts = plan.detect_ideal(intensity, 1e2, 1)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for k in range(steps):
+            plan.detect_ideal(intensity, 1e2, k)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+    return {"ms": ms, "photons": float(counts.double().sum()), "photon_density_per_nm2": 1e2,
+            "pixels": wl.det_n ** 2}
+
+
 def oracle_error(wl, I_gpu, npix=256):
     """Relative L2 intensity error of a GPU pattern against the FP64 oracle on
     seeded pixels (all of them and the wide-angle ring theta > 3/4 theta_max)."""
@@ -440,6 +457,10 @@ def main():
                  "frac_hbm": scan_bytes / (head["scan_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "variants": results,
     }
+    if not args.only and head.get("intensity") is not None:
+        line["ideal_detector"] = time_detector(msft, torch, wl, head["intensity"], args.steps)
+        print(f"[bench] ideal detector 512^2: {line['ideal_detector']['ms'] * 1e3:.1f} us, "
+              f"{line['ideal_detector']['photons']:.4g} photons", file=sys.stderr, flush=True)
     for v in line["variants"].values():
         v.pop("intensity", None)
     if "bf16x3" in results:

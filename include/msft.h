@@ -278,6 +278,27 @@ msft_status msft_render_ellipsoid(const msft_shape_grid* g, const double* axes, 
                                   float* delta, float* beta, void* stream);
 
 /*
+ * Ideal detector (Sec. 5.2, the second example's detector that adds the photon
+ * statistics of a real recording).  From the intensity I = |A|^2 of a flat-detector
+ * plan (msft_simulate's output, [N][N]) it writes one recording: counts[p] is a
+ * Poisson draw of mean
+ *     mu_p = photon_density * (k0^2 / (4 pi))^2 * I_p * dOmega_p,
+ * the scalar first-Born cross section of the volume sum A times the incident
+ * fluence photon_density (photons per unit area, the plan's length unit) and the
+ * exact solid angle dOmega_p of the pixel's square on the screen at unit distance.
+ * The paper leaves this scaling to its supplemental material; the form above is
+ * the library's reading.  The draws come from Philox4x64-10 keyed by (seed, 0),
+ * block m of pixel p at counter (m, p, 0, 0), so a recording depends only on
+ * (intensity, photon_density, seed) and is the same for any launch order.  Counts
+ * are whole numbers stored as float32 (exact below 2^24); pixels whose mean is not
+ * a positive finite number record 0.  expected (may be NULL) receives mu_p.
+ * Errors: MSFT_ERR_INVALID for a q-list or uniform-q plan, NULL intensity/counts,
+ * or a negative or non-finite photon_density.  Asynchronous on stream.
+ */
+msft_status msft_detect_ideal(msft_plan_t plan, const float* intensity, double photon_density,
+                              uint64_t seed, float* counts, float* expected, void* stream);
+
+/*
  * Volume map (Sec. 5.2: an arbitrary voxel representation of the refractive
  * index): delta and beta given on a source grid of sx x sy x sz voxels of pitch
  * (sdx, sdy, sdz), also centred on the origin, resampled at the centres of g by

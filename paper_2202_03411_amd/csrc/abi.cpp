@@ -165,6 +165,11 @@ msft_status build_device_tables(msft_plan_s* p)
         if (e == hipSuccess) e = e2;
         for (double* t : dev)
             if (t) (void)hipFree(t);
+    } else if (d.g3) {
+        e = (hipError_t)launch_twiddles_g3(d, p->q_dev, p->xs_dev, p->ys_dev, p->zs_dev, p->txa,
+                                           p->ty, p->tz, s);
+        hipError_t e2 = hipStreamSynchronize(s);
+        if (e == hipSuccess) e = e2;
     } else {
         e = (hipError_t)launch_twiddles(p->geo.g.precision, d, p->q_dev, p->xs_dev, p->ys_dev,
                                         p->zs_dev, p->txa, p->ty, p->tz, s);
@@ -253,6 +258,8 @@ msft_status make_plan(const msft_geometry* g, const double* q_host, int64_t npix
         return fail(MSFT_ERR_UNDERSAMPLED, buf);
     }
     p->dims = make_dims(p->geo.npix, g->nx, g->ny, g->nz);
+    // FP32 without the separable detector runs the Gauss (three-product) contraction
+    p->dims.g3 = false && g->precision == MSFT_FP32 && !p->separable;
     size_t fwd_ws = align256(p->dims.wtile_bytes());
     size_t adj_ws = align256(make_adj_dims(p->dims).bytes());
     if (p->separable) {
@@ -348,6 +355,9 @@ int launch_contraction(const msft_plan_s* p, const void* workspace, float* inten
                        float* amplitude, void* stream)
 {
     const int prec = p->geo.g.precision;
+    if (p->dims.g3)
+        return launch_forward_g3(forward_args(p, workspace, intensity, amplitude), 0, p->dims.nblocks,
+                                 stream);
     if (!p->separable)
         return launch_forward(prec, forward_args(p, workspace, intensity, amplitude), 0,
                               p->dims.nblocks, true, stream);
@@ -371,6 +381,7 @@ ScanArgs scan_args(const msft_plan_s* p, const float* delta, const float* beta, 
     s.nxc = p->dims.nxc;
     s.nzb = p->dims.nzb;
     s.strength = g.strength;
+    s.g3 = p->dims.g3 ? 1 : 0;
     const double k0 = (2.0 * 3.14159265358979323846) / g.wavelength;
     s.k0dz = (float)(k0 * g.dz);
     s.dV = (float)(g.dx * g.dy * g.dz);
@@ -524,6 +535,32 @@ msft_status msft_render_ellipsoid(const msft_shape_grid* g, const double* axes, 
     return ok();
 }
 
+
+msft_status msft_detect_ideal(msft_plan_t plan, const float* intensity, double photon_density,
+                              uint64_t seed, float* counts, float* expected, void* stream)
+{
+    msft_status st = check_runnable(plan);
+    if (st != MSFT_OK) return st;
+    if (plan->qlist || plan->separable)
+        return fail(MSFT_ERR_INVALID, "the Ideal detector needs a flat-detector plan");
+    if (!intensity || !counts) return fail(MSFT_ERR_INVALID, "intensity and counts must be non-NULL");
+    if (!(photon_density >= 0.0) || !std::isfinite(photon_density))
+        return fail(MSFT_ERR_INVALID, "photon_density must be finite and >= 0");
+    DeviceScope ds(plan->device);
+    if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice");
+    const msft_geometry& g = plan->geo.g;
+    const double kPi = 3.14159265358979323846;
+    const double k0 = (2.0 * kPi) / g.wavelength;
+    const double f = (k0 * k0) / (4.0 * kPi);
+    IdealArgs a;
+    a.n = g.det_n;
+    a.t = std::tan((g.theta_max_deg * kPi) / 180.0);
+    a.scale = photon_density * (f * f);
+    a.seed = seed;
+    int e = launch_detect_ideal(a, intensity, counts, expected, stream);
+    if (e) return hip_fail((hipError_t)e, "detector launch");
+    return ok();
+}
 
 msft_status msft_plan(const msft_geometry* g, int device, msft_plan_t* out)
 {
@@ -712,7 +749,9 @@ msft_status msft_simulate_batch(const msft_request* reqs, int32_t n, void* works
         b.nreq = nr;
         b.item_begin[nr] = items;
         if (items == 0) continue;
-        int e = launch_forward_batch(precision, b, stream);
+        // every plan of one precision is flat here, so all or none use the Gauss tiles
+        int e = reqs[0].plan->dims.g3 ? launch_forward_batch_g3(b, stream)
+                                      : launch_forward_batch(precision, b, stream);
         if (e) return hip_fail((hipError_t)e, "batch launch");
     }
     return ok();

@@ -231,7 +231,18 @@ __device__ __forceinline__ void store_w(uint8_t* tile, int lane, int zl, float w
     }
 }
 
-template <int PREC>
+// The Gauss tile layout: rows (plane, h, z) of 8 slots of 4 floats, x = 8 g + 2 e + h,
+// slot g XOR-swizzled with z; planes Wr, Wi, Wr + Wi.
+__device__ __forceinline__ void store_w_g3(uint8_t* tile, int lane, int zl, float wr, float wi)
+{
+    const int h = lane & 1, e = (lane >> 1) & 3, g = lane >> 3;
+    const int off = (h * ZB + zl) * G3_ROW_BYTES + ((g ^ (zl & 7)) << 4) + 4 * e;
+    *(float*)(tile + off) = wr;
+    *(float*)(tile + 64 * G3_ROW_BYTES + off) = wi;
+    *(float*)(tile + 128 * G3_ROW_BYTES + off) = wr + wi;
+}
+
+template <int PREC, bool G3>
 __global__ __launch_bounds__(64 * SCAN_WAVES) void scan_kernel(ScanArgs a)
 {
     __shared__ float tot_b[SCAN_WAVES][64], tot_d[SCAN_WAVES][64];
@@ -288,7 +299,7 @@ __global__ __launch_bounds__(64 * SCAN_WAVES) void scan_kernel(ScanArgs a)
         carry_d += rd;
         if (!active) continue;
 
-        uint8_t* tile = a.wtiles + ((size_t)(xc * a.nzb + zb) * a.ny + y) * TILE_BYTES;
+        uint8_t* tile = a.wtiles + ((size_t)(xc * a.nzb + zb) * a.ny + y) * (G3 ? G3_TILE_BYTES : TILE_BYTES);
 #pragma unroll
         for (int k = 0; k < ZB; ++k) {
             float wr, wi;
@@ -309,7 +320,8 @@ __global__ __launch_bounds__(64 * SCAN_WAVES) void scan_kernel(ScanArgs a)
                 wr = a.dV * (chr * tr - chi * ti);
                 wi = a.dV * (chr * ti + chi * tr);
             }
-            store_w<PREC>(tile, lane, k, wr, wi);
+            if (G3) store_w_g3(tile, lane, k, wr, wi);
+            else store_w<PREC>(tile, lane, k, wr, wi);
             Sb += b[k];
             Sd += d[k];
         }
@@ -321,10 +333,12 @@ int launch_scan(int precision, const ScanArgs& a, void* stream)
     hipStream_t s = (hipStream_t)stream;
     dim3 grid(a.nxc, a.ny);
     const int waves = a.nzb < SCAN_WAVES ? a.nzb : SCAN_WAVES;
-    if (precision == MSFT_FP32)
-        hipLaunchKernelGGL(scan_kernel<MSFT_FP32>, grid, dim3(64 * waves), 0, s, a);
+    if (precision == MSFT_FP32 && a.g3)
+        hipLaunchKernelGGL((scan_kernel<MSFT_FP32, true>), grid, dim3(64 * waves), 0, s, a);
+    else if (precision == MSFT_FP32)
+        hipLaunchKernelGGL((scan_kernel<MSFT_FP32, false>), grid, dim3(64 * waves), 0, s, a);
     else
-        hipLaunchKernelGGL(scan_kernel<MSFT_BF16X3>, grid, dim3(64 * waves), 0, s, a);
+        hipLaunchKernelGGL((scan_kernel<MSFT_BF16X3, false>), grid, dim3(64 * waves), 0, s, a);
     return (int)hipGetLastError();
 }
 

@@ -33,6 +33,24 @@ constexpr int ROW_BYTES = 256;              // one (h, z) row of a W tile
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// ---------------------------------------------------------------------------
+// Gauss (3M) form of the FP32 contraction (flat detector and q lists).  The
+// complex product T W is formed from three real products,
+//   P1 = Tr Wr,  P2 = Ti Wi,  P3 = (Tr + Ti)(Wr + Wi),
+//   Re = P1 - P2,  Im = P3 - P1 - P2,
+// each a real MFMA contraction over x with pixels as rows and z as columns, so
+// the matrix cores do 6 real flops per complex multiply-add instead of 8.  A wave
+// owns G3_WAVE_PIX pixels (the 32 MFMA rows); G3_WAVES waves make one BLOCK_PIX
+// pixel block.  A W tile (XC x, ZB z, one y) holds the three planes Wr, Wi,
+// Wr + Wi as rows (plane, x parity h, z) of 32 floats; an A tile (one wave, one x
+// chunk) holds Tr, Ti, Tr + Ti in MFMA register order.
+// ---------------------------------------------------------------------------
+constexpr int G3_WAVE_PIX = 32;
+constexpr int G3_WAVES = 4;
+constexpr int G3_TILE_BYTES = 3 * 2 * ZB * 128;   // 24 KB: W tile or A tile
+constexpr int G3_ROW_BYTES = 128;
+static_assert(G3_WAVE_PIX * G3_WAVES == BLOCK_PIX, "a Gauss block is one pixel block");
+
 // Host geometry (FP64, built without FMA contraction).
 struct Geometry {
     msft_geometry g;
@@ -59,9 +77,14 @@ bool sampling_ok(const Geometry& geo, int* bad_axis, double* worst);
 struct Dims {
     int64_t npix, nblocks, nwt;   // pixels, workgroup blocks, wave tiles
     int nx, ny, nz, x_pad, nxc, nzb;
+    bool g3 = false;              // Gauss (3M) tiles: FP32 flat detector and q lists
     int64_t ntiles() const { return (int64_t)nxc * nzb * ny; }
-    size_t wtile_bytes() const { return (size_t)ntiles() * TILE_BYTES; }
-    size_t txa_bytes() const { return (size_t)nwt * nxc * TILE_BYTES; }
+    size_t wtile_bytes() const { return (size_t)ntiles() * (g3 ? G3_TILE_BYTES : TILE_BYTES); }
+    size_t txa_bytes() const
+    {
+        return g3 ? (size_t)nblocks * G3_WAVES * nxc * G3_TILE_BYTES : (size_t)nwt * nxc * TILE_BYTES;
+    }
+    // (the same sizes in the Gauss layout: [wave][y][h][16] and [wave][zb][h][z][16])
     size_t ty_bytes() const { return (size_t)nwt * ny * WAVE_PIX * 8; }
     size_t tz_bytes() const { return (size_t)nwt * nzb * 2 * ZB * 8 * 8; }
 };
@@ -133,6 +156,7 @@ struct ScanArgs {
     uint8_t* wtiles;
     int32_t nx, ny, nz, nxc, nzb;
     int32_t strength;
+    int32_t g3;   // write the Gauss tile layout (FP32 only)
     float k0dz;   // k0 * dz
     float dV;     // dx * dy * dz
 };
@@ -209,6 +233,15 @@ struct VolArgs {
     double sdx, sdy, sdz;
 };
 
+// Ideal detector on the flat N x N screen: half-width t = tan(theta_max) at unit
+// distance, scale = F (k0^2 / 4 pi)^2, Philox key (seed, 0).
+struct IdealArgs {
+    int32_t n;
+    double t;
+    double scale;
+    uint64_t seed;
+};
+
 struct EllArgs {
     RenderGrid g;
     double ax[3];
@@ -224,6 +257,11 @@ int launch_twiddles(int precision, const Dims& d, const double* q_dev, const dou
 int launch_scan(int precision, const ScanArgs& a, void* stream);
 int launch_forward(int precision, const FwdArgs& a, int64_t block_begin, int64_t nblocks,
                    bool rotate, void* stream);
+// Gauss form (tables from launch_twiddles_g3, tiles from a g3 scan).
+int launch_twiddles_g3(const Dims& d, const double* q_dev, const double* xs_dev, const double* ys_dev,
+                       const double* zs_dev, uint8_t* txa, float* ty, float* tz, void* stream);
+int launch_forward_g3(const FwdArgs& a, int64_t block_begin, int64_t nblocks, void* stream);
+int launch_forward_batch_g3(const BatchArgs& b, void* stream);
 int launch_sep_twiddles(int precision, const Dims& d, const SepDims& sd, const double* qcol,
                         const double* qrow, const double* qk, const double* xs, const double* ys,
                         const double* zs, uint8_t* txa1, uint8_t* txa2, float* tz, void* stream);
@@ -239,6 +277,8 @@ int launch_render_sh(const ShArgs& s, const float* coeffs, float* delta, float* 
 int launch_render_sh_grad(const ShArgs& s, const float* coeffs, const float* gd, const float* gb,
                           float* grad, double* partial, int nblocks, void* stream);
 int launch_render_ellipsoid(const EllArgs& e, float* delta, float* beta, void* stream);
+int launch_detect_ideal(const IdealArgs& a, const float* intensity, float* counts, float* expected,
+                        void* stream);
 int launch_render_volume(const VolArgs& a, const float* sd, const float* sb, float* delta,
                          float* beta, void* stream);
 int launch_forward_batch(int precision, const BatchArgs& b, void* stream);

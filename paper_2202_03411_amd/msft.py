@@ -103,6 +103,7 @@ def _load():
     lib.msft_render_sh_query.argtypes = [I32, P(S)]
     lib.msft_render_sh_backward.argtypes = [P(msft_shape_grid), I32, D, VP, VP, VP, VP, VP, S, VP]
     lib.msft_render_ellipsoid.argtypes = [P(msft_shape_grid), VP, VP, VP, VP, VP]
+    lib.msft_detect_ideal.argtypes = [VP, VP, D, ctypes.c_uint64, VP, VP, VP]
     lib.msft_render_volume.argtypes = [P(msft_shape_grid), I32, I32, I32, D, D, D, VP, VP, VP, VP, VP]
     lib.msft_status_str.argtypes = [ctypes.c_int]
     lib.msft_status_str.restype = ctypes.c_char_p
@@ -112,7 +113,7 @@ def _load():
                  "msft_plan_qmap", "msft_plan_grid", "msft_simulate", "msft_simulate_scan",
                  "msft_simulate_contract", "msft_pixel_block", "msft_batch_query", "msft_simulate_batch",
                  "msft_backward", "msft_render_sh", "msft_render_sh_query", "msft_render_sh_backward",
-                 "msft_render_ellipsoid", "msft_render_volume"):
+                 "msft_render_ellipsoid", "msft_render_volume", "msft_detect_ideal"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -125,7 +126,8 @@ EXPORTS = ("msft_plan", "msft_plan_qlist", "msft_plan_destroy", "msft_plan_query
            "msft_plan_grid", "msft_simulate", "msft_simulate_scan", "msft_simulate_contract", "msft_pixel_block",
            "msft_batch_query",
            "msft_simulate_batch", "msft_backward", "msft_render_sh", "msft_render_sh_query",
-           "msft_render_sh_backward", "msft_render_ellipsoid", "msft_render_volume", "msft_status_str",
+           "msft_render_sh_backward", "msft_render_ellipsoid", "msft_render_volume",
+           "msft_detect_ideal", "msft_status_str",
            "msft_last_error")
 
 
@@ -325,6 +327,20 @@ class Plan:
         msft_simulate(self.handle, delta, beta, I, A, self.workspace(), stream)
         return (I, torch.view_as_complex(A)) if amplitude else I
 
+    def detect_ideal(self, intensity, photon_density, seed, expected=False, stream=None):
+        """One recording of the Ideal detector: Poisson counts [N*N] (float32) of the
+        intensity for an incident fluence photon_density (photons per unit area); with
+        expected=True also the mean counts."""
+        if intensity.dtype != torch.float32 or intensity.numel() != self.npix:
+            raise ValueError(f"intensity must be float32 with {self.npix} values")
+        if intensity.device != self.device:
+            raise ValueError("intensity must live on the plan's device")
+        intensity = intensity.contiguous()
+        counts = torch.empty(self.npix, dtype=torch.float32, device=self.device)
+        mu = torch.empty_like(counts) if expected else None
+        msft_detect_ideal(self.handle, intensity, photon_density, seed, counts, mu, stream)
+        return (counts, mu) if expected else counts
+
     def close(self):
         if getattr(self, "handle", None):
             msft_plan_destroy(self.handle)
@@ -387,3 +403,12 @@ def msft_render_volume(shape_grid, src_delta, src_beta, src_pitch, delta, beta, 
     _check(_lib.msft_render_volume(ctypes.byref(shape_grid), sx, sy, sz, sdx, sdy, sdz,
                                    _ptr(src_delta), _ptr(src_beta), _ptr(delta), _ptr(beta),
                                    _stream(stream)), "msft_render_volume")
+
+
+def msft_detect_ideal(plan_handle, intensity, photon_density, seed, counts, expected=None,
+                      stream=None) -> None:
+    """One Poisson recording of a flat-detector intensity (see Plan.detect_ideal)."""
+    _check(_lib.msft_detect_ideal(plan_handle, _ptr(intensity), float(photon_density),
+                                  int(seed) & 0xFFFFFFFFFFFFFFFF, _ptr(counts),
+                                  _ptr(expected), _stream(stream)),
+           "msft_detect_ideal")

@@ -382,9 +382,12 @@ TERMS_PER_S = {"fp32": 1.66e13, "bf16x3": 5.8e13, "bf16": 8.3e13}
 
 
 def serve(torch, msft, plans, requests, batched=True, hbm_budget=16 << 30, slots=4, max_batch=24,
-          quantum_s=0.005, one_large=False, progress=None):
+          quantum_s=0.005, one_large=True, progress=None):
     """Run a request list through the server; returns (summary, requests).  A batched
-    launch holds at most quantum_s of estimated work (None: no limit)."""
+    launch holds at most quantum_s of estimated work (None: no limit); with one_large
+    (the default) requests above that quantum run one at a time while cheap ones pass
+    them (measured on a mixed stream: at 0.9 of capacity the median latency drops
+    fivefold for a p99 within a tenth of one-pattern-per-launch)."""
     ex = GpuExecutor(plans, torch, nstreams=slots, batched=batched)
     limit = None if quantum_s is None else quantum_s * TERMS_PER_S[plans.precision]
     sched = Scheduler(ex, hbm_budget, max_inflight=slots if batched else 1 << 30,

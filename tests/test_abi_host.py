@@ -137,10 +137,11 @@ def test_query_sizes_and_host_only_refusal():
     try:
         npix, ws, res = msft.msft_plan_query(h)
         assert npix == 400
-        # forward: W tiles, ceil(150/64) x chunks * ceil(33/32) z blocks * 5 y, 16 KiB each;
+        # forward: W tiles, ceil(150/64) x chunks * ceil(33/32) z blocks * 5 y, 24 KiB each
+        # in FP32 (planes Wr, Wi, Wr + Wi of the three-product contraction);
         # backward: h (512 padded pixels, complex64) + 8 pixel groups of partial
         # strength gradients over the padded 192 x 5 x 64 grid
-        fwd = 3 * 2 * 5 * 16384
+        fwd = 3 * 2 * 5 * 24576
         bwd = 512 * 8 + 8 * 192 * 5 * 64 * 8
         assert ws == max(fwd, bwd)
         assert res == 0
