@@ -43,7 +43,9 @@ def profiled_traffic(prec):
     text = open(path).read()
     m = re.search(r"traffic per launch[^:]*:\s*([0-9.eE+]+) bytes", text)
     h = re.search(r"sha256 when counted:\s*([0-9a-f]{64})", text)
-    src = os.path.join(ROOT, "paper_2202_03411_amd", "csrc", "kernels.hip")
+    # the FP32 contraction is the three-product kernel of gauss.hip
+    src = os.path.join(ROOT, "paper_2202_03411_amd", "csrc",
+                       "gauss.hip" if prec == "fp32" else "kernels.hip")
     if not m or not h or hashlib.sha256(open(src, "rb").read()).hexdigest() != h.group(1):
         return None
     return float(m.group(1))
@@ -451,8 +453,11 @@ def main():
                      "peak": PEAK_TFLOPS[head_prec], "unit": "TFLOP/s",
                      "frac": head["contract_tflops"] / PEAK_TFLOPS[head_prec],
                      "traffic": profiled_traffic(head_prec),
-                     "kernel": f"fwd_kernel<{head_prec}>",
-                     "per_launch": f"{flops:.4e} algorithmic flops (8 per voxel-pixel term)"},
+                     "kernel": "fwd_g3_kernel" if head_prec == "fp32" else f"fwd_kernel<{head_prec}>",
+                     "per_launch": f"{flops:.4e} algorithmic flops (8 per voxel-pixel term)",
+                     "executed_flops_per_term": 6 if head_prec == "fp32" else 24,
+                     "frac_executed": head["contract_tflops"] / PEAK_TFLOPS[head_prec]
+                     * (6 if head_prec == "fp32" else 24) / 8.0},
         "scan": {"ms": head["scan_ms"], "gbs": scan_bytes / (head["scan_ms"] * 1e-3) / 1e9,
                  "frac_hbm": scan_bytes / (head["scan_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "variants": results,

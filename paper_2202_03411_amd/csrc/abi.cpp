@@ -259,7 +259,7 @@ msft_status make_plan(const msft_geometry* g, const double* q_host, int64_t npix
     }
     p->dims = make_dims(p->geo.npix, g->nx, g->ny, g->nz);
     // FP32 without the separable detector runs the Gauss (three-product) contraction
-    p->dims.g3 = false && g->precision == MSFT_FP32 && !p->separable;
+    p->dims.g3 = g->precision == MSFT_FP32 && !p->separable;
     size_t fwd_ws = align256(p->dims.wtile_bytes());
     size_t adj_ws = align256(make_adj_dims(p->dims).bytes());
     if (p->separable) {
