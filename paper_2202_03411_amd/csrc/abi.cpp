@@ -301,7 +301,7 @@ FwdArgs forward_args(const msft_plan_s* p, const void* wtiles, float* intensity,
     a.amplitude = amplitude;
     a.npix = p->dims.npix;
     a.ny = p->dims.ny;
-    a.nxc = p->dims.nxc;
+    a.nxc = p->dims.g3 ? p->dims.nxc3 : p->dims.nxc;
     a.nzb = p->dims.nzb;
     a.x_pad = p->dims.x_pad;
     a.group_blocks = a.group_tiles = a.a_waves = a.out_n = a.out_npad = 0;
@@ -382,6 +382,7 @@ ScanArgs scan_args(const msft_plan_s* p, const float* delta, const float* beta, 
     s.nzb = p->dims.nzb;
     s.strength = g.strength;
     s.g3 = p->dims.g3 ? 1 : 0;
+    s.nxc3 = p->dims.nxc3;
     const double k0 = (2.0 * 3.14159265358979323846) / g.wavelength;
     s.k0dz = (float)(k0 * g.dz);
     s.dV = (float)(g.dx * g.dy * g.dz);

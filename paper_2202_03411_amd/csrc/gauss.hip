@@ -12,10 +12,10 @@
 //
 // v_mfma_f32_32x32x2_f32: rows are the wave's 32 pixels, columns the 32 z of a
 // tile, K two x values (x parity = lane half).  Lane l holds output rows
-// 8j + 4h + u (j, u = 0..3, h = l / 32) at z = l % 32.  Four waves (one per SIMD)
-// make a pixel block; W tiles stream two per pipeline stage through a
-// double-buffered LDS ring, as in the four-product kernel.  Sums run in an order
-// fixed by the plan alone.
+// 8j + 4h + u (j, u = 0..3, h = l / 32) at z = l % 32.  Four waves make a pixel
+// block and two blocks share a CU (256 registers per lane), so each SIMD runs two
+// waves whose barriers are independent.  W tiles stream through a double-buffered
+// LDS ring.  Sums run in an order fixed by the plan alone.
 #include <hip/hip_runtime.h>
 
 #include "msft_internal.h"
@@ -29,8 +29,11 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int G3_THREADS = 64 * G3_WAVES;
-constexpr int G3_PLANE_F4 = 2 * ZB * G3_ROW_BYTES / 16;   // f32x4 per plane of a tile (512)
-constexpr int G3_TILE_F4 = G3_TILE_BYTES / 16;            // 1536
+constexpr int G3_PLANE_BYTES = 2 * ZB * G3_ROW_BYTES;     // 4 KB
+constexpr int G3_TILE_F4 = G3_TILE_BYTES / 16;            // 768
+constexpr int G3_COPY = G3_TILE_F4 / G3_THREADS;          // 16-byte pieces per thread per tile
+constexpr int G3_STEPS = G3_XC / 8;                       // f32x4 A values per plane
+static_assert(G3_COPY * G3_THREADS == G3_TILE_F4, "a tile is copied in whole pieces");
 
 // Pixel of Gauss wave wt at lane half h, output row r (0..15) of the lane.
 __device__ __forceinline__ int64_t g3_pixel(int64_t wt, int h, int r)
@@ -42,8 +45,8 @@ __device__ __forceinline__ int64_t g3_pixel(int64_t wt, int h, int r)
 // Plan-time tables.  T = exp(i phi), phi = -q . r, phases in FP64.
 // ---------------------------------------------------------------------------
 
-// A tiles [wt][xc][plane 3][g 8][lane 64][e 4] floats: lane (h, i) holds, for MFMA
-// step 4g + e, pixel wt*32 + i at x = xc*64 + 8g + 2e + h; planes Re T, Im T,
+// A tiles [wt][xc][plane 3][g 4][lane 64][e 4] floats: lane (h, i) holds, for MFMA
+// step 4g + e, pixel wt*32 + i at x = xc*32 + 8g + 2e + h; planes Re T, Im T,
 // Re T + Im T (the sum formed in FP64).
 __global__ void twiddle_txa_g3(float* txa, int64_t total, int64_t npix, int nx, int nxc,
                                const double* q, const double* xs)
@@ -52,12 +55,12 @@ __global__ void twiddle_txa_g3(float* txa, int64_t total, int64_t npix, int nx, 
     if (idx >= total) return;
     const int f = (int)(idx % (G3_TILE_BYTES / 4));
     const int64_t tile = idx / (G3_TILE_BYTES / 4);
-    const int plane = f / 2048, rem = f % 2048;
+    const int plane = f / (G3_PLANE_BYTES / 4), rem = f % (G3_PLANE_BYTES / 4);
     const int g = rem >> 8, lane = (rem >> 2) & 63, e = rem & 3;
     const int xc = (int)(tile % nxc);
     const int64_t wt = tile / nxc;
     const int64_t pix = wt * G3_WAVE_PIX + (lane & 31);
-    const int x = xc * XC + 8 * g + 2 * e + (lane >> 5);
+    const int x = xc * G3_XC + 8 * g + 2 * e + (lane >> 5);
     float v = 0.0f;
     if (pix < npix && x < nx) {
         double sn, cs;
@@ -116,36 +119,36 @@ __global__ void twiddle_tz_g3(float2* tz, int64_t total, int64_t npix, int nz, i
 // Contraction.
 // ---------------------------------------------------------------------------
 
-// The wave's A operand for one x chunk: Af[plane * 8 + g].
+// The wave's A operand for one x chunk: Af[plane * G3_STEPS + g].
 __device__ __forceinline__ void load_a_g3(const uint8_t* ta, int lane, f32x4* Af)
 {
 #pragma unroll
-    for (int k = 0; k < 24; ++k) Af[k] = ((const f32x4*)ta)[k * 64 + lane];
+    for (int k = 0; k < 3 * G3_STEPS; ++k) Af[k] = ((const f32x4*)ta)[k * 64 + lane];
 }
 
-// The three products of one W tile over the first 8 * ng slots (all 8 when FULL).
-// row: the lane's row (plane 0, h, z = col) of the tile in LDS; planes follow at
-// 64-row strides.
+// The three products of one W tile over its first xlen x (all G3_XC when FULL).
+// row: the lane's row (plane 0, h, z = col) of the tile in LDS; the planes follow
+// at G3_PLANE_BYTES.
 template <bool FULL>
 __device__ __forceinline__ void tile_g3(const uint8_t* row, int col, int xlen, const f32x4* Af,
                                         f32x16& P1, f32x16& P2, f32x16& P3)
 {
-    const int sw = col & 7;
+    const int sw = (col >> 1) & 3;
     P1 = f32x16{};
     P2 = f32x16{};
     P3 = f32x16{};
 #pragma unroll
-    for (int g = 0; g < 8; ++g) {
+    for (int g = 0; g < G3_STEPS; ++g) {
         if (FULL || 8 * g < xlen) {
             const int off = (g ^ sw) << 4;
             const f32x4 b1 = *(const f32x4*)(row + off);
-            const f32x4 b2 = *(const f32x4*)(row + 64 * G3_ROW_BYTES + off);
-            const f32x4 b3 = *(const f32x4*)(row + 128 * G3_ROW_BYTES + off);
+            const f32x4 b2 = *(const f32x4*)(row + G3_PLANE_BYTES + off);
+            const f32x4 b3 = *(const f32x4*)(row + 2 * G3_PLANE_BYTES + off);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 P1 = __builtin_amdgcn_mfma_f32_32x32x2f32(Af[g][e], b1[e], P1, 0, 0, 0);
-                P2 = __builtin_amdgcn_mfma_f32_32x32x2f32(Af[8 + g][e], b2[e], P2, 0, 0, 0);
-                P3 = __builtin_amdgcn_mfma_f32_32x32x2f32(Af[16 + g][e], b3[e], P3, 0, 0, 0);
+                P2 = __builtin_amdgcn_mfma_f32_32x32x2f32(Af[G3_STEPS + g][e], b2[e], P2, 0, 0, 0);
+                P3 = __builtin_amdgcn_mfma_f32_32x32x2f32(Af[2 * G3_STEPS + g][e], b3[e], P3, 0, 0, 0);
             }
         }
     }
@@ -166,14 +169,14 @@ __device__ __forceinline__ void combine_rotate(float* G, const f32x16& P1, const
     }
 }
 
-// All z blocks of one x chunk, two W tiles (y, y + 1) per pipeline stage; a lone
-// last tile is paired with the tile after it and its partner's rotation scaled
-// by 0.  t: next tile, k: next stage.
+// All z blocks of one x chunk, one W tile per pipeline stage; t: next tile.
 template <bool FULL>
 __device__ __forceinline__ void chunk_g3(const FwdArgs& a, int64_t wt, int64_t ntiles, const u32x4* gw,
-                                         uint8_t* lds, int xlen, const f32x4* Af, int64_t& t, int& k,
+                                         uint8_t* lds, int xlen, const f32x4* Af, int64_t& t,
                                          float* acc)
 {
+    // acc: the lane's 32 running sums in LDS, stride 64 floats (they change once per
+    // z block; keeping them out of registers leaves room for two waves per SIMD)
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int h = lane >> 5, col = lane & 31;
@@ -181,45 +184,27 @@ __device__ __forceinline__ void chunk_g3(const FwdArgs& a, int64_t wt, int64_t n
         float G[32];
 #pragma unroll
         for (int q = 0; q < 32; ++q) G[q] = 0.0f;
-        for (int y = 0; y < a.ny; y += 2) {
-            const int cnt = min(2, a.ny - y);
-            const int64_t tn = t + cnt;
-            const bool has_next = tn < ntiles;
-            u32x4 nx[12];
+        for (int y = 0; y < a.ny; ++y, ++t) {
+            const bool has_next = (t + 1) < ntiles;
+            u32x4 nx[G3_COPY];
             if (has_next) {
-                const int64_t tn1 = min(tn + 1, ntiles - 1);
 #pragma unroll
-                for (int u = 0; u < 6; ++u) {
-                    nx[u] = gw[tn * G3_TILE_F4 + u * G3_THREADS + tid];
-                    nx[6 + u] = gw[tn1 * G3_TILE_F4 + u * G3_THREADS + tid];
-                }
+                for (int u = 0; u < G3_COPY; ++u) nx[u] = gw[(t + 1) * G3_TILE_F4 + u * G3_THREADS + tid];
             }
-            const f32x4* typ0 = (const f32x4*)(a.ty + 2 * (((wt * a.ny + y) * 2 + h) * 16));
-            const f32x4* typ1 = (const f32x4*)(a.ty + 2 * (((wt * a.ny + y + cnt - 1) * 2 + h) * 16));
-            const float s1 = cnt == 2 ? 1.0f : 0.0f;
-            f32x4 ty0[8], ty1[8];
+            const f32x4* typ = (const f32x4*)(a.ty + 2 * (((wt * a.ny + y) * 2 + h) * 16));
+            f32x4 ty[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                ty0[u] = typ0[u];
-                ty1[u] = typ1[u] * s1;
-            }
-            const uint8_t* row = lds + (size_t)(k & 1) * 2 * G3_TILE_BYTES + (h * ZB + col) * G3_ROW_BYTES;
-            f32x16 A1, A2, A3, B1, B2, B3;
-            tile_g3<FULL>(row, col, xlen, Af, A1, A2, A3);
-            tile_g3<FULL>(row + G3_TILE_BYTES, col, xlen, Af, B1, B2, B3);
-            combine_rotate(G, A1, A2, A3, ty0);
-            combine_rotate(G, B1, B2, B3, ty1);
+            for (int u = 0; u < 8; ++u) ty[u] = typ[u];
+            const uint8_t* row = lds + (size_t)(t & 1) * G3_TILE_BYTES + (h * ZB + col) * G3_ROW_BYTES;
+            f32x16 P1, P2, P3;
+            tile_g3<FULL>(row, col, xlen, Af, P1, P2, P3);
+            combine_rotate(G, P1, P2, P3, ty);
             if (has_next) {
-                u32x4* nb = (u32x4*)(lds + (size_t)((k + 1) & 1) * 2 * G3_TILE_BYTES);
+                u32x4* nb = (u32x4*)(lds + (size_t)((t + 1) & 1) * G3_TILE_BYTES);
 #pragma unroll
-                for (int u = 0; u < 6; ++u) {
-                    nb[u * G3_THREADS + tid] = nx[u];
-                    nb[G3_TILE_F4 + u * G3_THREADS + tid] = nx[6 + u];
-                }
+                for (int u = 0; u < G3_COPY; ++u) nb[u * G3_THREADS + tid] = nx[u];
             }
             __syncthreads();
-            t += cnt;
-            ++k;
         }
         // acc[r] += Tz[r] * G[r]
         const f32x4* tzp = (const f32x4*)(a.tz + 2 * ((((wt * a.nzb + zb) * 2 + h) * ZB + col) * 16));
@@ -230,14 +215,14 @@ __device__ __forceinline__ void chunk_g3(const FwdArgs& a, int64_t wt, int64_t n
             for (int u = 0; u < 2; ++u) {
                 const int r = 2 * q + u;
                 const float tr = v[2 * u], ti = v[2 * u + 1];
-                acc[2 * r] += tr * G[2 * r] - ti * G[2 * r + 1];
-                acc[2 * r + 1] += tr * G[2 * r + 1] + ti * G[2 * r];
+                acc[(2 * r) * 64] += tr * G[2 * r] - ti * G[2 * r + 1];
+                acc[(2 * r + 1) * 64] += tr * G[2 * r + 1] + ti * G[2 * r];
             }
         }
     }
 }
 
-__device__ __forceinline__ void block_g3(const FwdArgs& a, int64_t block, uint8_t* lds)
+__device__ __forceinline__ void block_g3(const FwdArgs& a, int64_t block, uint8_t* lds, float* accs)
 {
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -245,38 +230,32 @@ __device__ __forceinline__ void block_g3(const FwdArgs& a, int64_t block, uint8_
     const int64_t ntiles = (int64_t)a.nxc * a.nzb * a.ny;
     const u32x4* gw = (const u32x4*)a.wtiles;
 
-    // first stage: tiles 0 and 1 -> LDS stage 0
-    {
-        const int64_t t1 = ntiles > 1 ? 1 : 0;
+    // first stage: tile 0 -> LDS buffer 0
 #pragma unroll
-        for (int u = 0; u < 6; ++u) {
-            ((u32x4*)lds)[u * G3_THREADS + tid] = gw[u * G3_THREADS + tid];
-            ((u32x4*)lds)[G3_TILE_F4 + u * G3_THREADS + tid] = gw[t1 * G3_TILE_F4 + u * G3_THREADS + tid];
-        }
-    }
+    for (int u = 0; u < G3_COPY; ++u) ((u32x4*)lds)[u * G3_THREADS + tid] = gw[u * G3_THREADS + tid];
     __syncthreads();
 
-    float acc[32];
+    float* accl = accs + wave * 32 * 64 + lane;   // [wave][q][lane]
 #pragma unroll
-    for (int q = 0; q < 32; ++q) acc[q] = 0.0f;
+    for (int q = 0; q < 32; ++q) accl[q * 64] = 0.0f;
 
     int64_t t = 0;
-    int k = 0;
     for (int xc = 0; xc < a.nxc; ++xc) {
-        const int xlen = min(XC, a.x_pad - xc * XC);
-        f32x4 Af[24];
+        const int xlen = min(G3_XC, a.x_pad - xc * G3_XC);
+        f32x4 Af[3 * G3_STEPS];
         load_a_g3(a.txa + (size_t)(wt * a.nxc + xc) * G3_TILE_BYTES, lane, Af);
         // one wait for the A operand per chunk (the memory counter is in order)
         __builtin_amdgcn_s_waitcnt(0);
-        if (xlen == XC) chunk_g3<true>(a, wt, ntiles, gw, lds, xlen, Af, t, k, acc);
-        else chunk_g3<false>(a, wt, ntiles, gw, lds, xlen, Af, t, k, acc);
+        if (xlen == G3_XC) chunk_g3<true>(a, wt, ntiles, gw, lds, xlen, Af, t, accl);
+        else chunk_g3<false>(a, wt, ntiles, gw, lds, xlen, Af, t, accl);
     }
     const int h = lane >> 5, col = lane & 31;
 
     // sum over the 32 z lanes of each half (fixed butterfly order)
+    float acc[32];
 #pragma unroll
     for (int q = 0; q < 32; ++q) {
-        float v = acc[q];
+        float v = accl[q * 64];
         v += __shfl_xor(v, 16, 32);
         v += __shfl_xor(v, 8, 32);
         v += __shfl_xor(v, 4, 32);
@@ -297,20 +276,22 @@ __device__ __forceinline__ void block_g3(const FwdArgs& a, int64_t block, uint8_
     }
 }
 
-__global__ __launch_bounds__(G3_THREADS) void fwd_g3_kernel(FwdArgs a, int64_t block_begin)
+__global__ __launch_bounds__(G3_THREADS, 2) void fwd_g3_kernel(FwdArgs a, int64_t block_begin)
 {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[4 * G3_TILE_BYTES];
-    block_g3(a, block_begin + blockIdx.x, lds);
+    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * G3_TILE_BYTES];
+    __shared__ float accs[G3_WAVES * 32 * 64];
+    block_g3(a, block_begin + blockIdx.x, lds, accs);
 }
 
 // Batched form: one workgroup per (request, pixel block) item in the host's order.
-__global__ __launch_bounds__(G3_THREADS) void fwd_g3_batch_kernel(BatchArgs b)
+__global__ __launch_bounds__(G3_THREADS, 2) void fwd_g3_batch_kernel(BatchArgs b)
 {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[4 * G3_TILE_BYTES];
+    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * G3_TILE_BYTES];
+    __shared__ float accs[G3_WAVES * 32 * 64];
     const int32_t it = blockIdx.x;
     int r = 0;
     while (r + 1 < b.nreq && b.item_begin[r + 1] <= it) ++r;
-    block_g3(b.req[r], (int64_t)b.block_begin[r] + (it - b.item_begin[r]), lds);
+    block_g3(b.req[r], (int64_t)b.block_begin[r] + (it - b.item_begin[r]), lds, accs);
 }
 
 int grid_for(int64_t total, int block) { return (int)ceil_div(total, block); }
@@ -323,9 +304,9 @@ int launch_twiddles_g3(const Dims& d, const double* q_dev, const double* xs_dev,
     hipStream_t s = (hipStream_t)stream;
     const int B = 256;
     const int64_t nwt = d.nblocks * G3_WAVES;
-    const int64_t na = nwt * d.nxc * (G3_TILE_BYTES / 4);
+    const int64_t na = nwt * d.nxc3 * (G3_TILE_BYTES / 4);
     hipLaunchKernelGGL(twiddle_txa_g3, dim3(grid_for(na, B)), dim3(B), 0, s, (float*)txa, na, d.npix,
-                       d.nx, d.nxc, q_dev, xs_dev);
+                       d.nx, d.nxc3, q_dev, xs_dev);
     const int64_t nty = nwt * d.ny * G3_WAVE_PIX;
     hipLaunchKernelGGL(twiddle_ty_g3, dim3(grid_for(nty, B)), dim3(B), 0, s, (float2*)ty, nty, d.npix,
                        d.ny, q_dev, ys_dev);

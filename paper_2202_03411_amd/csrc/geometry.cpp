@@ -145,6 +145,7 @@ Dims make_dims(int64_t npix, int nx, int ny, int nz)
     d.nz = nz;
     d.x_pad = (int)ceil_div(nx, XPAD) * XPAD;
     d.nxc = (int)ceil_div(nx, XC);
+    d.nxc3 = (int)ceil_div(nx, G3_XC);
     d.nzb = (int)ceil_div(nz, ZB);
     return d;
 }

@@ -231,15 +231,15 @@ __device__ __forceinline__ void store_w(uint8_t* tile, int lane, int zl, float w
     }
 }
 
-// The Gauss tile layout: rows (plane, h, z) of 8 slots of 4 floats, x = 8 g + 2 e + h,
-// slot g XOR-swizzled with z; planes Wr, Wi, Wr + Wi.
-__device__ __forceinline__ void store_w_g3(uint8_t* tile, int lane, int zl, float wr, float wi)
+// The Gauss tile layout: rows (plane, h, z) of 4 slots of 4 floats, x = 8 g + 2 e + h
+// within the tile's G3_XC, slot g XOR-swizzled with (z / 2) % 4; planes Wr, Wi, Wr + Wi.
+__device__ __forceinline__ void store_w_g3(uint8_t* tile, int xl, int zl, float wr, float wi)
 {
-    const int h = lane & 1, e = (lane >> 1) & 3, g = lane >> 3;
-    const int off = (h * ZB + zl) * G3_ROW_BYTES + ((g ^ (zl & 7)) << 4) + 4 * e;
+    const int h = xl & 1, e = (xl >> 1) & 3, g = xl >> 3;
+    const int off = (h * ZB + zl) * G3_ROW_BYTES + ((g ^ ((zl >> 1) & 3)) << 4) + 4 * e;
     *(float*)(tile + off) = wr;
-    *(float*)(tile + 64 * G3_ROW_BYTES + off) = wi;
-    *(float*)(tile + 128 * G3_ROW_BYTES + off) = wr + wi;
+    *(float*)(tile + 2 * ZB * G3_ROW_BYTES + off) = wi;
+    *(float*)(tile + 4 * ZB * G3_ROW_BYTES + off) = wr + wi;
 }
 
 template <int PREC, bool G3>
@@ -299,7 +299,11 @@ __global__ __launch_bounds__(64 * SCAN_WAVES) void scan_kernel(ScanArgs a)
         carry_d += rd;
         if (!active) continue;
 
-        uint8_t* tile = a.wtiles + ((size_t)(xc * a.nzb + zb) * a.ny + y) * (G3 ? G3_TILE_BYTES : TILE_BYTES);
+        // Gauss tiles hold G3_XC x: the lane's x chunk is 2 xc + lane / 32 (none past nxc3)
+        const int xc3 = 2 * xc + (lane >> 5);
+        if (G3 && xc3 >= a.nxc3) continue;
+        uint8_t* tile = G3 ? a.wtiles + ((size_t)(xc3 * a.nzb + zb) * a.ny + y) * G3_TILE_BYTES
+                           : a.wtiles + ((size_t)(xc * a.nzb + zb) * a.ny + y) * TILE_BYTES;
 #pragma unroll
         for (int k = 0; k < ZB; ++k) {
             float wr, wi;
@@ -320,7 +324,7 @@ __global__ __launch_bounds__(64 * SCAN_WAVES) void scan_kernel(ScanArgs a)
                 wr = a.dV * (chr * tr - chi * ti);
                 wi = a.dV * (chr * ti + chi * tr);
             }
-            if (G3) store_w_g3(tile, lane, k, wr, wi);
+            if (G3) store_w_g3(tile, lane & 31, k, wr, wi);
             else store_w<PREC>(tile, lane, k, wr, wi);
             Sb += b[k];
             Sd += d[k];

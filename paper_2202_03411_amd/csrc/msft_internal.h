@@ -41,14 +41,16 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // each a real MFMA contraction over x with pixels as rows and z as columns, so
 // the matrix cores do 6 real flops per complex multiply-add instead of 8.  A wave
 // owns G3_WAVE_PIX pixels (the 32 MFMA rows); G3_WAVES waves make one BLOCK_PIX
-// pixel block.  A W tile (XC x, ZB z, one y) holds the three planes Wr, Wi,
-// Wr + Wi as rows (plane, x parity h, z) of 32 floats; an A tile (one wave, one x
-// chunk) holds Tr, Ti, Tr + Ti in MFMA register order.
+// pixel block, and two such workgroups share a CU.  A W tile (G3_XC x, ZB z, one
+// y) holds the three planes Wr, Wi, Wr + Wi as rows (plane, x parity h, z) of 16
+// floats; an A tile (one wave, one x chunk) holds Tr, Ti, Tr + Ti in MFMA
+// register order.
 // ---------------------------------------------------------------------------
+constexpr int G3_XC = 32;
 constexpr int G3_WAVE_PIX = 32;
 constexpr int G3_WAVES = 4;
-constexpr int G3_TILE_BYTES = 3 * 2 * ZB * 128;   // 24 KB: W tile or A tile
-constexpr int G3_ROW_BYTES = 128;
+constexpr int G3_ROW_BYTES = G3_XC / 2 * 4;                 // 64
+constexpr int G3_TILE_BYTES = 3 * 2 * ZB * G3_ROW_BYTES;    // 12 KB: W tile or A tile
 static_assert(G3_WAVE_PIX * G3_WAVES == BLOCK_PIX, "a Gauss block is one pixel block");
 
 // Host geometry (FP64, built without FMA contraction).
@@ -78,11 +80,12 @@ struct Dims {
     int64_t npix, nblocks, nwt;   // pixels, workgroup blocks, wave tiles
     int nx, ny, nz, x_pad, nxc, nzb;
     bool g3 = false;              // Gauss (3M) tiles: FP32 flat detector and q lists
-    int64_t ntiles() const { return (int64_t)nxc * nzb * ny; }
+    int nxc3 = 0;                 // x chunks of G3_XC
+    int64_t ntiles() const { return (int64_t)(g3 ? nxc3 : nxc) * nzb * ny; }
     size_t wtile_bytes() const { return (size_t)ntiles() * (g3 ? G3_TILE_BYTES : TILE_BYTES); }
     size_t txa_bytes() const
     {
-        return g3 ? (size_t)nblocks * G3_WAVES * nxc * G3_TILE_BYTES : (size_t)nwt * nxc * TILE_BYTES;
+        return g3 ? (size_t)nblocks * G3_WAVES * nxc3 * G3_TILE_BYTES : (size_t)nwt * nxc * TILE_BYTES;
     }
     // (the same sizes in the Gauss layout: [wave][y][h][16] and [wave][zb][h][z][16])
     size_t ty_bytes() const { return (size_t)nwt * ny * WAVE_PIX * 8; }
@@ -157,6 +160,7 @@ struct ScanArgs {
     int32_t nx, ny, nz, nxc, nzb;
     int32_t strength;
     int32_t g3;   // write the Gauss tile layout (FP32 only)
+    int32_t nxc3; // its x chunks of G3_XC
     float k0dz;   // k0 * dz
     float dV;     // dx * dy * dz
 };
