@@ -37,11 +37,12 @@ def profiled_traffic(prec):
     summary, or None when the kernel source has changed since it was counted."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", f"fwd_kernel_{prec}_star128_det512_traffic.md")
+    kernel = "fwd_g3_kernel_fp32" if prec == "fp32" else f"fwd_kernel_{prec}"
+    path = os.path.join(ROOT, "profiles", f"{kernel}_star128_det512_traffic.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
-    m = re.search(r"traffic per launch[^:]*:\s*([0-9.eE+]+) bytes", text)
+    m = re.search(r"^fwd[^\n]*traffic per launch[^:]*:\s*([0-9.eE+]+) bytes", text, re.M)
     h = re.search(r"sha256 when counted:\s*([0-9a-f]{64})", text)
     # the FP32 contraction is the three-product kernel of gauss.hip
     src = os.path.join(ROOT, "paper_2202_03411_amd", "csrc",
@@ -400,7 +401,8 @@ def main():
                    "terms_per_s": P * V / (ms * 1e-3),
                    "contract_tflops": flops / (cms * 1e-3) / 1e12,
                    "resident_bytes": plan.resident_bytes, "workspace_bytes": plan.workspace_bytes,
-                   "error_vs_fp64_oracle": oracle_error(wl, r["intensity"])}
+                   "error_vs_fp64_oracle": oracle_error(wl, r["intensity"]),
+                   "intensity": r["intensity"]}
             print(f"[bench] {prec}: {ms:.3f} ms/pattern (contract {cms:.3f} ms, scan {sms:.4f} ms), "
                   f"{res['contract_tflops']:.1f} TFLOP/s algorithmic", file=sys.stderr, flush=True)
             if prec == "fp32" and not args.only:
