@@ -5,9 +5,9 @@
 //   R_v = sum_p h_p exp(-i q_p . r_v),        dL = sum_v 2 Re(R_v dw_v),
 // the transposed contraction of the forward model: pixels are the K dimension.
 //  adj_prep      h_p from g and the saved amplitudes.
-//  adj_contract  R over one pixel group per workgroup (split K), MFMA; the
-//                twiddles are regenerated per pixel chunk into LDS from FP64
-//                phases, not read from the plan.
+//  adj_contract  R over one pixel group per workgroup (split K), MFMA in the
+//                three-product (Gauss) form; the twiddles are regenerated per
+//                pixel chunk into LDS from FP64 phases, not read from the plan.
 //  adj_finalize  sums the pixel groups in a fixed order and applies the chain
 //                rule through w = dV (n^2 - 1) T and the column scan (Eqs. (7)-(9)),
 //                one wave per column.
@@ -54,17 +54,21 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b)
 }
 
 // Workgroup (s, xc, zb, yb): R for x chunk xc (64 x), z block zb (32 z), the 8 y
-// values yb*8 .. yb*8+7 (one per wave), summed over pixel group s.  Per chunk of
-// ADJ_CHUNK pixels the workgroup first writes into LDS
-//   A fragments of Tx = exp(-i q_x x) for the 64 x values, in register order
-//       (row tile rt = x/16, lane (h, i): row i = (x%16, re|im), k-half h),
+// values yb*8 .. yb*8+7 (one per wave), summed over pixel group s.  The complex
+// sum R = sum_p T B (T = exp(-i q_x x), B = Ty G) runs in Gauss's form: three real
+// contractions P1 = sum Tr Br, P2 = sum Ti Bi, P3 = sum (Tr + Ti)(Br + Bi), then
+// Re R = P1 - P2, Im R = P3 - P1 - P2, with x as MFMA rows (two row tiles of 32),
+// z as columns and pixels as K (two per v_mfma_f32_32x32x2_f32, one per lane
+// half).  Per chunk of ADJ_CHUNK pixels the workgroup first writes into LDS
+//   the A values Tr, Ti, Tr + Ti of pixel pair m for lane (h, i): pixel 2m + h,
+//       x = rt*32 + i, at afrag[(m * 64 + lane) * 8 + plane * 2 + rt],
 //   G = h_p exp(-i q_z z) for the 32 z values, and Ty = exp(-i q_y y) for 8 y,
-// then every wave runs 4 v_mfma_f32_32x32x2_f32 per pixel (one per row tile)
-// with B = component h of Ty * G.  Runs of 8 x (4 z) share one FP64-reduced
-// anchor and a step exp(-i q d) applied by complex multiplication.
+// then every wave runs 6 MFMAs per pixel pair with B formed on the fly.  Runs of
+// 8 x (4 z) share one FP64-reduced anchor and a step exp(-i q d) applied by
+// complex multiplication.
 __global__ __launch_bounds__(512) void adj_contract(AdjArgs a)
 {
-    __shared__ __attribute__((aligned(16))) float afrag[ADJ_CHUNK * 64 * 4];
+    __shared__ __attribute__((aligned(16))) float afrag[ADJ_CHUNK / 2 * 64 * 8];
     __shared__ __attribute__((aligned(16))) float2 gz[ADJ_CHUNK * ZB];
     __shared__ __attribute__((aligned(16))) float2 ty[ADJ_CHUNK * 8];
 
@@ -81,9 +85,9 @@ __global__ __launch_bounds__(512) void adj_contract(AdjArgs a)
     const int y = yb * 8 + wave;
     const bool wave_active = y < a.ny;
 
-    f32x16 C[4];
+    f32x16 P1[2], P2[2], P3[2];
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt) C[rt] = f32x16{};
+    for (int rt = 0; rt < 2; ++rt) P1[rt] = P2[rt] = P3[rt] = f32x16{};
 
     const int64_t p_begin = (int64_t)s * a.group_pix;
     const int64_t p_end = min(p_begin + a.group_pix, a.npix_pad);
@@ -107,16 +111,15 @@ __global__ __launch_bounds__(512) void adj_contract(AdjArgs a)
                 const int x0 = xc * XC + xl0;
                 float2 t = cis_reduced(-(qx * (a.xs0 + (double)x0 * a.dx)));
                 const float2 e = cis_reduced(-(qx * a.dx));
+                float* base = afrag + ((gp >> 1) * 64 + (gp & 1) * 32) * 8;
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
                     const int xl = xl0 + k;
                     const float2 v = (x0 + k < a.nx) ? t : make_float2(0.0f, 0.0f);
-                    const int rt = xl >> 4, i0 = 2 * (xl & 15);
-                    float* base = afrag + gp * 256;
-                    base[(i0) * 4 + rt] = v.x;            // h=0, re row: Re T
-                    base[(i0 + 1) * 4 + rt] = v.y;        // h=0, im row: Im T
-                    base[(32 + i0) * 4 + rt] = -v.y;      // h=1, re row: -Im T
-                    base[(32 + i0 + 1) * 4 + rt] = v.x;   // h=1, im row: Re T
+                    float* f = base + (xl & 31) * 8 + (xl >> 5);
+                    f[0] = v.x;           // plane 0: Re T
+                    f[2] = v.y;           // plane 1: Im T
+                    f[4] = v.x + v.y;     // plane 2: Re T + Im T
                     t = cmul(t, e);
                 }
             }
@@ -140,36 +143,41 @@ __global__ __launch_bounds__(512) void adj_contract(AdjArgs a)
             }
         }
         __syncthreads();
-        // ---- contraction over the chunk's pixels ----
+        // ---- contraction over the chunk's pixel pairs ----
         if (wave_active) {
 #pragma unroll 4
-            for (int pl = 0; pl < ADJ_CHUNK; ++pl) {
-                const f32x4 av = *(const f32x4*)(afrag + (pl * 64 + lane) * 4);
+            for (int m = 0; m < ADJ_CHUNK / 2; ++m) {
+                const f32x4 a0 = *(const f32x4*)(afrag + (m * 64 + lane) * 8);
+                const f32x4 a1 = *(const f32x4*)(afrag + (m * 64 + lane) * 8 + 4);
+                const int pl = 2 * m + h;
                 const float2 g = gz[pl * ZB + col];
                 const float2 t = ty[pl * 8 + wave];
-                const float bv = (h == 0) ? (t.x * g.x - t.y * g.y) : (t.x * g.y + t.y * g.x);
-                C[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[0], bv, C[0], 0, 0, 0);
-                C[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[1], bv, C[1], 0, 0, 0);
-                C[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[2], bv, C[2], 0, 0, 0);
-                C[3] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[3], bv, C[3], 0, 0, 0);
+                const float br = t.x * g.x - t.y * g.y;
+                const float bi = t.x * g.y + t.y * g.x;
+                const float bs = br + bi;
+#pragma unroll
+                for (int rt = 0; rt < 2; ++rt) {
+                    P1[rt] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[rt], br, P1[rt], 0, 0, 0);
+                    P2[rt] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[2 + rt], bi, P2[rt], 0, 0, 0);
+                    P3[rt] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[rt], bs, P3[rt], 0, 0, 0);
+                }
             }
         }
         __syncthreads();
     }
 
     if (!wave_active) return;
-    // rows 8j + 4h + u of row tile rt: x = rt*16 + 4j + 2h + u/2, component u&1
+    // row 8j + 4h + u of row tile rt is x = rt*32 + 8j + 4h + u
     const int64_t X2 = (int64_t)a.nxc * XC, NZ2 = (int64_t)a.nzb * ZB;
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt) {
+    for (int rt = 0; rt < 2; ++rt) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-#pragma unroll
-            for (int u2 = 0; u2 < 2; ++u2) {
-                const int xl = rt * 16 + 4 * j + 2 * h + u2;
-                const int64_t idx = (((int64_t)s * X2 + xc * XC + xl) * a.ny + y) * NZ2 + zb * ZB + col;
-                ((float2*)a.rpart)[idx] = make_float2(C[rt][4 * j + 2 * u2], C[rt][4 * j + 2 * u2 + 1]);
-            }
+        for (int r = 0; r < 16; ++r) {
+            const int xl = rt * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+            const int64_t idx = (((int64_t)s * X2 + xc * XC + xl) * a.ny + y) * NZ2 + zb * ZB + col;
+            const float re = P1[rt][r] - P2[rt][r];
+            const float im = (P3[rt][r] - P1[rt][r]) - P2[rt][r];
+            ((float2*)a.rpart)[idx] = make_float2(re, im);
         }
     }
 }
