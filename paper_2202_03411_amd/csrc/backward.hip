@@ -61,7 +61,8 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b)
 // z as columns and pixels as K (two per v_mfma_f32_32x32x2_f32, one per lane
 // half).  Per chunk of ADJ_CHUNK pixels the workgroup first writes into LDS
 //   the A values Tr, Ti, Tr + Ti of pixel pair m for lane (h, i): pixel 2m + h,
-//       x = rt*32 + i, at afrag[(m * 64 + lane) * 8 + plane * 2 + rt],
+//       x = rt*32 + i, value k = plane * 2 + rt at afrag[((2m + k / 4) * 64 + lane) * 4
+//       + k % 4] (each 16-byte read lane-contiguous, free of bank conflicts),
 //   G = h_p exp(-i q_z z) for the 32 z values, and Ty = exp(-i q_y y) for 8 y,
 // then every wave runs 6 MFMAs per pixel pair with B formed on the fly.  Runs of
 // 8 x (4 z) share one FP64-reduced anchor and a step exp(-i q d) applied by
@@ -111,15 +112,15 @@ __global__ __launch_bounds__(512) void adj_contract(AdjArgs a)
                 const int x0 = xc * XC + xl0;
                 float2 t = cis_reduced(-(qx * (a.xs0 + (double)x0 * a.dx)));
                 const float2 e = cis_reduced(-(qx * a.dx));
-                float* base = afrag + ((gp >> 1) * 64 + (gp & 1) * 32) * 8;
+                float* base = afrag + ((gp >> 1) * 128 + (gp & 1) * 32) * 4;
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
                     const int xl = xl0 + k;
                     const float2 v = (x0 + k < a.nx) ? t : make_float2(0.0f, 0.0f);
-                    float* f = base + (xl & 31) * 8 + (xl >> 5);
-                    f[0] = v.x;           // plane 0: Re T
-                    f[2] = v.y;           // plane 1: Im T
-                    f[4] = v.x + v.y;     // plane 2: Re T + Im T
+                    float* f = base + (xl & 31) * 4 + (xl >> 5);
+                    f[0] = v.x;               // plane 0: Re T
+                    f[2] = v.y;               // plane 1: Im T
+                    f[64 * 4] = v.x + v.y;    // plane 2: Re T + Im T (second half)
                     t = cmul(t, e);
                 }
             }
@@ -147,8 +148,8 @@ __global__ __launch_bounds__(512) void adj_contract(AdjArgs a)
         if (wave_active) {
 #pragma unroll 4
             for (int m = 0; m < ADJ_CHUNK / 2; ++m) {
-                const f32x4 a0 = *(const f32x4*)(afrag + (m * 64 + lane) * 8);
-                const f32x4 a1 = *(const f32x4*)(afrag + (m * 64 + lane) * 8 + 4);
+                const f32x4 a0 = *(const f32x4*)(afrag + ((2 * m) * 64 + lane) * 4);
+                const f32x4 a1 = *(const f32x4*)(afrag + ((2 * m + 1) * 64 + lane) * 4);
                 const int pl = 2 * m + h;
                 const float2 g = gz[pl * ZB + col];
                 const float2 t = ty[pl * 8 + wave];

@@ -155,7 +155,7 @@ __device__ __forceinline__ void tile_g3(const uint8_t* row, int col, int xlen, c
 }
 
 // G[r] += Ty[r] * C[r], C = (P1 - P2) + i (P3 - P1 - P2); G interleaved re, im;
-// ty: 8 x f32x4 = 16 complex.
+// ty: 8 x f32x4 = 16 complex.  Each component takes two chained FMAs into G.
 __device__ __forceinline__ void combine_rotate(float* G, const f32x16& P1, const f32x16& P2,
                                                const f32x16& P3, const f32x4* ty)
 {
@@ -164,8 +164,8 @@ __device__ __forceinline__ void combine_rotate(float* G, const f32x16& P1, const
         const float cr = P1[r] - P2[r];
         const float ci = (P3[r] - P1[r]) - P2[r];
         const float tr = ty[r >> 1][2 * (r & 1)], ti = ty[r >> 1][2 * (r & 1) + 1];
-        G[2 * r] += tr * cr - ti * ci;
-        G[2 * r + 1] += tr * ci + ti * cr;
+        G[2 * r] = __builtin_fmaf(-ti, ci, __builtin_fmaf(tr, cr, G[2 * r]));
+        G[2 * r + 1] = __builtin_fmaf(ti, cr, __builtin_fmaf(tr, ci, G[2 * r + 1]));
     }
 }
 

@@ -455,16 +455,17 @@ __device__ __forceinline__ f32x16 tile_product(const uint8_t* row, int col, int 
     return tile_mfma_partial<PREC>(zero, row, col, xlen, Af, Ahi, Alo);
 }
 
-// G[m] += s * Ty[m] * C[m] for the 8 complex slots m = 2j + u of a lane: C rows
+// G[m] += Ty[m] * C[m] for the 8 complex slots m = 2j + u of a lane: C rows
 // 4j + 2u (re) and 4j + 2u + 1 (im) of the MFMA result; ty: 4 x f32x4 of Ty.
+// Each component takes two chained FMAs into G.
 __device__ __forceinline__ void rotate_add(float* G, const f32x16& C, const f32x4* ty)
 {
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
         const int r = 4 * (m >> 1) + 2 * (m & 1);
         const float tr = ty[m >> 1][2 * (m & 1)], ti = ty[m >> 1][2 * (m & 1) + 1];
-        G[2 * m] += tr * C[r] - ti * C[r + 1];
-        G[2 * m + 1] += tr * C[r + 1] + ti * C[r];
+        G[2 * m] = __builtin_fmaf(-ti, C[r + 1], __builtin_fmaf(tr, C[r], G[2 * m]));
+        G[2 * m + 1] = __builtin_fmaf(ti, C[r], __builtin_fmaf(tr, C[r + 1], G[2 * m + 1]));
     }
 }
 
@@ -474,7 +475,7 @@ __device__ __forceinline__ void rotate_add(float* G, const f32x16& C, const f32x
 // ring of 2 x 2 tiles, so one barrier serves two tiles, each wave runs two
 // independent MFMA chains, and the first tile's Ty rotation can issue under the
 // second chain.  A lone last tile (odd ny) is paired with whatever tile follows
-// and its partner's rotation is scaled by 0.
+// and its partner's rotation is scaled by 0 (a branch there measured slower).
 // !ROT (second stage of the separable detector): the contraction already summed
 // over y, so each z block is one tile, added to G without a Ty factor; Tz is
 // loaded at the start of the z block to complete under the MFMA chain.
