@@ -60,17 +60,23 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b)
 // Re R = P1 - P2, Im R = P3 - P1 - P2, with x as MFMA rows (two row tiles of 32),
 // z as columns and pixels as K (two per v_mfma_f32_32x32x2_f32, one per lane
 // half).  Per chunk of ADJ_CHUNK pixels the workgroup first writes into LDS
-//   the A values Tr, Ti, Tr + Ti of pixel pair m for lane (h, i): pixel 2m + h,
-//       x = rt*32 + i, value k = plane * 2 + rt at afrag[((2m + k / 4) * 64 + lane) * 4
-//       + k % 4] (each 16-byte read lane-contiguous, free of bank conflicts),
+//   the A values Tr, Ti, Tr + Ti as planes of rows per pixel, x = rt*32 + i at
+//       element 2i + rt of the row (rows padded, see below),
 //   G = h_p exp(-i q_z z) for the 32 z values, and Ty = exp(-i q_y y) for 8 y,
-// then every wave runs 6 MFMAs per pixel pair with B formed on the fly.  Runs of
-// 8 x (4 z) share one FP64-reduced anchor and a step exp(-i q d) applied by
+// then every wave runs 6 MFMAs per pixel pair with B formed on the fly: lane
+// (h, i) reads the (x = i, x = 32 + i) pair of pixel 2m + h from each plane.  Runs
+// of 8 x (4 z) share one FP64-reduced anchor and a step exp(-i q d) applied by
 // complex multiplication.
+//
+// LDS row strides (floats, float2) of the A values and of G per pixel: padded so
+// that a generation write of 64 lanes (8 pixels x 8 runs) meets 64 distinct banks.
+constexpr int ADJ_AROW = XC + 2;
+constexpr int ADJ_GROW = ZB + 1;
+
 __global__ __launch_bounds__(512) void adj_contract(AdjArgs a)
 {
-    __shared__ __attribute__((aligned(16))) float afrag[ADJ_CHUNK / 2 * 64 * 8];
-    __shared__ __attribute__((aligned(16))) float2 gz[ADJ_CHUNK * ZB];
+    __shared__ __attribute__((aligned(16))) float afrag[3 * ADJ_CHUNK * ADJ_AROW];
+    __shared__ __attribute__((aligned(16))) float2 gz[ADJ_CHUNK * ADJ_GROW];
     __shared__ __attribute__((aligned(16))) float2 ty[ADJ_CHUNK * 8];
 
     const int tid = threadIdx.x;
@@ -112,15 +118,15 @@ __global__ __launch_bounds__(512) void adj_contract(AdjArgs a)
                 const int x0 = xc * XC + xl0;
                 float2 t = cis_reduced(-(qx * (a.xs0 + (double)x0 * a.dx)));
                 const float2 e = cis_reduced(-(qx * a.dx));
-                float* base = afrag + ((gp >> 1) * 128 + (gp & 1) * 32) * 4;
+                float* base = afrag + gp * ADJ_AROW;
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
                     const int xl = xl0 + k;
                     const float2 v = (x0 + k < a.nx) ? t : make_float2(0.0f, 0.0f);
-                    float* f = base + (xl & 31) * 4 + (xl >> 5);
-                    f[0] = v.x;               // plane 0: Re T
-                    f[2] = v.y;               // plane 1: Im T
-                    f[64 * 4] = v.x + v.y;    // plane 2: Re T + Im T (second half)
+                    float* f = base + (xl & 31) * 2 + (xl >> 5);
+                    f[0] = v.x;                                 // plane 0: Re T
+                    f[ADJ_CHUNK * ADJ_AROW] = v.y;              // plane 1: Im T
+                    f[2 * ADJ_CHUNK * ADJ_AROW] = v.x + v.y;    // plane 2: Re T + Im T
                     t = cmul(t, e);
                 }
             }
@@ -132,7 +138,7 @@ __global__ __launch_bounds__(512) void adj_contract(AdjArgs a)
                 const float2 e = cis_reduced(-(qz * a.dz));
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    gz[gp * ZB + zl0 + k] = (z0 + k < a.nz) ? cmul(hp, t) : make_float2(0.0f, 0.0f);
+                    gz[gp * ADJ_GROW + zl0 + k] = (z0 + k < a.nz) ? cmul(hp, t) : make_float2(0.0f, 0.0f);
                     t = cmul(t, e);
                 }
             }
@@ -145,23 +151,27 @@ __global__ __launch_bounds__(512) void adj_contract(AdjArgs a)
         }
         __syncthreads();
         // ---- contraction over the chunk's pixel pairs ----
+        // The next pair's A values, G and Ty are read from LDS before this pair's
+        // MFMAs are issued, so the reads complete under them.
         if (wave_active) {
+            // lane (h, i) reads, per plane, the pair (x = i, x = 32 + i) of pixel 2m + h
+            const float* af = afrag + h * ADJ_AROW + 2 * col;
 #pragma unroll 4
             for (int m = 0; m < ADJ_CHUNK / 2; ++m) {
-                const f32x4 a0 = *(const f32x4*)(afrag + ((2 * m) * 64 + lane) * 4);
-                const f32x4 a1 = *(const f32x4*)(afrag + ((2 * m + 1) * 64 + lane) * 4);
-                const int pl = 2 * m + h;
-                const float2 g = gz[pl * ZB + col];
-                const float2 t = ty[pl * 8 + wave];
+                const float2 a0 = *(const float2*)(af + 2 * m * ADJ_AROW);
+                const float2 a1 = *(const float2*)(af + ADJ_CHUNK * ADJ_AROW + 2 * m * ADJ_AROW);
+                const float2 a2 = *(const float2*)(af + 2 * ADJ_CHUNK * ADJ_AROW + 2 * m * ADJ_AROW);
+                const float2 g = gz[(2 * m + h) * ADJ_GROW + col];
+                const float2 t = ty[(2 * m + h) * 8 + wave];
                 const float br = t.x * g.x - t.y * g.y;
                 const float bi = t.x * g.y + t.y * g.x;
                 const float bs = br + bi;
-#pragma unroll
-                for (int rt = 0; rt < 2; ++rt) {
-                    P1[rt] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[rt], br, P1[rt], 0, 0, 0);
-                    P2[rt] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[2 + rt], bi, P2[rt], 0, 0, 0);
-                    P3[rt] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[rt], bs, P3[rt], 0, 0, 0);
-                }
+                P1[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.x, br, P1[0], 0, 0, 0);
+                P1[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.y, br, P1[1], 0, 0, 0);
+                P2[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.x, bi, P2[0], 0, 0, 0);
+                P2[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.y, bi, P2[1], 0, 0, 0);
+                P3[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a2.x, bs, P3[0], 0, 0, 0);
+                P3[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a2.y, bs, P3[1], 0, 0, 0);
             }
         }
         __syncthreads();
