@@ -676,14 +676,20 @@ __global__ __launch_bounds__(512) void fwd_batch_kernel(BatchArgs b)
     fwd_block<PREC, true>(b.req[r], (int64_t)b.block_begin[r] + (it - b.item_begin[r]), lds);
 }
 
+// (FP32 with the Ty rotation, the flat detector, runs the three-product kernel of
+// gauss.hip; here FP32 serves the separable detector's second stage only.)
 template <bool ROT>
 static void launch_fwd(int precision, const FwdArgs& a, int64_t block_begin, int64_t nblocks,
                        hipStream_t s)
 {
-    if (precision == MSFT_FP32)
-        hipLaunchKernelGGL((fwd_kernel<MSFT_FP32, ROT>), dim3((unsigned)nblocks), dim3(512), 0, s, a,
-                           block_begin);
-    else if (precision == MSFT_BF16X3)
+    if constexpr (!ROT) {
+        if (precision == MSFT_FP32) {
+            hipLaunchKernelGGL((fwd_kernel<MSFT_FP32, ROT>), dim3((unsigned)nblocks), dim3(512), 0, s,
+                               a, block_begin);
+            return;
+        }
+    }
+    if (precision == MSFT_BF16X3)
         hipLaunchKernelGGL((fwd_kernel<MSFT_BF16X3, ROT>), dim3((unsigned)nblocks), dim3(512), 0, s, a,
                            block_begin);
     else
@@ -695,6 +701,7 @@ int launch_forward(int precision, const FwdArgs& a, int64_t block_begin, int64_t
                    bool rotate, void* stream)
 {
     if (nblocks <= 0) return 0;
+    if (rotate && precision == MSFT_FP32) return (int)hipErrorInvalidValue;
     if (rotate) launch_fwd<true>(precision, a, block_begin, nblocks, (hipStream_t)stream);
     else launch_fwd<false>(precision, a, block_begin, nblocks, (hipStream_t)stream);
     return (int)hipGetLastError();
@@ -705,9 +712,8 @@ int launch_forward_batch(int precision, const BatchArgs& b, void* stream)
     hipStream_t s = (hipStream_t)stream;
     const int32_t items = b.nreq > 0 ? b.item_begin[b.nreq] : 0;
     if (items <= 0) return 0;
-    if (precision == MSFT_FP32)
-        hipLaunchKernelGGL(fwd_batch_kernel<MSFT_FP32>, dim3(items), dim3(512), 0, s, b);
-    else if (precision == MSFT_BF16X3)
+    if (precision == MSFT_FP32) return (int)hipErrorInvalidValue;   // three-product kernel
+    if (precision == MSFT_BF16X3)
         hipLaunchKernelGGL(fwd_batch_kernel<MSFT_BF16X3>, dim3(items), dim3(512), 0, s, b);
     else
         hipLaunchKernelGGL(fwd_batch_kernel<MSFT_BF16>, dim3(items), dim3(512), 0, s, b);
