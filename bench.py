@@ -333,7 +333,8 @@ def main():
     ap.add_argument("--batch", type=int, default=8, help="patterns per persistent batch launch")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["fp32", "bf16x3", "bf16", "uniform_fp32", "uniform_bf16x3"],
+    ap.add_argument("--only", choices=["fp32", "bf16x3", "bf16", "uniform_fp32", "uniform_bf16x3",
+                                       "backward_fp32"],
                     default=None,
                     help="time one precision only (profiling runs)")
     ap.add_argument("--serving", type=int, default=64,
@@ -385,6 +386,17 @@ def main():
                           "value": u["patterns_per_s"], "unit": "patterns/s", "n_gpus": 1,
                           "steps": args.steps, "warmup": args.warmup, "dtype": "f32",
                           "higher_is_better": True, "uniform_q": {prec: u}}))
+        return
+
+    if args.only == "backward_fp32":
+        with msft.Plan.for_workload(wl, "fp32") as plan:
+            ms = time_backward(msft, torch, plan, d, b, args.steps, args.warmup)
+        print(f"[bench] fp32 backward: {ms:.3f} ms/pattern, {flops / (ms * 1e-3) / 1e12:.1f} TFLOP/s "
+              "algorithmic", file=sys.stderr, flush=True)
+        print(json.dumps({"metric": "MSFT adjoint patterns/s, 128³ grid, 512² detector",
+                          "value": 1000.0 / ms, "unit": "patterns/s", "n_gpus": 1, "steps": args.steps,
+                          "warmup": args.warmup, "dtype": "f32", "higher_is_better": True,
+                          "ms_per_step": ms, "tflops_algorithmic": flops / (ms * 1e-3) / 1e12}))
         return
 
     results = {}
