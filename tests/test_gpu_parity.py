@@ -218,3 +218,16 @@ def test_parity_large_sampled(msft, large_wl, precision):
     err = _rel(I, Io)
     print(f"  large pattern rel L2 {err:.3e}  amplitude {_rel(A, Ao):.3e}")
     assert err <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_parity_2048_detector_sampled(msft, precision):
+    # the paper's largest detector (2048 x 2048, Sec. 6) on the 128^3 star body to
+    # 60 deg: 32768 pixel blocks, seeded pixels against the oracle
+    wl = inputs.star_workload(n=128, det_n=2048, seed=inputs.SEED_BASE + 11, name="star_2048")
+    pix = inputs.random_pixels(wl.det_n, 384, seed=79)
+    I, A = _run(msft, wl, precision, pixels=pix)
+    Io, Ao = _oracle(wl, pixels=pix)
+    err = _rel(I, Io)
+    print(f"  2048^2 detector rel L2 {err:.3e}  amplitude {_rel(A, Ao):.3e}")
+    assert err <= TOL[precision]
