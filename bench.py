@@ -350,7 +350,7 @@ def main():
                          "scaling hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(the forward model shards by pattern, so N GPUs would run N independent copies)",
               file=sys.stderr)
         sys.exit(2)
