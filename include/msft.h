@@ -59,7 +59,8 @@ typedef enum {
 
 /* Arithmetic of the x-sum contraction (the dominant step). */
 typedef enum {
-    MSFT_FP32 = 0,   /* FP32 MFMA, FP32 accumulation */
+    MSFT_FP32 = 0,   /* FP32 MFMA, FP32 accumulation; the complex x-sum as three real
+                        products (Gauss), P1 = Tr Wr, P2 = Ti Wi, P3 = (Tr+Ti)(Wr+Wi) */
     MSFT_BF16X3 = 1, /* BF16 hi+lo split, hi*hi + hi*lo + lo*hi on BF16 MFMA, FP32 accumulation */
     MSFT_BF16 = 2    /* plain BF16 operands (hi*hi only), FP32 accumulation: the unsplit
                         reference point, about 1e-3 relative intensity error */
