@@ -53,8 +53,9 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b)
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// Workgroup (s, xc, zb, yb): R for x chunk xc (64 x), z block zb (32 z), the 8 y
-// values yb*8 .. yb*8+7 (one per wave), summed over pixel group s.  The complex
+// Workgroup (s, xc, zb, yb): R for x chunk xc (64 x), z block zb (32 z), the 16 y
+// values yb*16 .. yb*16+15 (two per wave, sharing the wave's A and G reads), summed
+// over pixel group s.  The complex
 // sum R = sum_p T B (T = exp(-i q_x x), B = Ty G) runs in Gauss's form: three real
 // contractions P1 = sum Tr Br, P2 = sum Ti Bi, P3 = sum (Tr + Ti)(Br + Bi), then
 // Re R = P1 - P2, Im R = P3 - P1 - P2, with x as MFMA rows (two row tiles of 32),
@@ -62,8 +63,8 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b)
 // half).  Per chunk of ADJ_CHUNK pixels the workgroup first writes into LDS
 //   the A values Tr, Ti, Tr + Ti as planes of rows per pixel, x = rt*32 + i at
 //       element 2i + rt of the row (rows padded, see below),
-//   G = h_p exp(-i q_z z) for the 32 z values, and Ty = exp(-i q_y y) for 8 y,
-// then every wave runs 6 MFMAs per pixel pair with B formed on the fly: lane
+//   G = h_p exp(-i q_z z) for the 32 z values, and Ty = exp(-i q_y y) for 16 y,
+// then every wave runs 6 MFMAs per pixel pair and y with B formed on the fly: lane
 // (h, i) reads the (x = i, x = 32 + i) pair of pixel 2m + h from each plane.  Runs
 // of 8 x (4 z) share one FP64-reduced anchor and a step exp(-i q d) applied by
 // complex multiplication.
@@ -77,7 +78,7 @@ __global__ __launch_bounds__(512) void adj_contract(AdjArgs a)
 {
     __shared__ __attribute__((aligned(16))) float afrag[3 * ADJ_CHUNK * ADJ_AROW];
     __shared__ __attribute__((aligned(16))) float2 gz[ADJ_CHUNK * ADJ_GROW];
-    __shared__ __attribute__((aligned(16))) float2 ty[ADJ_CHUNK * 8];
+    __shared__ __attribute__((aligned(16))) float2 ty[ADJ_CHUNK * ADJ_Y];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -89,16 +90,19 @@ __global__ __launch_bounds__(512) void adj_contract(AdjArgs a)
     b /= a.nzb;
     const int xc = (int)(b % a.nxc);
     const int s = (int)(b / a.nxc);
-    const int y = yb * 8 + wave;
+    const int y = yb * ADJ_Y + 2 * wave;   // this wave's two y: y, y + 1
     const bool wave_active = y < a.ny;
 
-    f32x16 P1[2], P2[2], P3[2];
+    f32x16 P1[2][2], P2[2][2], P3[2][2];   // [y][row tile]
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt) P1[rt] = P2[rt] = P3[rt] = f32x16{};
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) P1[v][rt] = P2[v][rt] = P3[v][rt] = f32x16{};
 
     const int64_t p_begin = (int64_t)s * a.group_pix;
     const int64_t p_end = min(p_begin + a.group_pix, a.npix_pad);
     const int gp = tid >> 3, sub = tid & 7;   // generation: pixel, run index
+    static_assert(ADJ_Y == 16, "eight waves of two y each");
 
     for (int64_t p0 = p_begin; p0 < p_end; p0 += ADJ_CHUNK) {
         // ---- twiddles of ADJ_CHUNK pixels into LDS ----
@@ -142,17 +146,16 @@ __global__ __launch_bounds__(512) void adj_contract(AdjArgs a)
                     t = cmul(t, e);
                 }
             }
-            // Ty: y = yb*8 + sub
-            {
-                const int yy = yb * 8 + sub;
-                ty[gp * 8 + sub] = (yy < a.ny) ? cis_reduced(-(qy * (a.ys0 + (double)yy * a.dy)))
-                                               : make_float2(0.0f, 0.0f);
+            // Ty: y = yb*16 + 2 sub + v
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                const int yy = yb * ADJ_Y + 2 * sub + v;
+                ty[gp * ADJ_Y + 2 * sub + v] = (yy < a.ny) ? cis_reduced(-(qy * (a.ys0 + (double)yy * a.dy)))
+                                                           : make_float2(0.0f, 0.0f);
             }
         }
         __syncthreads();
         // ---- contraction over the chunk's pixel pairs ----
-        // The next pair's A values, G and Ty are read from LDS before this pair's
-        // MFMAs are issued, so the reads complete under them.
         if (wave_active) {
             // lane (h, i) reads, per plane, the pair (x = i, x = 32 + i) of pixel 2m + h
             const float* af = afrag + h * ADJ_AROW + 2 * col;
@@ -162,16 +165,20 @@ __global__ __launch_bounds__(512) void adj_contract(AdjArgs a)
                 const float2 a1 = *(const float2*)(af + ADJ_CHUNK * ADJ_AROW + 2 * m * ADJ_AROW);
                 const float2 a2 = *(const float2*)(af + 2 * ADJ_CHUNK * ADJ_AROW + 2 * m * ADJ_AROW);
                 const float2 g = gz[(2 * m + h) * ADJ_GROW + col];
-                const float2 t = ty[(2 * m + h) * 8 + wave];
-                const float br = t.x * g.x - t.y * g.y;
-                const float bi = t.x * g.y + t.y * g.x;
-                const float bs = br + bi;
-                P1[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.x, br, P1[0], 0, 0, 0);
-                P1[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.y, br, P1[1], 0, 0, 0);
-                P2[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.x, bi, P2[0], 0, 0, 0);
-                P2[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.y, bi, P2[1], 0, 0, 0);
-                P3[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a2.x, bs, P3[0], 0, 0, 0);
-                P3[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a2.y, bs, P3[1], 0, 0, 0);
+                const float4 t2 = *(const float4*)(ty + (2 * m + h) * ADJ_Y + 2 * wave);
+#pragma unroll
+                for (int v = 0; v < 2; ++v) {
+                    const float tx = v ? t2.z : t2.x, tyv = v ? t2.w : t2.y;
+                    const float br = tx * g.x - tyv * g.y;
+                    const float bi = tx * g.y + tyv * g.x;
+                    const float bs = br + bi;
+                    P1[v][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.x, br, P1[v][0], 0, 0, 0);
+                    P1[v][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.y, br, P1[v][1], 0, 0, 0);
+                    P2[v][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.x, bi, P2[v][0], 0, 0, 0);
+                    P2[v][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.y, bi, P2[v][1], 0, 0, 0);
+                    P3[v][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a2.x, bs, P3[v][0], 0, 0, 0);
+                    P3[v][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a2.y, bs, P3[v][1], 0, 0, 0);
+                }
             }
         }
         __syncthreads();
@@ -181,14 +188,18 @@ __global__ __launch_bounds__(512) void adj_contract(AdjArgs a)
     // row 8j + 4h + u of row tile rt is x = rt*32 + 8j + 4h + u
     const int64_t X2 = (int64_t)a.nxc * XC, NZ2 = (int64_t)a.nzb * ZB;
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt) {
+    for (int v = 0; v < 2; ++v) {
+        if (y + v >= a.ny) continue;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int xl = rt * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-            const int64_t idx = (((int64_t)s * X2 + xc * XC + xl) * a.ny + y) * NZ2 + zb * ZB + col;
-            const float re = P1[rt][r] - P2[rt][r];
-            const float im = (P3[rt][r] - P1[rt][r]) - P2[rt][r];
-            ((float2*)a.rpart)[idx] = make_float2(re, im);
+        for (int rt = 0; rt < 2; ++rt) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int xl = rt * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+                const int64_t idx = (((int64_t)s * X2 + xc * XC + xl) * a.ny + y + v) * NZ2 + zb * ZB + col;
+                const float re = P1[v][rt][r] - P2[v][rt][r];
+                const float im = (P3[v][rt][r] - P1[v][rt][r]) - P2[v][rt][r];
+                ((float2*)a.rpart)[idx] = make_float2(re, im);
+            }
         }
     }
 }

@@ -155,7 +155,7 @@ Dims make_dims(int64_t npix, int nx, int ny, int nz)
 AdjDims make_adj_dims(const Dims& d)
 {
     AdjDims a;
-    a.nyb = (int32_t)ceil_div(d.ny, 8);
+    a.nyb = (int32_t)ceil_div(d.ny, ADJ_Y);
     const int64_t npix_pad = d.nblocks * BLOCK_PIX;
     const int64_t chunks = ceil_div(npix_pad, ADJ_CHUNK);
     const int64_t base = (int64_t)d.nxc * d.nzb * a.nyb;

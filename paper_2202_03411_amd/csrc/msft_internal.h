@@ -176,8 +176,10 @@ struct BatchArgs {
     int32_t nreq;
 };
 
-// Adjoint: pixels per LDS chunk of the transposed contraction (one per 8 threads).
+// Adjoint: pixels per LDS chunk of the transposed contraction (one per 8 threads),
+// and y values per workgroup (two per wave of 8).
 constexpr int ADJ_CHUNK = 64;
+constexpr int ADJ_Y = 16;
 
 // Split-K layout of the adjoint: pixel group s of group_pix pixels writes its
 // partial R into rpart[s][x (nxc*64)][y][z (nzb*32)] complex.
