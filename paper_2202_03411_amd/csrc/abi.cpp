@@ -304,7 +304,7 @@ FwdArgs forward_args(const msft_plan_s* p, const void* wtiles, float* intensity,
     a.nxc = p->dims.g3 ? p->dims.nxc3 : p->dims.nxc;
     a.nzb = p->dims.nzb;
     a.x_pad = p->dims.x_pad;
-    a.group_blocks = a.group_tiles = a.a_waves = a.out_n = a.out_npad = 0;
+    a.group_blocks = a.group_tiles = a.out_n = a.out_npad = 0;
     return a;
 }
 
@@ -328,7 +328,6 @@ FwdArgs sep_stage2_args(const msft_plan_s* p, const void* workspace, float* inte
     a.x_pad = sd.y_pad;
     a.group_blocks = sd.npad / BLOCK_PIX;
     a.group_tiles = sd.nyc * p->dims.nzb;
-    a.a_waves = sd.npad / WAVE_PIX;
     a.out_n = sd.n;
     a.out_npad = sd.npad;
     return a;
@@ -360,12 +359,10 @@ int launch_contraction(const msft_plan_s* p, const void* workspace, float* inten
                                  stream);
     if (!p->separable)
         return launch_forward(prec, forward_args(p, workspace, intensity, amplitude), 0,
-                              p->dims.nblocks, true, stream);
+                              p->dims.nblocks, stream);
     int e = launch_sep_stage1(prec, sep_stage1_args(p, workspace), p->sep.nblk1, stream);
     if (e) return e;
-    const int64_t nblk2 = (int64_t)p->sep.n * (p->sep.npad / BLOCK_PIX);
-    return launch_forward(prec, sep_stage2_args(p, workspace, intensity, amplitude), 0, nblk2,
-                          false, stream);
+    return launch_sep_stage2(prec, sep_stage2_args(p, workspace, intensity, amplitude), stream);
 }
 
 ScanArgs scan_args(const msft_plan_s* p, const float* delta, const float* beta, void* wtiles)

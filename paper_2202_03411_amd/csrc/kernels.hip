@@ -4,8 +4,11 @@
 //  scan_kernel   column scan of the incident field along z and the effective
 //                strength w = dV (n^2 - 1) T (Eqs. (6)-(9)), written in the
 //                contraction's LDS tile layout.
-//  fwd_block     the x-sum as a real-ified complex MFMA contraction with the
-//                y/z phase-weighted reduction and |A|^2 fused behind it.
+//  fwd_block     the x-sum as a real-ified complex MFMA contraction (BF16
+//                precisions) with the y/z phase-weighted reduction and |A|^2
+//                fused behind it.
+//  sep_*         the two stages of the separable (uniform-q) detector and its
+//                adjoint.
 #include <hip/hip_runtime.h>
 
 #include "msft_internal.h"
@@ -470,19 +473,14 @@ __device__ __forceinline__ void rotate_add(float* G, const f32x16& C, const f32x
 }
 
 // All z blocks of one x chunk; t is the next tile, k the next pipeline stage.
-//
-// ROT (the flat detector): two tiles (y, y + 1) per stage in a double-buffered
-// ring of 2 x 2 tiles, so one barrier serves two tiles, each wave runs two
-// independent MFMA chains, and the first tile's Ty rotation can issue under the
-// second chain.  A lone last tile (odd ny) is paired with whatever tile follows
-// and its partner's rotation is scaled by 0 (a branch there measured slower).
-// !ROT (second stage of the separable detector): the contraction already summed
-// over y, so each z block is one tile, added to G without a Ty factor; Tz is
-// loaded at the start of the z block to complete under the MFMA chain.
-// FULL: the chunk holds XC x values.  The paired loop decides this per chunk,
-// which keeps its tile loop free of branches (measured faster); the single-tile
-// loop decides per tile (measured faster there).
-template <int PREC, bool ROT, bool FULL>
+// Two tiles (y, y + 1) per stage in a double-buffered ring of 2 x 2 tiles, so one
+// barrier serves two tiles, each wave runs two independent MFMA chains, and the
+// first tile's Ty rotation can issue under the second chain.  A lone last tile
+// (odd ny) is paired with whatever tile follows and its partner's rotation is
+// scaled by 0 (a branch there measured slower).
+// FULL: the chunk holds XC x values, decided per chunk, which keeps the tile loop
+// free of branches (measured faster).
+template <int PREC, bool FULL>
 __device__ __forceinline__ void fwd_chunk(const FwdArgs& a, int64_t wt, int64_t ntiles, const uint4* gw,
                                           uint8_t* lds, int xlen, const f32x4* Af, const bf16x8* Ahi,
                                           const bf16x8* Alo, int64_t& t, int& k, float* acc)
@@ -495,74 +493,44 @@ __device__ __forceinline__ void fwd_chunk(const FwdArgs& a, int64_t wt, int64_t 
 #pragma unroll
         for (int q = 0; q < 16; ++q) G[q] = 0.0f;
         const f32x4* tzp = (const f32x4*)(a.tz + 2 * ((((wt * a.nzb + zb) * 2 + h) * ZB + col) * 8));
-        f32x4 tzv[4];
-        if constexpr (!ROT) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) tzv[q] = tzp[q];
-        }
-        if constexpr (ROT) {
-            for (int y = 0; y < a.ny; y += 2) {
-                const int cnt = min(2, a.ny - y);
-                const int64_t tn = t + cnt;
-                const bool has_next = tn < ntiles;
-                uint4 n0, n1, n2, n3;
-                if (has_next) {
-                    const int64_t tn1 = min(tn + 1, ntiles - 1);
-                    n0 = gw[tn * (TILE_BYTES / 16) + tid];
-                    n1 = gw[tn * (TILE_BYTES / 16) + 512 + tid];
-                    n2 = gw[tn1 * (TILE_BYTES / 16) + tid];
-                    n3 = gw[tn1 * (TILE_BYTES / 16) + 512 + tid];
-                }
-                const f32x4* typ0 = (const f32x4*)(a.ty + 2 * ((wt * a.ny + y) * WAVE_PIX + h * 8));
-                const f32x4* typ1 = (const f32x4*)(a.ty + 2 * ((wt * a.ny + y + cnt - 1) * WAVE_PIX + h * 8));
-                const float s1 = cnt == 2 ? 1.0f : 0.0f;
-                const f32x4 ty0[4] = {typ0[0], typ0[1], typ0[2], typ0[3]};
-                const f32x4 ty1[4] = {typ1[0] * s1, typ1[1] * s1, typ1[2] * s1, typ1[3] * s1};
+        for (int y = 0; y < a.ny; y += 2) {
+            const int cnt = min(2, a.ny - y);
+            const int64_t tn = t + cnt;
+            const bool has_next = tn < ntiles;
+            uint4 n0, n1, n2, n3;
+            if (has_next) {
+                const int64_t tn1 = min(tn + 1, ntiles - 1);
+                n0 = gw[tn * (TILE_BYTES / 16) + tid];
+                n1 = gw[tn * (TILE_BYTES / 16) + 512 + tid];
+                n2 = gw[tn1 * (TILE_BYTES / 16) + tid];
+                n3 = gw[tn1 * (TILE_BYTES / 16) + 512 + tid];
+            }
+            const f32x4* typ0 = (const f32x4*)(a.ty + 2 * ((wt * a.ny + y) * WAVE_PIX + h * 8));
+            const f32x4* typ1 = (const f32x4*)(a.ty + 2 * ((wt * a.ny + y + cnt - 1) * WAVE_PIX + h * 8));
+            const float s1 = cnt == 2 ? 1.0f : 0.0f;
+            const f32x4 ty0[4] = {typ0[0], typ0[1], typ0[2], typ0[3]};
+            const f32x4 ty1[4] = {typ1[0] * s1, typ1[1] * s1, typ1[2] * s1, typ1[3] * s1};
 
-                const uint8_t* row = lds + (size_t)(k & 1) * 2 * TILE_BYTES + (h * ZB + col) * ROW_BYTES;
-                const f32x16 C0 = tile_product<PREC, FULL>(row, col, xlen, Af, Ahi, Alo);
-                const f32x16 C1 = tile_product<PREC, FULL>(row + TILE_BYTES, col, xlen, Af, Ahi, Alo);
-                rotate_add(G, C0, ty0);
-                rotate_add(G, C1, ty1);
-                if (has_next) {
-                    uint4* nb = (uint4*)(lds + (size_t)((k + 1) & 1) * 2 * TILE_BYTES);
-                    nb[tid] = n0;
-                    nb[tid + 512] = n1;
-                    nb[1024 + tid] = n2;
-                    nb[1024 + tid + 512] = n3;
-                }
-                __syncthreads();
-                t += cnt;
-                ++k;
+            const uint8_t* row = lds + (size_t)(k & 1) * 2 * TILE_BYTES + (h * ZB + col) * ROW_BYTES;
+            const f32x16 C0 = tile_product<PREC, FULL>(row, col, xlen, Af, Ahi, Alo);
+            const f32x16 C1 = tile_product<PREC, FULL>(row + TILE_BYTES, col, xlen, Af, Ahi, Alo);
+            rotate_add(G, C0, ty0);
+            rotate_add(G, C1, ty1);
+            if (has_next) {
+                uint4* nb = (uint4*)(lds + (size_t)((k + 1) & 1) * 2 * TILE_BYTES);
+                nb[tid] = n0;
+                nb[tid + 512] = n1;
+                nb[1024 + tid] = n2;
+                nb[1024 + tid + 512] = n3;
             }
-        } else {
-            for (int y = 0; y < a.ny; ++y, ++t) {
-                const bool has_next = (t + 1) < ntiles;
-                uint4 n0, n1;
-                if (has_next) {
-                    n0 = gw[(t + 1) * (TILE_BYTES / 16) + tid];
-                    n1 = gw[(t + 1) * (TILE_BYTES / 16) + 512 + tid];
-                }
-                const uint8_t* row = lds + (t & 1) * TILE_BYTES + (h * ZB + col) * ROW_BYTES;
-                const f32x16 C = tile_product<PREC, FULL>(row, col, xlen, Af, Ahi, Alo);
-#pragma unroll
-                for (int m = 0; m < 8; ++m) {
-                    const int r = 4 * (m >> 1) + 2 * (m & 1);
-                    G[2 * m] += C[r];
-                    G[2 * m + 1] += C[r + 1];
-                }
-                if (has_next) {
-                    uint4* nb = (uint4*)(lds + ((t + 1) & 1) * TILE_BYTES);
-                    nb[tid] = n0;
-                    nb[tid + 512] = n1;
-                }
-                __syncthreads();
-            }
+            __syncthreads();
+            t += cnt;
+            ++k;
         }
         // acc[m] += Tz[m] * G[m]
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const f32x4 v = ROT ? tzp[q] : tzv[q];
+            const f32x4 v = tzp[q];
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
                 const int m = 2 * q + u;
@@ -574,31 +542,25 @@ __device__ __forceinline__ void fwd_chunk(const FwdArgs& a, int64_t wt, int64_t 
     }
 }
 
-// One pixel block (BLOCK_PIX pixels) of the contraction.  A tile group (one
-// detector column in the separable detector's second stage) reads its own tiles
-// and shares the A operand of its position within the group.
-template <int PREC, bool ROT>
+// One pixel block (BLOCK_PIX pixels) of the contraction.
+template <int PREC>
 __device__ __forceinline__ void fwd_block(const FwdArgs& a, int64_t block, uint8_t* lds)
 {
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int64_t wt = block * WAVES + wave;
     const int64_t ntiles = (int64_t)a.nxc * a.nzb * a.ny;
-    const int64_t group = a.group_blocks ? block / a.group_blocks : 0;
-    const int64_t wa = a.a_waves ? wt % a.a_waves : wt;
-    const uint4* gw = (const uint4*)(a.wtiles + (size_t)group * a.group_tiles * TILE_BYTES);
+    const uint4* gw = (const uint4*)a.wtiles;
 
-    // first stage: tile 0 (and tile 1 for the paired stages) -> LDS buffer 0
+    // first stage: tiles 0 and 1 -> LDS buffer 0
     {
         const uint4 r0 = gw[tid], r1 = gw[tid + 512];
         ((uint4*)lds)[tid] = r0;
         ((uint4*)lds)[tid + 512] = r1;
-        if (ROT) {
-            const int64_t t1 = ntiles > 1 ? 1 : 0;
-            const uint4 r2 = gw[t1 * (TILE_BYTES / 16) + tid], r3 = gw[t1 * (TILE_BYTES / 16) + 512 + tid];
-            ((uint4*)lds)[1024 + tid] = r2;
-            ((uint4*)lds)[1024 + tid + 512] = r3;
-        }
+        const int64_t t1 = ntiles > 1 ? 1 : 0;
+        const uint4 r2 = gw[t1 * (TILE_BYTES / 16) + tid], r3 = gw[t1 * (TILE_BYTES / 16) + 512 + tid];
+        ((uint4*)lds)[1024 + tid] = r2;
+        ((uint4*)lds)[1024 + tid + 512] = r3;
     }
     __syncthreads();
 
@@ -612,15 +574,15 @@ __device__ __forceinline__ void fwd_block(const FwdArgs& a, int64_t block, uint8
         const int xlen = min(XC, a.x_pad - xc * XC);
         f32x4 Af[16];
         bf16x8 Ahi[8], Alo[8];
-        load_a<PREC>(a.txa + (size_t)(wa * a.nxc + xc) * TILE_BYTES, lane, Af, Ahi, Alo);
+        load_a<PREC>(a.txa + (size_t)(wt * a.nxc + xc) * TILE_BYTES, lane, Af, Ahi, Alo);
         // Wait for the A operand here, once per chunk.  The memory counter is in
         // order, so without this the waits the compiler places for A inside the
         // tile loop would also wait for the next tile's prefetch, mid-chain.
         __builtin_amdgcn_s_waitcnt(0);
-        if (ROT && xlen == XC)
-            fwd_chunk<PREC, ROT, true>(a, wt, ntiles, gw, lds, xlen, Af, Ahi, Alo, t, k, acc);
+        if (xlen == XC)
+            fwd_chunk<PREC, true>(a, wt, ntiles, gw, lds, xlen, Af, Ahi, Alo, t, k, acc);
         else
-            fwd_chunk<PREC, ROT, false>(a, wt, ntiles, gw, lds, xlen, Af, Ahi, Alo, t, k, acc);
+            fwd_chunk<PREC, false>(a, wt, ntiles, gw, lds, xlen, Af, Ahi, Alo, t, k, acc);
     }
     const int h = lane >> 5, col = lane & 31;
 
@@ -639,27 +601,20 @@ __device__ __forceinline__ void fwd_block(const FwdArgs& a, int64_t block, uint8
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
             const int64_t pix = slot_pixel(wt, h, m);
-            int64_t out = pix;
-            bool valid = pix < a.npix;
-            if (a.out_n) {   // kernel pixel (i, j) of the separable detector -> p = j N + i
-                const int64_t i = pix / a.out_npad, j = pix - i * a.out_npad;
-                valid = valid && j < a.out_n;
-                out = j * a.out_n + i;
-            }
-            if (valid) {
+            if (pix < a.npix) {
                 const float re = acc[2 * m], im = acc[2 * m + 1];
-                a.intensity[out] = re * re + im * im;
-                if (a.amplitude) ((float2*)a.amplitude)[out] = make_float2(re, im);
+                a.intensity[pix] = re * re + im * im;
+                if (a.amplitude) ((float2*)a.amplitude)[pix] = make_float2(re, im);
             }
         }
     }
 }
 
-template <int PREC, bool ROT>
+template <int PREC>
 __global__ __launch_bounds__(512) void fwd_kernel(FwdArgs a, int64_t block_begin)
 {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[(ROT ? 4 : 2) * TILE_BYTES];
-    fwd_block<PREC, ROT>(a, block_begin + blockIdx.x, lds);
+    __shared__ __attribute__((aligned(16))) uint8_t lds[4 * TILE_BYTES];
+    fwd_block<PREC>(a, block_begin + blockIdx.x, lds);
 }
 
 // Batched form: one workgroup per (request, pixel block) item, items numbered in
@@ -673,37 +628,19 @@ __global__ __launch_bounds__(512) void fwd_batch_kernel(BatchArgs b)
     const int32_t it = blockIdx.x;
     int r = 0;
     while (r + 1 < b.nreq && b.item_begin[r + 1] <= it) ++r;
-    fwd_block<PREC, true>(b.req[r], (int64_t)b.block_begin[r] + (it - b.item_begin[r]), lds);
+    fwd_block<PREC>(b.req[r], (int64_t)b.block_begin[r] + (it - b.item_begin[r]), lds);
 }
 
-// (FP32 with the Ty rotation, the flat detector, runs the three-product kernel of
-// gauss.hip; here FP32 serves the separable detector's second stage only.)
-template <bool ROT>
-static void launch_fwd(int precision, const FwdArgs& a, int64_t block_begin, int64_t nblocks,
-                       hipStream_t s)
-{
-    if constexpr (!ROT) {
-        if (precision == MSFT_FP32) {
-            hipLaunchKernelGGL((fwd_kernel<MSFT_FP32, ROT>), dim3((unsigned)nblocks), dim3(512), 0, s,
-                               a, block_begin);
-            return;
-        }
-    }
-    if (precision == MSFT_BF16X3)
-        hipLaunchKernelGGL((fwd_kernel<MSFT_BF16X3, ROT>), dim3((unsigned)nblocks), dim3(512), 0, s, a,
-                           block_begin);
-    else
-        hipLaunchKernelGGL((fwd_kernel<MSFT_BF16, ROT>), dim3((unsigned)nblocks), dim3(512), 0, s, a,
-                           block_begin);
-}
-
-int launch_forward(int precision, const FwdArgs& a, int64_t block_begin, int64_t nblocks,
-                   bool rotate, void* stream)
+// Flat detector, BF16 precisions (FP32 runs the three-product kernel of gauss.hip).
+int launch_forward(int precision, const FwdArgs& a, int64_t block_begin, int64_t nblocks, void* stream)
 {
     if (nblocks <= 0) return 0;
-    if (rotate && precision == MSFT_FP32) return (int)hipErrorInvalidValue;
-    if (rotate) launch_fwd<true>(precision, a, block_begin, nblocks, (hipStream_t)stream);
-    else launch_fwd<false>(precision, a, block_begin, nblocks, (hipStream_t)stream);
+    if (precision == MSFT_FP32) return (int)hipErrorInvalidValue;
+    hipStream_t s = (hipStream_t)stream;
+    if (precision == MSFT_BF16X3)
+        hipLaunchKernelGGL(fwd_kernel<MSFT_BF16X3>, dim3((unsigned)nblocks), dim3(512), 0, s, a, block_begin);
+    else
+        hipLaunchKernelGGL(fwd_kernel<MSFT_BF16>, dim3((unsigned)nblocks), dim3(512), 0, s, a, block_begin);
     return (int)hipGetLastError();
 }
 
@@ -763,24 +700,27 @@ __device__ __forceinline__ void store_h4(uint8_t* tile, int h, int zl, int yl, c
     }
 }
 
-template <int PREC, bool PLAIN>
-__global__ __launch_bounds__(512) void sep_stage1_kernel(Stage1Args a)
+// NY y per workgroup: S1_Y for the H tiles (one 16-byte slot per lane); the plain
+// output of the adjoint takes any NY, and with NY = 1 two workgroups share a CU.
+template <int PREC, bool PLAIN, int NY>
+__global__ __launch_bounds__(512, NY == 1 ? 4 : 2) void sep_stage1_kernel(Stage1Args a)
 {
+    static_assert(PLAIN || NY == S1_Y, "H tiles are written S1_Y consecutive y at a time");
     __shared__ __attribute__((aligned(16))) uint8_t lds[2 * TILE_BYTES];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int h = lane >> 5, col = lane & 31;
-    const int y0 = blockIdx.y * S1_Y, zb = blockIdx.z;
+    const int y0 = blockIdx.y * NY, zb = blockIdx.z;
     const int64_t wt = (int64_t)blockIdx.x * WAVES + wave;
-    const int nyh = max(0, min(S1_Y, a.ny - y0));   // y of this workgroup inside the grid
+    const int nyh = max(0, min(NY, a.ny - y0));   // y of this workgroup inside the grid
     const uint4* wbase = (const uint4*)a.wtiles;
     // tile (xc, y0 + u) of this z block, in uint4 units
     auto tile_at = [&](int xc, int u) {
         return wbase + ((size_t)(xc * a.nzb + zb) * a.ny + y0 + u) * (TILE_BYTES / 16);
     };
-    f32x16 C[S1_Y];
+    f32x16 C[NY];
 #pragma unroll
-    for (int u = 0; u < S1_Y; ++u) C[u] = f32x16{};
+    for (int u = 0; u < NY; ++u) C[u] = f32x16{};
     if (nyh > 0) {
         {
             const uint4* g0 = tile_at(0, 0);
@@ -797,7 +737,7 @@ __global__ __launch_bounds__(512) void sep_stage1_kernel(Stage1Args a)
             __builtin_amdgcn_s_waitcnt(0);
             const int xlen = min(XC, a.x_pad - xc * XC);
 #pragma unroll
-            for (int u = 0; u < S1_Y; ++u) {
+            for (int u = 0; u < NY; ++u) {
                 if (u < nyh) {
                     // next tile: (xc, u + 1) or (xc + 1, 0)
                     const int nxc_ = (u + 1 < nyh) ? xc : xc + 1;
@@ -832,20 +772,148 @@ __global__ __launch_bounds__(512) void sep_stage1_kernel(Stage1Args a)
             if (PLAIN) {
                 // rows of the adjoint's R: 32 lanes write 32 consecutive z
 #pragma unroll
-                for (int u = 0; u < S1_Y; ++u)
+                for (int u = 0; u < NY; ++u)
                     if (u < nyh)
                         ((float2*)a.rplain)[((size_t)i * a.ny + y0 + u) * a.nz2 + zb * ZB + col] =
                             make_float2(C[u][r], C[u][r + 1]);
             } else {
-                float re[S1_Y], im[S1_Y];
+                float re[NY], im[NY];
 #pragma unroll
-                for (int u = 0; u < S1_Y; ++u) {
+                for (int u = 0; u < NY; ++u) {
                     re[u] = C[u][r];
                     im[u] = C[u][r + 1];
                 }
                 uint8_t* tile = a.htiles + ((size_t)(i * a.nyc + yc) * a.nzb + zb) * TILE_BYTES;
                 store_h4<PREC>(tile, 0, col, yl, re);
                 store_h4<PREC>(tile, 1, col, yl, im);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Second stage of the separable detector: A(i, j) = sum_z Tz(i, j, z) sum_y
+// exp(-i q_y(j) y) H(i, y, z).  The A operand, exp(-i q_y(j) y) for the 16 rows j
+// of a wave, does not depend on the column i, so a workgroup (one block of 128
+// rows j, CPW consecutive columns i) loads it once per y chunk and multiplies the
+// tiles of all its columns with it: per y chunk, for each column, one tile per z
+// block (double-buffered in LDS), rotated by Tz into the column's own per-lane
+// sums.  The per-workgroup costs (first tile, the wait for the A operand, the
+// z-lane butterfly) are paid once per CPW columns.
+// ---------------------------------------------------------------------------
+template <int PREC, int CPW>
+__global__ __launch_bounds__(512) void sep_stage2_kernel(FwdArgs a)
+{
+    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * TILE_BYTES];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int h = lane >> 5, col = lane & 31;
+    const int64_t cg = blockIdx.x / a.group_blocks, rb = blockIdx.x - cg * a.group_blocks;
+    const int64_t i0 = cg * CPW;
+    const int ncol = (int)min((int64_t)CPW, (int64_t)a.out_n - i0);   // >= 1, uniform
+    const int64_t wa = rb * WAVES + wave;                                // A operand row
+    const int nzb = a.nzb;
+    // tile (xc, zb) of column i0 + c, in uint4 units
+    auto tile_at = [&](int xc, int c, int zb) {
+        return (const uint4*)(a.wtiles + ((size_t)(i0 + c) * a.group_tiles + (size_t)xc * nzb + zb) * TILE_BYTES);
+    };
+    {
+        const uint4* g0 = tile_at(0, 0, 0);
+        const uint4 r0 = g0[tid], r1 = g0[tid + 512];
+        ((uint4*)lds)[tid] = r0;
+        ((uint4*)lds)[tid + 512] = r1;
+    }
+    __syncthreads();
+
+    float acc[CPW][16];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[c][q] = 0.0f;
+
+    int k = 0;   // tiles consumed; tile k sits in LDS buffer k & 1
+    for (int xc = 0; xc < a.nxc; ++xc) {
+        const int xlen = min(XC, a.x_pad - xc * XC);
+        f32x4 Af[16];
+        bf16x8 Ahi[8], Alo[8];
+        load_a<PREC>(a.txa + (size_t)(wa * a.nxc + xc) * TILE_BYTES, lane, Af, Ahi, Alo);
+        __builtin_amdgcn_s_waitcnt(0);
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) {
+            if (c < ncol) {
+                const int64_t wt = ((i0 + c) * a.group_blocks + rb) * WAVES + wave;
+                for (int zb = 0; zb < nzb; ++zb) {
+                    const f32x4* tzp = (const f32x4*)(a.tz + 2 * ((((wt * nzb + zb) * 2 + h) * ZB + col) * 8));
+                    f32x4 tzv[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) tzv[q] = tzp[q];
+                    // next tile: (xc, c, zb + 1), (xc, c + 1, 0) or (xc + 1, 0, 0)
+                    int nx_ = xc, nc = c, nz_ = zb + 1;
+                    if (nz_ == nzb) {
+                        nz_ = 0;
+                        if (++nc == ncol) {
+                            nc = 0;
+                            ++nx_;
+                        }
+                    }
+                    const bool has_next = nx_ < a.nxc;
+                    uint4 n0, n1;
+                    if (has_next) {
+                        const uint4* g = tile_at(nx_, nc, nz_);
+                        n0 = g[tid];
+                        n1 = g[tid + 512];
+                    }
+                    const uint8_t* row = lds + (k & 1) * TILE_BYTES + (h * ZB + col) * ROW_BYTES;
+                    const f32x16 C = tile_product<PREC, false>(row, col, xlen, Af, Ahi, Alo);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+                        for (int u = 0; u < 2; ++u) {
+                            const int m = 2 * q + u;
+                            const int r = 4 * (m >> 1) + 2 * (m & 1);
+                            const float tr = tzv[q][2 * u], ti = tzv[q][2 * u + 1];
+                            acc[c][2 * m] += tr * C[r] - ti * C[r + 1];
+                            acc[c][2 * m + 1] += tr * C[r + 1] + ti * C[r];
+                        }
+                    }
+                    if (has_next) {
+                        uint4* nb = (uint4*)(lds + ((k + 1) & 1) * TILE_BYTES);
+                        nb[tid] = n0;
+                        nb[tid + 512] = n1;
+                    }
+                    __syncthreads();
+                    ++k;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+        if (c < ncol) {
+            // sum over the 32 z lanes of each half (fixed butterfly order)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                float v = acc[c][q];
+                v += __shfl_xor(v, 16, 32);
+                v += __shfl_xor(v, 8, 32);
+                v += __shfl_xor(v, 4, 32);
+                v += __shfl_xor(v, 2, 32);
+                v += __shfl_xor(v, 1, 32);
+                acc[c][q] = v;
+            }
+            if (col == 0) {
+                const int64_t i = i0 + c;
+                const int64_t wt = (i * a.group_blocks + rb) * WAVES + wave;
+#pragma unroll
+                for (int m = 0; m < 8; ++m) {
+                    const int64_t j = slot_pixel(wt, h, m) - i * a.out_npad;
+                    if (j < a.out_n) {
+                        const int64_t out = j * a.out_n + i;
+                        const float re = acc[c][2 * m], im = acc[c][2 * m + 1];
+                        a.intensity[out] = re * re + im * im;
+                        if (a.amplitude) ((float2*)a.amplitude)[out] = make_float2(re, im);
+                    }
+                }
             }
         }
     }
@@ -941,8 +1009,17 @@ int launch_sep_adjoint(const SepAdjArgs& ka, const Stage1Args& ra, int64_t nblk_
     const int nic = (int)ceil_div(ka.n, XC);
     const dim3 g1((unsigned)ceil_div(ka.ny, BLOCK_PIX), (unsigned)(nic * XC / S1_Y), (unsigned)ka.nzb);
     hipLaunchKernelGGL(sepadj_rows_kernel, g1, dim3(512), 0, s, ka);
-    const dim3 g2((unsigned)nblk_rows, (unsigned)ceil_div(ra.ny, S1_Y), (unsigned)ra.nzb);
-    hipLaunchKernelGGL((sep_stage1_kernel<MSFT_FP32, true>), g2, dim3(512), 0, s, ra);
+    // as many y per workgroup as keep two workgroups per CU in the grid
+    const int ny_wg = nblk_rows * ceil_div(ra.ny, 4) * ra.nzb >= 2 * CHIP_CUS   ? 4
+                      : nblk_rows * ceil_div(ra.ny, 2) * ra.nzb >= 2 * CHIP_CUS ? 2
+                                                                                  : 1;
+    const dim3 g2((unsigned)nblk_rows, (unsigned)ceil_div(ra.ny, ny_wg), (unsigned)ra.nzb);
+    if (ny_wg == 4)
+        hipLaunchKernelGGL((sep_stage1_kernel<MSFT_FP32, true, 4>), g2, dim3(512), 0, s, ra);
+    else if (ny_wg == 2)
+        hipLaunchKernelGGL((sep_stage1_kernel<MSFT_FP32, true, 2>), g2, dim3(512), 0, s, ra);
+    else
+        hipLaunchKernelGGL((sep_stage1_kernel<MSFT_FP32, true, 1>), g2, dim3(512), 0, s, ra);
     return (int)hipGetLastError();
 }
 
@@ -958,16 +1035,41 @@ int launch_sep_adj_tables(const SepDims& sd, int nx, int ny, const double* xq3, 
     return (int)hipGetLastError();
 }
 
+template <int CPW>
+static void launch_stage2_cpw(int precision, const FwdArgs& a, hipStream_t s)
+{
+    const dim3 grid((unsigned)(ceil_div(a.out_n, CPW) * a.group_blocks));
+    if (precision == MSFT_FP32)
+        hipLaunchKernelGGL((sep_stage2_kernel<MSFT_FP32, CPW>), grid, dim3(512), 0, s, a);
+    else if (precision == MSFT_BF16X3)
+        hipLaunchKernelGGL((sep_stage2_kernel<MSFT_BF16X3, CPW>), grid, dim3(512), 0, s, a);
+    else
+        hipLaunchKernelGGL((sep_stage2_kernel<MSFT_BF16, CPW>), grid, dim3(512), 0, s, a);
+}
+
+// Second stage: as many columns per workgroup as keep STAGE2_MIN_WG workgroups.
+constexpr int64_t STAGE2_MIN_WG = 2 * CHIP_CUS;
+
+int launch_sep_stage2(int precision, const FwdArgs& a, void* stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    if (a.out_n <= 0 || a.group_blocks <= 0) return (int)hipErrorInvalidValue;
+    const int64_t gb = a.group_blocks;
+    if (ceil_div(a.out_n, 2) * gb >= STAGE2_MIN_WG) launch_stage2_cpw<2>(precision, a, s);
+    else launch_stage2_cpw<1>(precision, a, s);
+    return (int)hipGetLastError();
+}
+
 int launch_sep_stage1(int precision, const Stage1Args& a, int64_t nblk, void* stream)
 {
     hipStream_t s = (hipStream_t)stream;
     const dim3 grid((unsigned)nblk, (unsigned)(a.nyc * XC / S1_Y), (unsigned)a.nzb);
     if (precision == MSFT_FP32)
-        hipLaunchKernelGGL((sep_stage1_kernel<MSFT_FP32, false>), grid, dim3(512), 0, s, a);
+        hipLaunchKernelGGL((sep_stage1_kernel<MSFT_FP32, false, S1_Y>), grid, dim3(512), 0, s, a);
     else if (precision == MSFT_BF16X3)
-        hipLaunchKernelGGL((sep_stage1_kernel<MSFT_BF16X3, false>), grid, dim3(512), 0, s, a);
+        hipLaunchKernelGGL((sep_stage1_kernel<MSFT_BF16X3, false, S1_Y>), grid, dim3(512), 0, s, a);
     else
-        hipLaunchKernelGGL((sep_stage1_kernel<MSFT_BF16, false>), grid, dim3(512), 0, s, a);
+        hipLaunchKernelGGL((sep_stage1_kernel<MSFT_BF16, false, S1_Y>), grid, dim3(512), 0, s, a);
     return (int)hipGetLastError();
 }
 

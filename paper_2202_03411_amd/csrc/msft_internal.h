@@ -30,6 +30,7 @@ constexpr int WAVES = 8;                    // waves per workgroup
 constexpr int BLOCK_PIX = WAVE_PIX * WAVES; // pixels per workgroup = one work item
 constexpr int TILE_BYTES = 16384;           // one W tile, one A-operand tile
 constexpr int ROW_BYTES = 256;              // one (h, z) row of a W tile
+constexpr int64_t CHIP_CUS = 256;           // compute units of one MI355X (8 XCDs x 32)
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -103,11 +104,11 @@ struct FwdArgs {
     float* amplitude;       // [npix] complex or null
     int64_t npix;
     int32_t ny, nxc, nzb, x_pad;
-    // Second stage of the separable detector (all zero otherwise): blocks
-    // [g * group_blocks, (g + 1) * group_blocks) read tile group g at
-    // wtiles + g * group_tiles tiles; wave wt uses A tile row wt % a_waves;
-    // kernel pixel i * out_npad + j is written to j * out_n + i when j < out_n.
-    int32_t group_blocks, group_tiles, a_waves, out_n, out_npad;
+    // Second stage of the separable detector (all zero otherwise): column i
+    // reads its tile group at wtiles + i * group_tiles tiles; its rows j form
+    // group_blocks pixel blocks; kernel pixel i * out_npad + j is written to
+    // j * out_n + i when j < out_n.
+    int32_t group_blocks, group_tiles, out_n, out_npad;
 };
 
 // Separable (uniform transverse q) detector: q_x depends on the column i only,
@@ -261,8 +262,7 @@ int launch_twiddles(int precision, const Dims& d, const double* q_dev, const dou
                     const double* ys_dev, const double* zs_dev, uint8_t* txa, float* ty,
                     float* tz, void* stream);
 int launch_scan(int precision, const ScanArgs& a, void* stream);
-int launch_forward(int precision, const FwdArgs& a, int64_t block_begin, int64_t nblocks,
-                   bool rotate, void* stream);
+int launch_forward(int precision, const FwdArgs& a, int64_t block_begin, int64_t nblocks, void* stream);
 // Gauss form (tables from launch_twiddles_g3, tiles from a g3 scan).
 int launch_twiddles_g3(const Dims& d, const double* q_dev, const double* xs_dev, const double* ys_dev,
                        const double* zs_dev, uint8_t* txa, float* ty, float* tz, void* stream);
@@ -272,6 +272,8 @@ int launch_sep_twiddles(int precision, const Dims& d, const SepDims& sd, const d
                         const double* qrow, const double* qk, const double* xs, const double* ys,
                         const double* zs, uint8_t* txa1, uint8_t* txa2, float* tz, void* stream);
 int launch_sep_stage1(int precision, const Stage1Args& a, int64_t nblk, void* stream);
+// a: second-stage arguments (group_blocks, group_tiles, out_n, out_npad set)
+int launch_sep_stage2(int precision, const FwdArgs& a, void* stream);
 int launch_sep_adjoint(const SepAdjArgs& ka, const Stage1Args& ra, int64_t nblk_rows, void* stream);
 int launch_sep_adj_tables(const SepDims& sd, int nx, int ny, const double* xq3, const double* qx,
                           const double* yq3, const double* qy, uint8_t* txT, uint8_t* tyT,

@@ -146,12 +146,14 @@ def test_qlist_small_angle_is_fft(msft):
     assert _rel(I, F.ravel()) <= 1e-5
 
 
-def test_batch_bitwise_equals_single(msft):
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_batch_bitwise_equals_single(msft, precision):
     import torch
+    print(f"[gpu] batch of 3 plans, {precision}", flush=True)
     wls = [_workload("b0", (37, 29, 45), 23, (9.0, 8.0, 7.0), inputs.MODE_MSFT, 21),
            _workload("b1", (64, 16, 40), 48, (5.0, 5.0, 5.0), inputs.MODE_MSFT, 22),
            _workload("b2", (20, 20, 20), 33, (8.0, 8.0, 8.0), inputs.MODE_BORN, 23)]
-    plans = [msft.Plan.for_workload(w, "fp32") for w in wls]
+    plans = [msft.Plan.for_workload(w, precision) for w in wls]
     try:
         singles, reqs, outs = [], [], []
         for p, w in zip(plans, wls):
@@ -189,6 +191,35 @@ def test_batch_tile_ranges(msft):
         msft.msft_simulate_batch(reqs, ws)
         torch.cuda.synchronize()
         assert torch.equal(I, Ib)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_empty_volume_and_empty_requests(msft, precision):
+    # A volume with no material scatters nothing: every strength is exactly zero, so
+    # every sum is.  An empty batch and an empty tile range launch nothing and leave
+    # their outputs as they were.
+    import torch
+    print(f"[gpu] empty inputs, {precision}", flush=True)
+    w = _workload("zero", (33, 20, 40), 40, (6.0, 6.0, 6.0), inputs.MODE_MSFT, 51)
+    with msft.Plan.for_workload(w, precision) as p:
+        d = torch.zeros(w.grid, device="cuda")
+        b = torch.zeros(w.grid, device="cuda")
+        I, A = p.simulate(d, b, amplitude=True)
+        torch.cuda.synchronize()
+        assert torch.count_nonzero(I).item() == 0 and torch.count_nonzero(A).item() == 0
+        ws = msft.workspace_tensor(msft.msft_batch_query([]), "cuda")
+        msft.msft_simulate_batch([], ws)
+        nb = -(-p.npix // msft.msft_pixel_block())
+        Ib = torch.full_like(I, -1.0)
+        reqs = [(p.handle, d, b, Ib, None, (nb, nb)), (p.handle, d, b, Ib, None, (0, 0))]
+        ws = msft.workspace_tensor(msft.msft_batch_query(reqs), "cuda")
+        msft.msft_simulate_batch(reqs, ws)
+        torch.cuda.synchronize()
+        assert torch.all(Ib == -1.0).item()
+        with pytest.raises(msft.MSFTError):
+            msft.msft_simulate_batch([(p.handle, d, b, Ib, None, (1, 0))], ws)
+        with pytest.raises(msft.MSFTError):
+            msft.msft_simulate_batch([(p.handle, d, b, Ib, None, (0, nb + 1))], ws)
 
 
 def test_repeatable(msft):

@@ -120,6 +120,25 @@ def test_uniform_pattern_sampled(env, precision):
     assert np.all(I[pix][~ok] == 0.0)
 
 
+@pytest.mark.parametrize("n", [510, 383, 255])
+def test_uniform_column_groups(env, n):
+    # Detector sides whose second stage runs 4, 2 and 1 columns per workgroup, each
+    # with a ragged last group; ny = 70 gives a full and a partial y chunk.  Seeded
+    # pixels plus every row of the last three columns and of column 0.
+    d, b = _field((20, 70, 33), 60 + n)
+    wl = inputs.Workload(f"cols{n}", 45.0, 60.0, n, (9.0, 7.0, 8.0), inputs.MODE_MSFT, d, b)
+    rows = np.arange(n)
+    pix = np.concatenate([inputs.random_pixels(n, 400, seed=n)] +
+                         [rows * n + i for i in (0, n - 3, n - 2, n - 1)])
+    Io, _, ok = _oracle(wl, pixels=pix)
+    for precision in ("fp32", "bf16x3"):
+        I, _ = _gpu(env, wl, precision)
+        err = _rel(I[pix][ok], Io[ok])
+        print(f"  N={n} {precision}: rel L2 {err:.3e} on {int(ok.sum())} pixels")
+        assert err <= TOL[precision]
+        assert np.all(I[pix][~ok] == 0.0)
+
+
 def test_uniform_repeatable(env):
     d, b = _field((40, 30, 50), 57)
     wl = inputs.Workload("rep", 45.0, 60.0, 37, (7.0, 7.0, 7.0), inputs.MODE_MSFT, d, b)
