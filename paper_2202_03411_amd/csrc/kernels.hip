@@ -926,15 +926,16 @@ __global__ __launch_bounds__(512) void sep_stage2_kernel(FwdArgs a)
 //   K(i, y, z) = sum_j exp(-i q_y(j) y) [h(i, j) exp(-i q_z(i, j) z)]   (this kernel)
 //   R(x, y, z) = sum_i exp(-i q_x(i) x) K(i, y, z)          (sep_stage1_kernel, PLAIN)
 // Workgroup (128 rows y, S1_Y consecutive columns i, z block).  Per chunk of 64
-// detector rows j the wave loads its A operand (one table shared by every column),
-// the workgroup forms the S1_Y B tiles h Tz in LDS in the W tile layout (j in
-// place of x) from the plan's Tz table, and the wave multiplies them into S1_Y
-// accumulators.  K is stored in tiles (i chunk, z block, y) with i in place of x
+// detector rows j the wave loads its A operand (one table shared by every column)
+// and multiplies the chunk's S1_Y B tiles h Tz into S1_Y accumulators; the B
+// tiles (W tile layout, j in place of x) sit in a double-buffered LDS ring, and
+// the workgroup forms the next chunk's tiles right behind the MFMA chain, from
+// Tz values loaded one chunk ahead, so one barrier per chunk remains.  K is stored in tiles (i chunk, z block, y) with i in place of x
 // (columns beyond N store zeros), ready to be the B operand of the second sum.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(512) void sepadj_rows_kernel(SepAdjArgs a)
 {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[S1_Y * TILE_BYTES];
+    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * S1_Y * TILE_BYTES];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int h = lane >> 5, col = lane & 31;
@@ -944,43 +945,67 @@ __global__ __launch_bounds__(512) void sepadj_rows_kernel(SepAdjArgs a)
     // this thread's 4 consecutive entries of one Tz block (16 pixels x 32 z of a z block)
     const int w4 = tid >> 7, e0 = (tid & 127) * 4;
     const int hh = e0 >> 8, z = (e0 >> 3) & 31, m0 = e0 & 7;
+    // the thread's Tz entries of chunk jc, column i0 + u
+    auto load_tz = [&](int jc, f32x4 (&t)[S1_Y][2]) {
+#pragma unroll
+        for (int u = 0; u < S1_Y; ++u) {
+            if (u < nih) {
+                const int64_t wt2 = (int64_t)(i0 + u) * (a.npad / WAVE_PIX) + jc * (XC / WAVE_PIX) + w4;
+                const f32x4* tzp = (const f32x4*)(a.tz + 2 * ((wt2 * a.nzb + zb) * (2 * ZB * 8) + e0));
+                t[u][0] = tzp[0];
+                t[u][1] = tzp[1];
+            }
+        }
+    };
+    // B tiles h Tz of chunk jc (rows j in place of x) into the S1_Y tiles at buf
+    auto form_tiles = [&](int jc, uint8_t* buf, const f32x4 (&t)[S1_Y][2]) {
+#pragma unroll
+        for (int u = 0; u < S1_Y; ++u) {
+            if (u < nih) {
+                const int64_t i = i0 + u;
+                const float tz[8] = {t[u][0][0], t[u][0][1], t[u][0][2], t[u][0][3],
+                                     t[u][1][0], t[u][1][1], t[u][1][2], t[u][1][3]};
+                uint8_t* tile = buf + u * TILE_BYTES;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int m = m0 + v;
+                    const int jl = w4 * WAVE_PIX + 4 * (m >> 1) + 2 * hh + (m & 1);
+                    const int64_t j = (int64_t)jc * XC + jl;
+                    float2 hv = make_float2(0.0f, 0.0f);
+                    if (j < a.n) hv = ((const float2*)a.h)[j * a.n + i];
+                    const float tr = tz[2 * v], ti = tz[2 * v + 1];
+                    *(float*)(tile + tile_slot_offset(0, z, jl >> 2) + (jl & 3) * 4) = hv.x * tr - hv.y * ti;
+                    *(float*)(tile + tile_slot_offset(1, z, jl >> 2) + (jl & 3) * 4) = hv.x * ti + hv.y * tr;
+                }
+            }
+        }
+    };
     f32x16 C[S1_Y];
 #pragma unroll
     for (int u = 0; u < S1_Y; ++u) C[u] = f32x16{};
     if (nih > 0) {
+        f32x4 tzn[S1_Y][2];
+        load_tz(0, tzn);
+        form_tiles(0, lds, tzn);
+        if (a.njc > 1) load_tz(1, tzn);
+        __syncthreads();
         for (int jc = 0; jc < a.njc; ++jc) {
             f32x4 Af[16];
             bf16x8 Ahi[8], Alo[8];
             load_a<MSFT_FP32>(a.tyT + (size_t)(wt * a.njc + jc) * TILE_BYTES, lane, Af, Ahi, Alo);
-            __syncthreads();   // every wave is done with the previous chunk's tiles
-#pragma unroll
-            for (int u = 0; u < S1_Y; ++u) {
-                if (u < nih) {
-                    const int64_t i = i0 + u;
-                    const int64_t wt2 = i * (a.npad / WAVE_PIX) + jc * (XC / WAVE_PIX) + w4;
-                    const f32x4* tzp = (const f32x4*)(a.tz + 2 * ((wt2 * a.nzb + zb) * (2 * ZB * 8) + e0));
-                    const f32x4 t01 = tzp[0], t23 = tzp[1];
-                    const float tz[8] = {t01[0], t01[1], t01[2], t01[3], t23[0], t23[1], t23[2], t23[3]};
-                    uint8_t* tile = lds + u * TILE_BYTES;
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int m = m0 + v;
-                        const int jl = w4 * WAVE_PIX + 4 * (m >> 1) + 2 * hh + (m & 1);
-                        const int64_t j = (int64_t)jc * XC + jl;
-                        float2 hv = make_float2(0.0f, 0.0f);
-                        if (j < a.n) hv = ((const float2*)a.h)[j * a.n + i];
-                        const float tr = tz[2 * v], ti = tz[2 * v + 1];
-                        *(float*)(tile + tile_slot_offset(0, z, jl >> 2) + (jl & 3) * 4) = hv.x * tr - hv.y * ti;
-                        *(float*)(tile + tile_slot_offset(1, z, jl >> 2) + (jl & 3) * 4) = hv.x * ti + hv.y * tr;
-                    }
-                }
-            }
-            __syncthreads();
+            const uint8_t* cur = lds + (jc & 1) * S1_Y * TILE_BYTES;
 #pragma unroll
             for (int u = 0; u < S1_Y; ++u)
                 if (u < nih)
-                    C[u] = tile_mfma<MSFT_FP32, XC>(C[u], lds + u * TILE_BYTES + (h * ZB + col) * ROW_BYTES,
+                    C[u] = tile_mfma<MSFT_FP32, XC>(C[u], cur + u * TILE_BYTES + (h * ZB + col) * ROW_BYTES,
                                                     col, Af, Ahi, Alo);
+            // the next chunk's tiles go to the other buffer, which every wave finished
+            // reading before the last barrier; its Tz values arrived during this chunk
+            if (jc + 1 < a.njc) {
+                form_tiles(jc + 1, lds + ((jc + 1) & 1) * S1_Y * TILE_BYTES, tzn);
+                if (jc + 2 < a.njc) load_tz(jc + 2, tzn);
+            }
+            __syncthreads();
         }
     }
     const int ic = i0 / XC, il = i0 - ic * XC;
