@@ -154,7 +154,13 @@ __global__ __launch_bounds__(256) void render_sh_grad_kernel(ShArgs s, const flo
         const double o = occupancy(s.r0 * (1.0 + rs), d.r, s.g.edge);
         const double w = ((double)gd[v] * s.g.delta0 + (double)gb[v] * s.g.beta0) * o * (1.0 - o) /
                          s.g.edge * s.r0;
-        for_each_ylm<L>(s, d, [&](int idx, double y) { acc[idx] += (float)(w * y); });
+        // Recompute the harmonics from a voxel index the compiler cannot prove equal
+        // to v: reusing the first pass's values keeps all (L+1)^2 of them live in FP64
+        // across the radius and the weight, which spills at L = 12 (4x slower there).
+        int64_t v2 = v;
+        asm volatile("" : "+v"(v2));
+        const VoxelDir d2 = voxel_dir(s.g, v2);
+        for_each_ylm<L>(s, d2, [&](int idx, double y) { acc[idx] += (float)(w * y); });
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
