@@ -175,13 +175,23 @@ __global__ __launch_bounds__(256) void render_sh_grad_kernel(ShArgs s, const flo
             (((double)wsum[0][k] + (double)wsum[1][k]) + (double)wsum[2][k]) + (double)wsum[3][k];
 }
 
-__global__ void render_sh_grad_reduce(const double* partial, int nblocks, int nc, float* grad)
+// One workgroup per coefficient: thread t adds the partials b = t, t + 256, ... in
+// FP64, then a fixed pairwise tree over the 256 threads.  The order is fixed, so
+// repeated calls give the same bits.  (One thread per coefficient walking all the
+// partials waited on one load at a time: most of the gradient's time.)
+__global__ __launch_bounds__(256) void render_sh_grad_reduce(const double* partial, int nblocks, float* grad)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nc) return;
+    __shared__ double red[256];
+    const int k = blockIdx.x, t = threadIdx.x;
     double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += partial[(int64_t)b * MAX_SH_COEFFS + k];
-    grad[k] = (float)s;
+    for (int b = t; b < nblocks; b += 256) s += partial[(int64_t)b * MAX_SH_COEFFS + k];
+    red[t] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) red[t] += red[t + h];
+        __syncthreads();
+    }
+    if (t == 0) grad[k] = (float)red[0];
 }
 
 __global__ __launch_bounds__(256) void render_ellipsoid_kernel(EllArgs e, float* delta, float* beta)
@@ -271,8 +281,8 @@ int launch_render_sh_grad(const ShArgs& s, const float* coeffs, const float* gd,
         hipLaunchKernelGGL(render_sh_grad_kernel<MAX_SH_L>, dim3((unsigned)nblocks), dim3(256), 0, st,
                            s, coeffs, gd, gb, partial);
     const int nc = (s.lmax + 1) * (s.lmax + 1);
-    hipLaunchKernelGGL(render_sh_grad_reduce, dim3((unsigned)ceil_div(nc, 64)), dim3(64), 0, st,
-                       (const double*)partial, nblocks, nc, grad);
+    hipLaunchKernelGGL(render_sh_grad_reduce, dim3((unsigned)nc), dim3(256), 0, st, (const double*)partial,
+                       nblocks, grad);
     return (int)hipGetLastError();
 }
 
