@@ -120,10 +120,11 @@ def test_uniform_pattern_sampled(env, precision):
     assert np.all(I[pix][~ok] == 0.0)
 
 
-@pytest.mark.parametrize("n", [510, 383, 255])
+@pytest.mark.parametrize("n", [511, 383, 255])
 def test_uniform_column_groups(env, n):
-    # Detector sides whose second stage runs 4, 2 and 1 columns per workgroup, each
-    # with a ragged last group; ny = 70 gives a full and a partial y chunk.  Seeded
+    # Detector sides whose second stage runs 2, 2 and 1 columns per workgroup (the
+    # odd sides leave a last group of one column); 511 and 383 also differ in their
+    # row blocks (4 and 3).  ny = 70 gives a full and a partial y chunk.  Seeded
     # pixels plus every row of the last three columns and of column 0.
     d, b = _field((20, 70, 33), 60 + n)
     wl = inputs.Workload(f"cols{n}", 45.0, 60.0, n, (9.0, 7.0, 8.0), inputs.MODE_MSFT, d, b)
