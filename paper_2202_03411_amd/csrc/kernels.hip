@@ -1072,7 +1072,9 @@ static void launch_stage2_cpw(int precision, const FwdArgs& a, hipStream_t s)
         hipLaunchKernelGGL((sep_stage2_kernel<MSFT_BF16, CPW>), grid, dim3(512), 0, s, a);
 }
 
-// Second stage: as many columns per workgroup as keep STAGE2_MIN_WG workgroups.
+// Second stage: two columns per workgroup when that still leaves STAGE2_MIN_WG
+// workgroups (two per CU), else one.  Four measured no faster in FP32 and slower
+// in BF16.
 constexpr int64_t STAGE2_MIN_WG = 2 * CHIP_CUS;
 
 int launch_sep_stage2(int precision, const FwdArgs& a, void* stream)
