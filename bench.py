@@ -7,12 +7,16 @@ beta = 0.02) on a 128^3 voxel grid, lambda = 45 nm, flat 512 x 512 detector to
 MFMA contraction with the fused y/z reduction, |A|^2.  Inputs are resident in
 HBM before timing starts.  Prints ONE JSON line.
 
-Reported beside the headline (FP32, one pattern per launch):
-  - the BF16 hi+lo split contraction,
-  - a batch of patterns in one persistent launch against the same patterns
-    launched one by one,
+Reported beside the headline (FP32, one pattern per launch; 100 timed patterns
+after 10 warm-ups by default):
+  - the BF16 hi+lo split contraction and plain BF16,
+  - a batch of patterns in one batched launch against the same patterns
+    launched one by one, and the FP32 adjoint,
   - the dominant kernel against the FP32 matrix-core roofline (HIP events on
-    the stream the kernel runs on),
+    the stream the kernel runs on), with its HBM traffic from the committed
+    counter summary,
+  - the served stream (batched against plain), the uniform-q detector, the shape
+    renderers and the Ideal detector,
   - the FP64 CPU oracle timed on a bounded pixel sample (cpu_baseline).
 """
 from __future__ import annotations
