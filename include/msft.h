@@ -53,7 +53,7 @@ typedef enum {
     MSFT_ERR_UNDERSAMPLED = 2,  /* pitch * max|q| > pi on some axis (see MSFT_ALLOW_ALIAS) */
     MSFT_ERR_NOMEM = 3,         /* device or host allocation failed */
     MSFT_ERR_DEVICE = 4,        /* a HIP runtime call failed */
-    MSFT_ERR_BUSY = 5,          /* workspace too small for the batch */
+    MSFT_ERR_BUSY = 5,          /* workspace too small for the call */
     MSFT_ERR_UNSUPPORTED = 6    /* the plan cannot run this call (host-only plan, ...) */
 } msft_status;
 
@@ -142,13 +142,22 @@ msft_status msft_plan_qlist(const msft_geometry* g, const double* q_host, int64_
 msft_status msft_plan_destroy(msft_plan_t plan);
 
 /*
- * Sizes of a plan: npix = P; workspace_bytes = device scratch one msft_simulate
- * or msft_backward call needs (the effective strength w in the contraction's
- * tile layout, plus the backward's partial sums); resident_bytes = device
- * memory the plan itself holds.  Any pointer may be NULL.
+ * Sizes of a plan (the HBM footprint a scheduler admits requests by):
+ *   npix              P, the number of pixels (or q values);
+ *   workspace_bytes   device scratch that one msft_simulate or msft_backward call
+ *                     of this plan needs (the larger of the two: the effective
+ *                     strength w in the contraction's tile layout, plus the
+ *                     backward's partial sums);
+ *   resident_bytes    device memory the plan itself holds (q map, twiddles);
+ *   per_request_bytes device memory one request of this plan holds while it is
+ *                     in flight: its delta and beta (8 bytes per voxel), its
+ *                     intensity and amplitude (12 bytes per pixel) and its share
+ *                     of a msft_simulate_batch workspace (the forward's scratch),
+ *                     each rounded up to 256 bytes.
+ * Any output pointer may be NULL.
  */
 msft_status msft_plan_query(msft_plan_t plan, int64_t* npix, size_t* workspace_bytes,
-                            size_t* resident_bytes);
+                            size_t* resident_bytes, size_t* per_request_bytes);
 
 /* Copy the plan's FP64 transfer momenta, q_host[P][3] as (qx, qy, qz). */
 msft_status msft_plan_qmap(msft_plan_t plan, double* q_host);
@@ -163,12 +172,15 @@ msft_status msft_plan_grid(msft_plan_t plan, double* x, double* y, double* z);
  *   delta, beta : device float32 [nx][ny][nz]
  *   intensity   : device float32 [P] (written)
  *   amplitude   : device complex64 [P] or NULL (written if given)
- *   workspace   : device buffer of at least workspace_bytes, 256-byte aligned
+ *   workspace   : device buffer of ws_bytes bytes, 256-byte aligned; ws_bytes
+ *                 must be at least msft_plan_query's workspace_bytes
+ *                 (MSFT_ERR_BUSY otherwise, nothing launched)
  * Results do not depend on the stream, the batch a call is part of, or on
  * earlier calls: the order of every floating-point sum is fixed by the plan.
  */
 msft_status msft_simulate(msft_plan_t plan, const float* delta, const float* beta,
-                          float* intensity, float* amplitude, void* workspace, void* stream);
+                          float* intensity, float* amplitude, void* workspace, size_t ws_bytes,
+                          void* stream);
 
 /*
  * The two stages of msft_simulate, for callers that time or reuse them:
@@ -179,9 +191,9 @@ msft_status msft_simulate(msft_plan_t plan, const float* delta, const float* bet
  * msft_simulate_contract on one stream and one workspace equals msft_simulate bit for bit.
  */
 msft_status msft_simulate_scan(msft_plan_t plan, const float* delta, const float* beta,
-                          void* workspace, void* stream);
-msft_status msft_simulate_contract(msft_plan_t plan, const void* workspace, float* intensity,
-                          float* amplitude, void* stream);
+                               void* workspace, size_t ws_bytes, void* stream);
+msft_status msft_simulate_contract(msft_plan_t plan, const void* workspace, size_t ws_bytes,
+                                   float* intensity, float* amplitude, void* stream);
 
 /* One request of a batch; tile_begin/tile_end select pixel blocks (-1 = all). */
 typedef struct {
@@ -220,11 +232,13 @@ msft_status msft_simulate_batch(const msft_request* reqs, int32_t n, void* works
  *   dL/d delta_s = 2 Re(R_s dw_s/d delta_s) + 2 k0 dz Im(sum_{s'>s} R_s' w_s')
  *   dL/d beta_s  = 2 Re(R_s dw_s/d beta_s)  - 2 k0 dz Re(sum_{s'>s} R_s' w_s')
  * (second terms only for MSFT_STRENGTH_MSFT).  The twiddles are recomputed
- * on the fly, not read from the plan.
+ * on the fly, not read from the plan.  workspace: as for msft_simulate
+ * (ws_bytes at least msft_plan_query's workspace_bytes).
  */
 msft_status msft_backward(msft_plan_t plan, const float* delta, const float* beta,
                           const float* amplitude, const float* grad_intensity,
-                          float* grad_delta, float* grad_beta, void* workspace, void* stream);
+                          float* grad_delta, float* grad_beta, void* workspace, size_t ws_bytes,
+                          void* stream);
 
 /*
  * Shape rendering (Sec. 5.2): delta and beta of a sample on a voxel grid centred

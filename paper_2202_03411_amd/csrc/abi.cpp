@@ -267,7 +267,13 @@ msft_status make_plan(const msft_geometry* g, const double* q_host, int64_t npix
         fwd_ws += align256(p->sep.h_bytes(p->dims.nzb));
         adj_ws = sep_adj_layout(p, nullptr, nullptr);
     }
+    p->fwd_workspace = fwd_ws;
+    p->adj_workspace = adj_ws;
     p->workspace_bytes = std::max(fwd_ws, adj_ws);
+    // delta, beta in; intensity and amplitude out; the request's W tiles in a batch
+    p->per_request = align256(sizeof(float) * (size_t)g->nx * g->ny * g->nz) * 2 +
+                     align256(sizeof(float) * (size_t)p->geo.npix) +
+                     align256(2 * sizeof(float) * (size_t)p->geo.npix) + fwd_ws;
     p->device = device;
     if (device >= 0) {
         int count = 0;
@@ -289,6 +295,18 @@ msft_status make_plan(const msft_geometry* g, const double* q_host, int64_t npix
 }
 
 bool aligned256(const void* ptr) { return ((uintptr_t)ptr & 255) == 0; }
+
+// A caller's workspace: 256-byte aligned and at least `need` bytes.
+msft_status check_workspace(const void* ws, size_t ws_bytes, size_t need)
+{
+    if (!aligned256(ws)) return fail(MSFT_ERR_INVALID, "workspace must be 256-byte aligned");
+    if (ws_bytes < need) {
+        char buf[128];
+        std::snprintf(buf, sizeof buf, "workspace of %zu bytes, the call needs %zu", ws_bytes, need);
+        return fail(MSFT_ERR_BUSY, buf);
+    }
+    return MSFT_OK;
+}
 
 FwdArgs forward_args(const msft_plan_s* p, const void* wtiles, float* intensity, float* amplitude)
 {
@@ -585,12 +603,13 @@ msft_status msft_plan_destroy(msft_plan_t plan)
 }
 
 msft_status msft_plan_query(msft_plan_t plan, int64_t* npix, size_t* workspace_bytes,
-                            size_t* resident_bytes)
+                            size_t* resident_bytes, size_t* per_request_bytes)
 {
     if (!plan) return fail(MSFT_ERR_INVALID, "plan is NULL");
     if (npix) *npix = plan->geo.npix;
     if (workspace_bytes) *workspace_bytes = plan->workspace_bytes;
     if (resident_bytes) *resident_bytes = plan->resident_bytes;
+    if (per_request_bytes) *per_request_bytes = plan->per_request;
     return ok();
 }
 
@@ -610,16 +629,10 @@ msft_status msft_plan_grid(msft_plan_t plan, double* x, double* y, double* z)
     return ok();
 }
 
-msft_status msft_simulate(msft_plan_t plan, const float* delta, const float* beta, float* intensity,
-                          float* amplitude, void* workspace, void* stream)
+// The scan and the contraction of one target, the plan's device current.
+static msft_status simulate_launch(msft_plan_t plan, const float* delta, const float* beta,
+                                   float* intensity, float* amplitude, void* workspace, void* stream)
 {
-    msft_status st = check_runnable(plan);
-    if (st != MSFT_OK) return st;
-    if (!delta || !beta || !intensity || !workspace)
-        return fail(MSFT_ERR_INVALID, "delta, beta, intensity and workspace must be non-NULL");
-    if (!aligned256(workspace)) return fail(MSFT_ERR_INVALID, "workspace must be 256-byte aligned");
-    DeviceScope ds(plan->device);
-    if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice");
     const ScanArgs sa = scan_args(plan, delta, beta, workspace);
     int e = launch_scan(plan->geo.g.precision, sa, stream);
     if (e) return hip_fail((hipError_t)e, "scan launch");
@@ -628,13 +641,28 @@ msft_status msft_simulate(msft_plan_t plan, const float* delta, const float* bet
     return ok();
 }
 
+msft_status msft_simulate(msft_plan_t plan, const float* delta, const float* beta, float* intensity,
+                          float* amplitude, void* workspace, size_t ws_bytes, void* stream)
+{
+    msft_status st = check_runnable(plan);
+    if (st != MSFT_OK) return st;
+    if (!delta || !beta || !intensity || !workspace)
+        return fail(MSFT_ERR_INVALID, "delta, beta, intensity and workspace must be non-NULL");
+    st = check_workspace(workspace, ws_bytes, plan->fwd_workspace);
+    if (st != MSFT_OK) return st;
+    DeviceScope ds(plan->device);
+    if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice");
+    return simulate_launch(plan, delta, beta, intensity, amplitude, workspace, stream);
+}
+
 msft_status msft_simulate_scan(msft_plan_t plan, const float* delta, const float* beta, void* workspace,
-                          void* stream)
+                               size_t ws_bytes, void* stream)
 {
     msft_status st = check_runnable(plan);
     if (st != MSFT_OK) return st;
     if (!delta || !beta || !workspace) return fail(MSFT_ERR_INVALID, "NULL argument");
-    if (!aligned256(workspace)) return fail(MSFT_ERR_INVALID, "workspace must be 256-byte aligned");
+    st = check_workspace(workspace, ws_bytes, plan->fwd_workspace);
+    if (st != MSFT_OK) return st;
     DeviceScope ds(plan->device);
     if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice");
     int e = launch_scan(plan->geo.g.precision, scan_args(plan, delta, beta, workspace), stream);
@@ -642,13 +670,14 @@ msft_status msft_simulate_scan(msft_plan_t plan, const float* delta, const float
     return ok();
 }
 
-msft_status msft_simulate_contract(msft_plan_t plan, const void* workspace, float* intensity, float* amplitude,
-                          void* stream)
+msft_status msft_simulate_contract(msft_plan_t plan, const void* workspace, size_t ws_bytes,
+                                   float* intensity, float* amplitude, void* stream)
 {
     msft_status st = check_runnable(plan);
     if (st != MSFT_OK) return st;
     if (!workspace || !intensity) return fail(MSFT_ERR_INVALID, "NULL argument");
-    if (!aligned256(workspace)) return fail(MSFT_ERR_INVALID, "workspace must be 256-byte aligned");
+    st = check_workspace(workspace, ws_bytes, plan->fwd_workspace);
+    if (st != MSFT_OK) return st;
     DeviceScope ds(plan->device);
     if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice");
     int e = launch_contraction(plan, workspace, intensity, amplitude, stream);
@@ -757,13 +786,14 @@ msft_status msft_simulate_batch(const msft_request* reqs, int32_t n, void* works
 
 msft_status msft_backward(msft_plan_t plan, const float* delta, const float* beta,
                           const float* amplitude, const float* grad_intensity, float* grad_delta,
-                          float* grad_beta, void* workspace, void* stream)
+                          float* grad_beta, void* workspace, size_t ws_bytes, void* stream)
 {
     msft_status st = check_runnable(plan);
     if (st != MSFT_OK) return st;
     if (!delta || !beta || !amplitude || !grad_intensity || !grad_delta || !grad_beta || !workspace)
         return fail(MSFT_ERR_INVALID, "NULL argument");
-    if (!aligned256(workspace)) return fail(MSFT_ERR_INVALID, "workspace must be 256-byte aligned");
+    st = check_workspace(workspace, ws_bytes, plan->adj_workspace);
+    if (st != MSFT_OK) return st;
     const Dims& d = plan->dims;
     const msft_geometry& g = plan->geo.g;
     const AdjDims ad = make_adj_dims(d);

@@ -313,5 +313,8 @@ struct msft_plan_s {
     bool separable = false;
     msft::SepDims sep;
     size_t resident_bytes = 0;
-    size_t workspace_bytes = 0;
+    size_t workspace_bytes = 0;   // max of the two below
+    size_t fwd_workspace = 0;     // msft_simulate: W tiles (+ H tiles, separable detector)
+    size_t adj_workspace = 0;     // msft_backward
+    size_t per_request = 0;       // one request's own buffers + its share of a batch workspace
 };

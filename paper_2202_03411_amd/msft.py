@@ -88,16 +88,16 @@ def _load():
     lib.msft_plan.argtypes = [P(msft_geometry), ctypes.c_int, P(VP)]
     lib.msft_plan_qlist.argtypes = [P(msft_geometry), VP, I64, ctypes.c_int, P(VP)]
     lib.msft_plan_destroy.argtypes = [VP]
-    lib.msft_plan_query.argtypes = [VP, P(I64), P(S), P(S)]
+    lib.msft_plan_query.argtypes = [VP, P(I64), P(S), P(S), P(S)]
     lib.msft_plan_qmap.argtypes = [VP, VP]
     lib.msft_plan_grid.argtypes = [VP, VP, VP, VP]
-    lib.msft_simulate.argtypes = [VP, VP, VP, VP, VP, VP, VP]
-    lib.msft_simulate_scan.argtypes = [VP, VP, VP, VP, VP]
-    lib.msft_simulate_contract.argtypes = [VP, VP, VP, VP, VP]
+    lib.msft_simulate.argtypes = [VP, VP, VP, VP, VP, VP, S, VP]
+    lib.msft_simulate_scan.argtypes = [VP, VP, VP, VP, S, VP]
+    lib.msft_simulate_contract.argtypes = [VP, VP, S, VP, VP, VP]
     lib.msft_pixel_block.argtypes = []
     lib.msft_batch_query.argtypes = [P(msft_request), I32, P(S)]
     lib.msft_simulate_batch.argtypes = [P(msft_request), I32, VP, S, VP]
-    lib.msft_backward.argtypes = [VP, VP, VP, VP, VP, VP, VP, VP, VP]
+    lib.msft_backward.argtypes = [VP, VP, VP, VP, VP, VP, VP, VP, S, VP]
     D = ctypes.c_double
     lib.msft_render_sh.argtypes = [P(msft_shape_grid), I32, D, VP, VP, VP, VP]
     lib.msft_render_sh_query.argtypes = [I32, P(S)]
@@ -123,7 +123,8 @@ LIBRARY_PATH = _build.LIB
 
 # every symbol the C header declares
 EXPORTS = ("msft_plan", "msft_plan_qlist", "msft_plan_destroy", "msft_plan_query", "msft_plan_qmap",
-           "msft_plan_grid", "msft_simulate", "msft_simulate_scan", "msft_simulate_contract", "msft_pixel_block",
+           "msft_plan_grid", "msft_simulate", "msft_simulate_scan", "msft_simulate_contract",
+           "msft_pixel_block",
            "msft_batch_query",
            "msft_simulate_batch", "msft_backward", "msft_render_sh", "msft_render_sh_query",
            "msft_render_sh_backward", "msft_render_ellipsoid", "msft_render_volume",
@@ -177,10 +178,62 @@ def make_geometry(wavelength, theta_max_deg, det_n, grid, pitch, precision="fp32
     return g
 
 
+# What the binding knows of each live plan, to check the buffers it is handed
+# before their pointers cross the boundary: handle -> (grid, npix, device, workspace).
+_PLANS: dict = {}
+
+
+def _register(handle: int, geometry: msft_geometry, device: int) -> int:
+    npix, ws, _, _ = msft_plan_query(handle)
+    _PLANS[handle] = ((geometry.nx, geometry.ny, geometry.nz), npix, int(device), ws)
+    return handle
+
+
+def _plan_info(plan: int):
+    info = _PLANS.get(plan)
+    if info is None:
+        raise ValueError("unknown plan handle (create plans with msft_plan / msft_plan_qlist)")
+    return info
+
+
+def _check_tensor(t, name, numel, device, dtype=torch.float32, shape=None):
+    """A float32, contiguous buffer of `numel` values on the plan's device."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.device.type != "cuda" or t.device.index != device:
+        raise ValueError(f"{name} must live on cuda:{device}, got {t.device}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if t.numel() != numel:
+        raise ValueError(f"{name} must hold {numel} values, got {t.numel()}")
+
+
+def _check_workspace(ws, device):
+    _check_tensor(ws, "workspace", ws.numel(), device, dtype=ws.dtype)
+    return ws.numel() * ws.element_size()
+
+
+def _check_io(plan, delta=None, beta=None, intensity=None, amplitude=None):
+    grid, npix, dev, _ = _plan_info(plan)
+    V = grid[0] * grid[1] * grid[2]
+    for name, t in (("delta", delta), ("beta", beta)):
+        if t is not None:
+            _check_tensor(t, name, V, dev)
+    if intensity is not None:
+        _check_tensor(intensity, "intensity", npix, dev)
+    if amplitude is not None:
+        _check_tensor(amplitude, "amplitude", 2 * npix, dev)
+    return dev
+
+
 def msft_plan(geometry: msft_geometry, device: int = 0) -> int:
     h = ctypes.c_void_p()
     _check(_lib.msft_plan(ctypes.byref(geometry), int(device), ctypes.byref(h)), "msft_plan")
-    return h.value
+    return _register(h.value, geometry, device)
 
 
 def msft_plan_qlist(geometry: msft_geometry, q, device: int = 0) -> int:
@@ -188,19 +241,20 @@ def msft_plan_qlist(geometry: msft_geometry, q, device: int = 0) -> int:
     h = ctypes.c_void_p()
     _check(_lib.msft_plan_qlist(ctypes.byref(geometry), q.ctypes.data_as(ctypes.c_void_p),
                                 q.shape[0], int(device), ctypes.byref(h)), "msft_plan_qlist")
-    return h.value
+    return _register(h.value, geometry, device)
 
 
 def msft_plan_destroy(plan: int) -> None:
     _check(_lib.msft_plan_destroy(ctypes.c_void_p(plan)), "msft_plan_destroy")
+    _PLANS.pop(plan, None)
 
 
 def msft_plan_query(plan: int):
-    """(npix, workspace_bytes, resident_bytes)."""
-    n, w, r = ctypes.c_int64(), ctypes.c_size_t(), ctypes.c_size_t()
+    """(npix, workspace_bytes, resident_bytes, per_request_bytes)."""
+    n, w, r, q = ctypes.c_int64(), ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
     _check(_lib.msft_plan_query(ctypes.c_void_p(plan), ctypes.byref(n), ctypes.byref(w),
-                                ctypes.byref(r)), "msft_plan_query")
-    return n.value, w.value, r.value
+                                ctypes.byref(r), ctypes.byref(q)), "msft_plan_query")
+    return n.value, w.value, r.value, q.value
 
 
 def msft_plan_qmap(plan: int) -> np.ndarray:
@@ -219,18 +273,26 @@ def msft_plan_grid(plan: int, shape):
 
 
 def msft_simulate(plan, delta, beta, intensity, amplitude, workspace, stream=None) -> None:
+    dev = _check_io(plan, delta, beta, intensity, amplitude)
+    nbytes = _check_workspace(workspace, dev)
     _check(_lib.msft_simulate(ctypes.c_void_p(plan), _ptr(delta), _ptr(beta), _ptr(intensity),
-                              _ptr(amplitude), _ptr(workspace), _stream(stream)), "msft_simulate")
+                              _ptr(amplitude), _ptr(workspace), nbytes, _stream(stream)),
+           "msft_simulate")
 
 
 def msft_simulate_scan(plan, delta, beta, workspace, stream=None) -> None:
+    dev = _check_io(plan, delta, beta)
+    nbytes = _check_workspace(workspace, dev)
     _check(_lib.msft_simulate_scan(ctypes.c_void_p(plan), _ptr(delta), _ptr(beta), _ptr(workspace),
-                              _stream(stream)), "msft_simulate_scan")
+                                   nbytes, _stream(stream)), "msft_simulate_scan")
 
 
 def msft_simulate_contract(plan, workspace, intensity, amplitude, stream=None) -> None:
-    _check(_lib.msft_simulate_contract(ctypes.c_void_p(plan), _ptr(workspace), _ptr(intensity),
-                              _ptr(amplitude), _stream(stream)), "msft_simulate_contract")
+    dev = _check_io(plan, intensity=intensity, amplitude=amplitude)
+    nbytes = _check_workspace(workspace, dev)
+    _check(_lib.msft_simulate_contract(ctypes.c_void_p(plan), _ptr(workspace), nbytes,
+                                       _ptr(intensity), _ptr(amplitude), _stream(stream)),
+           "msft_simulate_contract")
 
 
 def msft_pixel_block() -> int:
@@ -238,10 +300,12 @@ def msft_pixel_block() -> int:
 
 
 def _requests(reqs):
+    """The C request array; every buffer is checked against its plan first."""
     arr = (msft_request * max(len(reqs), 1))()
     for k, r in enumerate(reqs):
         plan, delta, beta, inten, amp = r[:5]
         rng = r[5] if len(r) > 5 else (-1, -1)
+        _check_io(plan, delta, beta, inten, amp)
         arr[k] = msft_request(plan, delta.data_ptr(), beta.data_ptr(), inten.data_ptr(),
                               amp.data_ptr() if amp is not None else None, int(rng[0]), int(rng[1]))
     return arr
@@ -257,16 +321,20 @@ def msft_batch_query(reqs) -> int:
 
 def msft_simulate_batch(reqs, workspace, stream=None) -> None:
     arr = _requests(reqs)
-    _check(_lib.msft_simulate_batch(arr, len(reqs), _ptr(workspace),
-                                    workspace.numel() * workspace.element_size(), _stream(stream)),
+    dev = _plan_info(reqs[0][0])[2] if len(reqs) else workspace.device.index
+    nbytes = _check_workspace(workspace, dev)
+    _check(_lib.msft_simulate_batch(arr, len(reqs), _ptr(workspace), nbytes, _stream(stream)),
            "msft_simulate_batch")
 
 
 def msft_backward(plan, delta, beta, amplitude, grad_intensity, grad_delta, grad_beta, workspace,
                   stream=None) -> None:
+    dev = _check_io(plan, delta, beta, grad_intensity, amplitude)
+    _check_io(plan, grad_delta, grad_beta)
+    nbytes = _check_workspace(workspace, dev)
     _check(_lib.msft_backward(ctypes.c_void_p(plan), _ptr(delta), _ptr(beta), _ptr(amplitude),
                               _ptr(grad_intensity), _ptr(grad_delta), _ptr(grad_beta),
-                              _ptr(workspace), _stream(stream)), "msft_backward")
+                              _ptr(workspace), nbytes, _stream(stream)), "msft_backward")
 
 
 def workspace_tensor(nbytes: int, device) -> torch.Tensor:
@@ -284,12 +352,14 @@ class Plan:
         self.geometry = make_geometry(wavelength, theta_max_deg, det_n, grid, pitch, precision,
                                       strength, allow_alias, detector)
         self.grid = tuple(int(v) for v in grid)
+        self.pitch = tuple(float(v) for v in pitch)
         self.device_index = int(device)
         if q is None:
             self.handle = msft_plan(self.geometry, self.device_index)
         else:
             self.handle = msft_plan_qlist(self.geometry, q, self.device_index)
-        self.npix, self.workspace_bytes, self.resident_bytes = msft_plan_query(self.handle)
+        (self.npix, self.workspace_bytes, self.resident_bytes,
+         self.per_request_bytes) = msft_plan_query(self.handle)
         self._ws = None
 
     @classmethod

@@ -27,21 +27,35 @@ class Request:
     rid: int
     arrival: float                 # seconds, on the server clock
     key: tuple                     # geometry key: (wavelength, theta, det_n, grid, pitch, mode)
-    payload: object = None         # executor-specific inputs (device delta/beta, ...)
-    admitted: float = math.nan
+    payload: object = None         # executor inputs: a shape to render, or device (delta, beta)
+    admitted: float = math.nan     # first work launched
     done: float = math.nan
-    footprint: int = 0
-    cost: float = 0.0              # executor's work estimate (voxel-pixel terms on the GPU)
+    io_bytes: int = 0              # inputs and outputs, held from the first launch to completion
+    ws_bytes: int = 0              # scratch of one launch item of this request
+    blocks: int = 1                # pixel blocks (work items) of the request
+    block_cost: float = 0.0        # executor's estimate of one block's device time (s)
+    wave_blocks: int = 1           # blocks the device runs at once: slices are multiples of it
+    next_block: int = 0            # first block not launched yet
+    open_items: int = 0            # launched items not finished yet
     result: object = None
+    state: object = None           # executor's per-request device state
 
     @property
     def latency(self):
         return self.done - self.arrival
 
+    @property
+    def cost(self):
+        return self.blocks * self.block_cost
+
+    @property
+    def footprint(self):
+        return self.io_bytes + self.ws_bytes
+
 
 @dataclasses.dataclass
 class Batch:
-    requests: list
+    items: list                    # (request, first block, end block)
     handle: object
     footprint: int
     launched: float
@@ -52,42 +66,49 @@ class Scheduler:
     """Admission + batching policy, independent of the device.
 
     executor must provide:
-      footprint(req) -> bytes the request holds while in flight
-      launch(list[Request]) -> handle        (asynchronous)
+      describe(req)    fill req.io_bytes, req.ws_bytes, req.blocks, req.block_cost,
+                       req.wave_blocks
+      launch(items) -> handle                 (asynchronous; items: (req, b0, b1))
       poll(handle) -> bool                    (True once finished)
-      finish(handle, list[Request])          (collect results, free buffers)
-    and may provide cost(req) -> work estimate, used with max_batch_cost.
+      finish(handle, items)                   (release the launch's buffers)
+      complete(req)                           (all of req's blocks are done: set req.result)
 
-    Every request of a launch completes when the launch does, so a launch groups
-    queued requests only up to max_batch_cost of work (at least one request):
-    cheap requests share a launch, an expensive one runs in its own, and the
-    launches in flight share the device.  With one_large, at most one launch of
-    an expensive request (cost above max_batch_cost) is in flight: expensive
-    requests run one after another in arrival order instead of slowing each
-    other down, while cheap requests behind a waiting expensive one may start.
+    A launch holds at most `quantum` seconds of estimated device work.  A request
+    whose whole cost fits the quantum is cheap: cheap requests are grouped in arrival
+    order, up to the quantum and max_batch, and go first.  An expensive request is cut
+    into slices of pixel blocks worth about one quantum each (a whole number of device
+    waves of blocks, at least one, so that a slice fills the device), launched one
+    slice per launch, oldest request first; cheap requests that arrive meanwhile start between
+    its slices instead of waiting for all of it.  At most max_inflight launches are in
+    flight, so the device always has queued work; expensive slices leave one launch
+    slot to cheap arrivals.  Memory: a request's inputs and outputs are charged from
+    its first launch to its completion, each launch item's scratch while it runs; the
+    total stays within hbm_budget.  With quantum None nothing is sliced and requests
+    are grouped first-come first-served up to max_batch.
     """
 
     def __init__(self, executor, hbm_budget: int, max_inflight: int = 3, max_batch: int = 24,
-                 clock: Callable[[], float] = time.perf_counter, max_batch_cost=None,
-                 one_large: bool = False):
+                 clock: Callable[[], float] = time.perf_counter, quantum=None):
         if max_inflight < 1 or max_batch < 1:
             raise ValueError("max_inflight and max_batch must be >= 1")
+        if quantum is not None and not quantum > 0:
+            raise ValueError("quantum must be > 0 or None")
         self.ex = executor
         self.budget = int(hbm_budget)
         self.max_inflight = max_inflight
         self.max_batch = max_batch
-        self.max_batch_cost = max_batch_cost
-        self.one_large = bool(one_large) and max_batch_cost is not None
+        self.quantum = quantum
         self.clock = clock
-        self.queue: collections.deque = collections.deque()
+        self.queue: list = []          # requests with blocks not launched yet, arrival order
         self.inflight: list = []
         self.used = 0
         self.completed: list = []
         self.rejected: list = []
 
     def submit(self, req: Request):
-        req.footprint = int(self.ex.footprint(req))
-        req.cost = float(self.ex.cost(req)) if hasattr(self.ex, "cost") else 0.0
+        self.ex.describe(req)
+        req.next_block = 0
+        req.open_items = 0
         if req.footprint > self.budget:
             # could never be admitted: refuse instead of blocking the queue
             self.rejected.append(req)
@@ -100,50 +121,75 @@ class Scheduler:
         still = []
         for b in self.inflight:
             if self.ex.poll(b.handle):
-                self.ex.finish(b.handle, b.requests)
-                for r in b.requests:
-                    r.done = now
-                    self.completed.append(r)
+                self.ex.finish(b.handle, b.items)
                 self.used -= b.footprint
+                for r, _, _ in b.items:
+                    r.open_items -= 1
+                    if r.open_items == 0 and r.next_block == r.blocks:
+                        r.done = now
+                        self.ex.complete(r)
+                        self.used -= r.io_bytes
+                        self.completed.append(r)
             else:
                 still.append(b)
         self.inflight = still
 
-    def _large(self, r):
-        return self.max_batch_cost is not None and r.cost > self.max_batch_cost
+    def _cheap(self, r):
+        return self.quantum is None or (r.next_block == 0 and r.cost <= self.quantum)
+
+    def _take(self, items, r, b0, b1):
+        items.append((r, b0, b1))
+        r.next_block = b1
+        r.open_items += 1
+        need = r.ws_bytes + (r.io_bytes if b0 == 0 else 0)
+        return need
 
     def admit_and_launch(self):
-        """Form at most one batch from the head of the queue (FIFO; with one_large,
-        cheap requests may pass an expensive one that waits for the running one)."""
+        """Form at most one launch: cheap requests first (arrival order), else one
+        slice of the oldest expensive request."""
         if len(self.inflight) >= self.max_inflight or not self.queue:
             return None
-        start = 0
-        large_busy = self.one_large and any(b.large for b in self.inflight)
-        if large_busy:
-            while start < len(self.queue) and self._large(self.queue[start]):
-                start += 1
-            if start == len(self.queue):
-                return None
-        batch, foot, cost = [], 0, 0.0
-        while start < len(self.queue) and len(batch) < self.max_batch:
-            r = self.queue[start]
-            if self.used + foot + r.footprint > self.budget:
+        items, foot, cost = [], 0, 0.0
+        k = 0
+        while k < len(self.queue) and len(items) < self.max_batch:
+            r = self.queue[k]
+            if not self._cheap(r):
+                k += 1
+                continue
+            need = r.io_bytes + r.ws_bytes
+            if self.used + foot + need > self.budget:
                 break
-            if batch and self.max_batch_cost is not None and cost + r.cost > self.max_batch_cost:
+            if items and self.quantum is not None and cost + r.cost > self.quantum:
                 break
-            if large_busy and self._large(r):
-                break
-            batch.append(r)
-            del self.queue[start]
-            foot += r.footprint
+            foot += self._take(items, r, 0, r.blocks)
             cost += r.cost
-        if not batch:
+            del self.queue[k]
+        large = False
+        if not items:
+            big = [r for r in self.queue if not self._cheap(r)]
+            n_large = sum(1 for b in self.inflight if b.large)
+            if big and (self.max_inflight == 1 or n_large < self.max_inflight - 1):
+                r = big[0]
+                wave = max(1, r.wave_blocks)
+                per = (max(1, int(self.quantum / (r.block_cost * wave))) * wave
+                       if r.block_cost > 0 else r.blocks)
+                b0 = r.next_block
+                b1 = min(r.blocks, b0 + per)
+                need = r.ws_bytes + (r.io_bytes if b0 == 0 else 0)
+                if self.used + need <= self.budget:
+                    foot += self._take(items, r, b0, b1)
+                    if b1 == r.blocks:
+                        self.queue.remove(r)
+                    large = True
+        if not items:
             return None
         now = self.clock()
-        for r in batch:
-            r.admitted = now
-        handle = self.ex.launch(batch)
-        b = Batch(batch, handle, foot, now, any(self._large(r) for r in batch))
+        for r, b0, _ in items:
+            if b0 == 0:
+                r.admitted = now
+        handle = self.ex.launch(items)
+        ws = sum(r.ws_bytes for r, _, _ in items)
+        b = Batch(items, handle, ws, now, large)
         self.inflight.append(b)
         self.used += foot
         return b
@@ -214,13 +260,20 @@ def summarize(requests, t0: float, t_end: float):
 # ---------------------------------------------------------------------------
 
 class PlanCache:
-    """One resident plan per (geometry, precision); plans are built on first use."""
+    """One resident plan per (geometry, precision); plans are built on first use.
 
-    def __init__(self, msft, precision: str, device: int = 0):
+    With calibrate (the default) a new plan times two forward passes of an empty
+    volume on the device, and the second one's duration per pixel block becomes the
+    plan's block_cost: the scheduler's work estimates are the plan's measured rate,
+    not a constant."""
+
+    def __init__(self, msft, precision: str, device: int = 0, calibrate: bool = True):
         self.msft = msft
         self.precision = precision
         self.device = device
+        self.calibrate = calibrate
         self.plans = {}
+        self.block_cost = {}
 
     def get(self, key):
         p = self.plans.get(key)
@@ -229,7 +282,24 @@ class PlanCache:
             p = self.msft.Plan(wavelength, theta, det_n, grid, pitch, self.precision, mode,
                                self.device)
             self.plans[key] = p
+            self.block_cost[key] = self._measure(p) if self.calibrate else 0.0
         return p
+
+    def blocks(self, key):
+        return -(-self.get(key).npix // self.msft.msft_pixel_block())
+
+    def _measure(self, p):
+        import torch
+        dev = p.device
+        d = torch.zeros(p.grid, dtype=torch.float32, device=dev)
+        I = torch.empty(p.npix, dtype=torch.float32, device=dev)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        p.simulate(d, d, out=I)
+        e0.record()
+        p.simulate(d, d, out=I)
+        e1.record()
+        torch.cuda.synchronize(dev)
+        return e0.elapsed_time(e1) * 1e-3 / (-(-p.npix // self.msft.msft_pixel_block()))
 
     def resident_bytes(self):
         return sum(p.resident_bytes for p in self.plans.values())
@@ -238,130 +308,174 @@ class PlanCache:
         for p in self.plans.values():
             p.close()
         self.plans.clear()
+        self.block_cost.clear()
+
+
+@dataclasses.dataclass
+class Shape:
+    """A request's target, rendered on the device when its first work is launched:
+    an ellipsoid (semi-axes `axes`, body axes the columns of `rot`) or a star body
+    r0 (1 + sum c_lm Y_lm) (`coeffs`: (lmax + 1)^2 values at l*l + l + m)."""
+    kind: str
+    axes: object = None
+    rot: object = None
+    r0: float = 0.0
+    coeffs: object = None
+    lmax: int = 8
+    delta0: float = 0.01
+    beta0: float = 0.02
+
+
+class _ReqState:
+    __slots__ = ("delta", "beta", "out", "ready", "stream")
+
+    def __init__(self):
+        self.delta = self.beta = self.out = self.ready = None
+        self.stream = -1
 
 
 class GpuExecutor:
-    """Runs each admitted group as one batched launch (msft_simulate_batch).
+    """Runs each launch's items (request, pixel blocks) as one msft_simulate_batch.
 
-    Every in-flight launch owns one stream of a small pool (default priority)
-    and its own workspace, so launches overlap on the device.  With
-    ``batched=False`` every request is its own msft_simulate launch on a single
-    stream (the plain one-pattern-per-launch form), reusing the plan's workspace.
+    Every in-flight launch owns one stream of a small pool (default priority) and
+    its own workspace, so launches overlap on the device.  A request's target is
+    rendered (msft_render_ellipsoid / msft_render_sh) on the stream of its first
+    launch, into buffers that live until the request completes; later slices of
+    the request on other streams wait for that render.  With ``batched=False``
+    every request is its own render + msft_simulate on one stream (the plain
+    one-pattern-per-launch form), reusing the plan's workspace.  keep_inputs keeps
+    each request's rendered delta and beta on the request after it completes.
     """
 
-    def __init__(self, plans: PlanCache, torch, nstreams: int = 3, batched: bool = True):
+    def __init__(self, plans: PlanCache, torch, nstreams: int = 3, batched: bool = True,
+                 keep_inputs: bool = False):
         self.plans = plans
         self.torch = torch
         self.msft = plans.msft
         self.batched = batched
+        self.keep_inputs = keep_inputs
         n = nstreams if batched else 1
         self.streams = [torch.cuda.Stream() for _ in range(n)]
         self.free = list(range(n))
+        # pixel blocks resident at once: compute units x workgroups per CU of the
+        # contraction (two of the FP32 three-product kernel, one of the BF16 kernel)
+        cus = torch.cuda.get_device_properties(plans.device).multi_processor_count
+        self.wave_blocks = cus * (2 if plans.precision == "fp32" else 1)
 
-    def cost(self, req):
+    def describe(self, req):
         p = self.plans.get(req.key)
-        return float(p.npix) * p.grid[0] * p.grid[1] * p.grid[2]
+        V = p.grid[0] * p.grid[1] * p.grid[2]
 
-    def footprint(self, req):
-        p = self.plans.get(req.key)
-        out = 4 * p.npix
+        def r256(b):
+            return -(-b // 256) * 256
+        req.io_bytes = 2 * r256(4 * V) + r256(4 * p.npix)
+        # msft_plan_query's per-request bytes less the inputs, intensity and
+        # amplitude: the forward scratch of one batch item
+        req.ws_bytes = p.per_request_bytes - 2 * r256(4 * V) - r256(4 * p.npix) - r256(8 * p.npix)
         if not self.batched:
-            return out
-        d, b = req.payload
-        return self.msft.msft_batch_query([(p.handle, d, b, d, None)]) + out
+            req.ws_bytes = 0           # one stream: the plan's own workspace
+        req.blocks = self.plans.blocks(req.key)
+        req.block_cost = self.plans.block_cost.get(req.key, 0.0)
+        req.wave_blocks = self.wave_blocks
 
-    def launch(self, batch):
+    def _render(self, req, p):
+        torch, msft = self.torch, self.msft
+        st = _ReqState()
+        sh = req.payload
+        if isinstance(sh, Shape):
+            g = msft.make_shape_grid(p.grid, p.pitch, 0.0, sh.delta0, sh.beta0)
+            st.delta = torch.empty(p.grid, dtype=torch.float32, device=p.device)
+            st.beta = torch.empty_like(st.delta)
+            if sh.kind == "ellipsoid":
+                msft.msft_render_ellipsoid(g, sh.axes, sh.rot, st.delta, st.beta)
+            else:
+                c = torch.from_numpy(sh.coeffs).to(p.device)
+                msft.msft_render_sh(g, sh.lmax, sh.r0, c, st.delta, st.beta)
+        else:
+            st.delta, st.beta = sh
+        st.out = torch.empty(p.npix, dtype=torch.float32, device=p.device)
+        return st
+
+    def launch(self, items):
         torch = self.torch
         sidx = self.free.pop() if self.batched else 0
         s = self.streams[sidx]
-        outs, reqs, keep = [], [], []
+        reqs, keep = [], []
         with torch.cuda.stream(s):
-            for r in batch:
+            for r, b0, b1 in items:
                 p = self.plans.get(r.key)
-                d, b = r.payload
-                I = torch.empty(p.npix, dtype=torch.float32, device="cuda")
-                outs.append(I)
-                reqs.append((p.handle, d, b, I, None))
+                if r.state is None:
+                    r.state = self._render(r, p)
+                    r.state.stream = sidx
+                    if self.batched and b1 < r.blocks:
+                        r.state.ready = torch.cuda.Event()
+                        r.state.ready.record(s)
+                elif r.state.stream != sidx and r.state.ready is not None:
+                    s.wait_event(r.state.ready)
+                st = r.state
+                if self.batched:
+                    reqs.append((p.handle, st.delta, st.beta, st.out, None, (b0, b1)))
+                else:
+                    self.msft.msft_simulate(p.handle, st.delta, st.beta, st.out, None,
+                                            p.workspace(), stream=s)
             if self.batched:
-                ws = self.msft.workspace_tensor(self.msft.msft_batch_query(reqs), "cuda")
+                ws = self.msft.workspace_tensor(self.msft.msft_batch_query(reqs), p.device)
                 self.msft.msft_simulate_batch(reqs, ws, stream=s)
                 keep.append(ws)
-            else:
-                for (h, d, b, I, _), r in zip(reqs, batch):
-                    self.msft.msft_simulate(h, d, b, I, None, self.plans.get(r.key).workspace(),
-                                            stream=s)
             ev = torch.cuda.Event()
             ev.record(s)
-        return {"event": ev, "stream": sidx, "outs": outs, "keep": keep}
+        return {"event": ev, "stream": sidx, "keep": keep}
 
     def poll(self, handle):
         return handle["event"].query()
 
-    def finish(self, handle, batch):
-        for r, I in zip(batch, handle["outs"]):
-            r.result = I
+    def finish(self, handle, items):
         handle["keep"].clear()
         if self.batched:
             self.free.append(handle["stream"])
 
+    def complete(self, req):
+        st = req.state
+        req.result = st.out
+        req.state = None
+        if self.keep_inputs:
+            req.payload = (st.delta, st.beta)
+
 
 # ---------------------------------------------------------------------------
-# seeded request streams (shapes rendered on the device)
+# seeded request streams (a fresh shape per request, rendered on the device)
 # ---------------------------------------------------------------------------
 
 SERVE_GRIDS = (64, 96, 128, 192)
 SERVE_DETS = (256, 512, 1024)
 
 
-class ShapePool:
-    """A few hard-voxel shapes per grid size, rendered on the GPU by the library
-    from seeds: ellipsoids (semi-axes U[80, 250] nm, Haar-random orientation) and
-    l <= 8 harmonic bodies (R0 ~ U[80, 170] nm, c ~ N(0, 0.08^2), r_max <= 340 nm),
-    all in one fixed box so that a (grid, detector) pair shares one plan."""
+def random_shape(rng, box=700.0, delta0=0.01, beta0=0.02):
+    """Half ellipsoids (semi-axes U[80, 250] nm, Haar-random orientation), half
+    l <= 8 harmonic bodies (R0 ~ U[80, 170] nm, c ~ N(0, 0.08^2) for 1 <= l <= 8,
+    redrawn until r_max <= 340 nm), in the fixed box shared by every request."""
+    import numpy as np
 
-    def __init__(self, torch, grids=SERVE_GRIDS, per_kind=2, box=700.0, delta0=0.01, beta0=0.02,
-                 seed=0, device="cuda"):
-        import numpy as np
-
-        from . import inputs, msft
-        self.box = box
-        self.shapes = {}
-        rng = np.random.default_rng(seed)
-        for n in grids:
-            g = msft.make_shape_grid((n, n, n), (box / n,) * 3, 0.0, delta0, beta0)
-            lst = []
-            for _ in range(per_kind):
-                axes = rng.uniform(80.0, 250.0, size=3)
-                R = inputs.haar_rotation(rng)
-                d = torch.empty((n, n, n), dtype=torch.float32, device=device)
-                b = torch.empty_like(d)
-                msft.msft_render_ellipsoid(g, axes, R, d, b)
-                lst.append((d, b))
-            for _ in range(per_kind):
-                while True:
-                    r0 = float(rng.uniform(80.0, 170.0))
-                    coeffs = inputs.sh_coefficients(rng, 1, 8, 0.08)
-                    _, rmax = inputs.sh_radius_range(coeffs, r0, 91, 181)
-                    if rmax <= 340.0:
-                        break
-                cvec = np.zeros(81, np.float32)
-                for l, m, v in coeffs:
-                    cvec[l * l + l + m] = v
-                c = torch.from_numpy(cvec).to(device)
-                d = torch.empty((n, n, n), dtype=torch.float32, device=device)
-                b = torch.empty_like(d)
-                msft.msft_render_sh(g, 8, r0, c, d, b)
-                lst.append((d, b))
-            self.shapes[n] = lst
-
-    def pick(self, n, k):
-        return self.shapes[n][k % len(self.shapes[n])]
+    from . import inputs
+    if rng.random() < 0.5:
+        return Shape("ellipsoid", axes=rng.uniform(80.0, 250.0, size=3),
+                     rot=inputs.haar_rotation(rng), delta0=delta0, beta0=beta0)
+    while True:
+        r0 = float(rng.uniform(80.0, 170.0))
+        coeffs = inputs.sh_coefficients(rng, 1, 8, 0.08)
+        _, rmax = inputs.sh_radius_range(coeffs, r0, 91, 181)
+        if rmax <= 0.5 * box - 10.0:
+            break
+    cvec = np.zeros(81, np.float32)
+    for l, m, v in coeffs:
+        cvec[l * l + l + m] = v
+    return Shape("harmonic", r0=r0, coeffs=cvec, lmax=8, delta0=delta0, beta0=beta0)
 
 
-def make_requests(pool, count, seed, rate=None, wavelength=45.0, theta=60.0,
-                  grids=SERVE_GRIDS, dets=SERVE_DETS):
-    """Seeded requests: uniform grid and detector size, a pool shape; Poisson
-    arrivals at `rate` per second, or all at t = 0 when rate is None."""
+def make_requests(count, seed, rate=None, wavelength=45.0, theta=60.0, grids=SERVE_GRIDS,
+                  dets=SERVE_DETS, box=700.0):
+    """Seeded requests: uniform grid and detector size, a fresh random shape each;
+    Poisson arrivals at `rate` per second, or all at t = 0 when rate is None."""
     import numpy as np
     rng = np.random.default_rng(seed)
     arr = poisson_arrivals(count, rate, seed + 1) if rate else np.zeros(count)
@@ -369,30 +483,21 @@ def make_requests(pool, count, seed, rate=None, wavelength=45.0, theta=60.0,
     for k in range(count):
         n = int(rng.choice(grids))
         det = int(rng.choice(dets))
-        shape = int(rng.integers(0, 1 << 30))
-        pitch = pool.box / n
+        pitch = box / n
         key = (wavelength, theta, det, (n, n, n), (pitch, pitch, pitch), "msft")
-        out.append(Request(k, float(arr[k]), key, pool.pick(n, shape)))
+        out.append(Request(k, float(arr[k]), key, random_shape(rng, box)))
     return out
 
 
-# Voxel-pixel terms per second of the contraction (measured, 128^3 / 512^2), used
-# only to turn a launch's time quantum into a work limit.
-TERMS_PER_S = {"fp32": 1.66e13, "bf16x3": 5.8e13, "bf16": 8.3e13}
-
-
 def serve(torch, msft, plans, requests, batched=True, hbm_budget=16 << 30, slots=4, max_batch=24,
-          quantum_s=0.005, one_large=True, progress=None):
+          quantum_s=0.005, progress=None, keep_inputs=False):
     """Run a request list through the server; returns (summary, requests).  A batched
-    launch holds at most quantum_s of estimated work (None: no limit); with one_large
-    (the default) requests above that quantum run one at a time while cheap ones pass
-    them (measured on a mixed stream: at 0.9 of capacity the median latency drops
-    fivefold for a p99 within a tenth of one-pattern-per-launch)."""
-    ex = GpuExecutor(plans, torch, nstreams=slots, batched=batched)
-    limit = None if quantum_s is None else quantum_s * TERMS_PER_S[plans.precision]
+    launch holds at most quantum_s of the plans' measured work: expensive requests
+    are sliced into pixel-block ranges of that size (None: no slicing)."""
+    ex = GpuExecutor(plans, torch, nstreams=slots, batched=batched, keep_inputs=keep_inputs)
     sched = Scheduler(ex, hbm_budget, max_inflight=slots if batched else 1 << 30,
-                      max_batch=max_batch if batched else 1, max_batch_cost=limit,
-                      one_large=one_large and batched)
+                      max_batch=max_batch if batched else 1,
+                      quantum=quantum_s if batched else None)
     t0 = run_stream(sched, requests, progress=progress)
     torch.cuda.synchronize()
     t_end = max(r.done for r in sched.completed) if sched.completed else t0
@@ -411,16 +516,18 @@ def benchmark(count=96, precision="fp32", loads=(0.8,), seed=20220205, device=0,
     import torch
 
     from . import msft
-    pool = ShapePool(torch, seed=seed)
     plans = PlanCache(msft, precision, device)
-    probe = make_requests(pool, count, seed, None)
+    probe = make_requests(count, seed, None)
     for r in probe:
         plans.get(r.key)          # plans and twiddles resident before the clock starts
     out = {"precision": precision, "requests": count, "resident_plans": len(plans.plans),
-           "resident_bytes": plans.resident_bytes()}
+           "resident_bytes": plans.resident_bytes(),
+           "stream": "C3 families: grids {64,96,128,192}^3 in a 700 nm box, detectors "
+                     "{256,512,1024}^2 to 60 deg, lambda 45 nm, a fresh seeded ellipsoid or "
+                     "l <= 8 harmonic body per request rendered on the GPU at launch"}
 
     def run(name, rate, batched):
-        reqs = make_requests(pool, count, seed, rate)
+        reqs = make_requests(count, seed, rate)
         mode = "batched" if batched else "plain"
         prog = (lambda d, n: log(f"{name} {mode}: {d}/{n} done")) if log else None
         s, _ = serve(torch, msft, plans, reqs, batched=batched, progress=prog)

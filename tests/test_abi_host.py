@@ -58,7 +58,7 @@ def test_uniform_plan_sizes():
     g = msft.make_geometry(45.0, 60.0, 23, (150, 70, 40), (3.0, 3.0, 3.0), detector="uniform_q")
     h = msft.msft_plan(g, -1)
     try:
-        npix, ws, _ = msft.msft_plan_query(h)
+        npix, ws, _, _ = msft.msft_plan_query(h)
         assert npix == 529
         fwd = 3 * 2 * 70 * 16384 + 23 * 2 * 2 * 16384
         assert ws >= fwd
@@ -135,17 +135,22 @@ def test_query_sizes_and_host_only_refusal():
     g = msft.make_geometry(45.0, 60.0, 20, (150, 5, 33), (3.0, 9.0, 8.0))
     h = msft.msft_plan(g, -1)
     try:
-        npix, ws, res = msft.msft_plan_query(h)
+        npix, ws, res, per_req = msft.msft_plan_query(h)
         assert npix == 400
-        # forward: W tiles, ceil(150/64) x chunks * ceil(33/32) z blocks * 5 y, 24 KiB each
-        # in FP32 (planes Wr, Wi, Wr + Wi of the three-product contraction);
+        # forward: W tiles, ceil(150/32) x chunks * ceil(33/32) z blocks * 5 y, 12 KiB each
+        # in FP32 (planes Wr, Wi, Wr + Wi of the three-product contraction, 32 x each);
         # backward: h (512 padded pixels, complex64) + 8 pixel groups of partial
         # strength gradients over the padded 192 x 5 x 64 grid
-        fwd = 3 * 2 * 5 * 24576
+        fwd = 5 * 2 * 5 * 12288
         bwd = 512 * 8 + 8 * 192 * 5 * 64 * 8
         assert ws == max(fwd, bwd)
         assert res == 0
-        s = msft._lib.msft_simulate(ctypes.c_void_p(h), None, None, None, None, None, None)
+        # one request: delta and beta (150*5*33 floats each, rounded up to 256 bytes),
+        # intensity and amplitude (400 floats, 400 complex), its forward workspace
+        def r256(b):
+            return -(-b // 256) * 256
+        assert per_req == 2 * r256(4 * 150 * 5 * 33) + r256(4 * 400) + r256(8 * 400) + fwd
+        s = msft._lib.msft_simulate(ctypes.c_void_p(h), None, None, None, None, None, 0, None)
         assert s == msft.MSFT_ERR_UNSUPPORTED
     finally:
         msft.msft_plan_destroy(h)
@@ -171,3 +176,26 @@ def test_status_strings():
         assert msft.msft_status_str(s)
     assert msft.msft_status_str(99) == "unknown status"
     assert msft.msft_pixel_block() == 128
+
+
+def test_binding_checks_buffers_before_the_call():
+    # The binding refuses buffers that do not match the plan (shape, dtype, device,
+    # layout) before any pointer reaches the library; nothing here touches a GPU.
+    import torch
+    g = msft.make_geometry(45.0, 60.0, 8, (6, 5, 4), (8.0, 8.0, 8.0))
+    h = msft.msft_plan(g, -1)
+    try:
+        d = torch.zeros((6, 5, 4))
+        I = torch.zeros(64)
+        ws = torch.zeros(1 << 20, dtype=torch.uint8)
+        with pytest.raises(ValueError, match="cuda"):
+            msft.msft_simulate(h, d, d, I, None, ws)
+        with pytest.raises(TypeError, match="float32"):
+            msft.msft_simulate(h, d.double(), d, I, None, ws)
+        with pytest.raises((TypeError, ValueError)):
+            msft.msft_batch_query([(h, d, d, torch.zeros(63), None)])
+        with pytest.raises(ValueError, match="unknown plan"):
+            msft.msft_simulate(12345, d, d, I, None, ws)
+    finally:
+        msft.msft_plan_destroy(h)
+

@@ -16,30 +16,35 @@ class Clock:
 
 
 class FakeExecutor:
-    """Launch of a batch takes the sum of its requests' durations; footprint and
-    duration (also the work estimate) from the request key."""
+    """A launch takes the modelled time of its items (blocks x per-block time);
+    memory and size of a request come from its key: key -> (io bytes, scratch bytes,
+    blocks, seconds per block)."""
 
-    def __init__(self, clock, foot, dur):
-        self.clock, self.foot, self.dur = clock, foot, dur
+    def __init__(self, clock, spec):
+        self.clock, self.spec = clock, spec
         self.launches = []
+        self.completed = []
 
-    def footprint(self, req):
-        return self.foot[req.key]
+    def describe(self, req):
+        req.io_bytes, req.ws_bytes, req.blocks, req.block_cost = self.spec[req.key][:4]
+        req.wave_blocks = self.spec[req.key][4] if len(self.spec[req.key]) > 4 else 1
 
-    def cost(self, req):
-        return self.dur[req.key]
-
-    def launch(self, batch):
-        h = {"end": self.clock() + sum(self.dur[r.key] for r in batch), "ids": [r.rid for r in batch]}
+    def launch(self, items):
+        dur = sum((b1 - b0) * r.block_cost for r, b0, b1 in items)
+        h = {"end": self.clock() + dur, "ids": [r.rid for r, _, _ in items],
+             "items": [(r.rid, b0, b1) for r, b0, b1 in items]}
         self.launches.append(h)
         return h
 
     def poll(self, h):
         return self.clock() >= h["end"]
 
-    def finish(self, h, batch):
-        for r in batch:
-            r.result = ("done", r.rid)
+    def finish(self, h, items):
+        pass
+
+    def complete(self, req):
+        req.result = ("done", req.rid)
+        self.completed.append(req.rid)
 
 
 def _drive(sched, clock, reqs, dt=0.001, horizon=100.0):
@@ -63,8 +68,8 @@ def _reqs(keys, arrivals):
 
 def test_budget_never_exceeded_and_all_complete():
     clock = Clock()
-    ex = FakeExecutor(clock, {"s": 10, "m": 30, "l": 60}, {"s": 0.01, "m": 0.03, "l": 0.06})
-    sched = Scheduler(ex, hbm_budget=100, max_inflight=3, max_batch=4, clock=clock)
+    ex = FakeExecutor(clock, {"s": (6, 4, 1, 0.01), "m": (20, 10, 3, 0.01), "l": (40, 20, 6, 0.01)})
+    sched = Scheduler(ex, hbm_budget=100, max_inflight=3, max_batch=4, clock=clock, quantum=0.02)
     keys = ["s", "m", "l", "m", "s", "l", "l", "s", "m", "s"] * 3
     arr = list(poisson_arrivals(len(keys), rate=50.0, seed=1))
     reqs = _reqs(keys, arr)
@@ -75,22 +80,24 @@ def test_budget_never_exceeded_and_all_complete():
     assert sched.used == 0
 
 
-def test_fifo_admission_order_and_batch_limit():
+def test_fifo_order_and_batch_limit_without_quantum():
     clock = Clock()
-    ex = FakeExecutor(clock, {"a": 1}, {"a": 0.05})
+    ex = FakeExecutor(clock, {"a": (1, 0, 5, 0.01)})
     sched = Scheduler(ex, hbm_budget=1000, max_inflight=2, max_batch=3, clock=clock)
     reqs = _reqs(["a"] * 11, [0.0] * 11)
     _drive(sched, clock, reqs)
     order = [rid for h in ex.launches for rid in h["ids"]]
     assert order == list(range(11))
     assert all(len(h["ids"]) <= 3 for h in ex.launches)
+    # nothing is sliced without a quantum
+    assert all(b0 == 0 and b1 == 5 for h in ex.launches for _, b0, b1 in h["items"])
 
 
 def test_arrivals_join_while_earlier_work_runs():
     # the second request arrives while the first launch is still running and is
     # admitted into a new launch before the first completes
     clock = Clock()
-    ex = FakeExecutor(clock, {"a": 1}, {"a": 0.2})
+    ex = FakeExecutor(clock, {"a": (1, 0, 1, 0.2)})
     sched = Scheduler(ex, hbm_budget=10, max_inflight=2, max_batch=8, clock=clock)
     r0, r1 = Request(0, 0.0, "a"), Request(1, 0.05, "a")
     _drive(sched, clock, [r0, r1])
@@ -100,7 +107,7 @@ def test_arrivals_join_while_earlier_work_runs():
 
 def test_waits_for_memory_then_runs():
     clock = Clock()
-    ex = FakeExecutor(clock, {"big": 80}, {"big": 0.1})
+    ex = FakeExecutor(clock, {"big": (60, 20, 1, 0.1)})
     sched = Scheduler(ex, hbm_budget=100, max_inflight=4, max_batch=4, clock=clock)
     reqs = _reqs(["big"] * 3, [0.0, 0.0, 0.0])
     _drive(sched, clock, reqs)
@@ -112,7 +119,7 @@ def test_waits_for_memory_then_runs():
 
 def test_oversize_request_refused_not_blocking():
     clock = Clock()
-    ex = FakeExecutor(clock, {"huge": 500, "s": 1}, {"huge": 1.0, "s": 0.01})
+    ex = FakeExecutor(clock, {"huge": (400, 100, 1, 1.0), "s": (1, 0, 1, 0.01)})
     sched = Scheduler(ex, hbm_budget=100, clock=clock)
     reqs = _reqs(["s", "huge", "s"], [0.0, 0.0, 0.0])
     _drive(sched, clock, reqs)
@@ -120,43 +127,66 @@ def test_oversize_request_refused_not_blocking():
     assert sorted(r.rid for r in sched.completed) == [0, 2]
 
 
-def test_work_quantum_keeps_expensive_requests_apart():
-    # launches group cheap requests up to the work limit; an expensive request gets a
-    # launch of its own (and is never split or skipped: FIFO still holds)
+def test_cheap_requests_grouped_up_to_the_quantum():
+    # cheap requests share launches up to the work limit, in arrival order
     clock = Clock()
-    ex = FakeExecutor(clock, {"s": 1, "l": 1}, {"s": 0.01, "l": 0.5})
+    ex = FakeExecutor(clock, {"s": (1, 1, 1, 0.01)})
     sched = Scheduler(ex, hbm_budget=1000, max_inflight=8, max_batch=24, clock=clock,
-                      max_batch_cost=0.045)
-    keys = ["s"] * 6 + ["l"] + ["s"] * 3
-    for r in _reqs(keys, [0.0] * len(keys)):
+                      quantum=0.045)
+    for r in _reqs(["s"] * 10, [0.0] * 10):
         sched.submit(r)
     sched.step()
-    assert [h["ids"] for h in ex.launches] == [[0, 1, 2, 3], [4, 5], [6], [7, 8, 9]]
+    assert [h["ids"] for h in ex.launches] == [[0, 1, 2, 3], [4, 5, 6, 7], [8, 9]]
 
 
-def test_one_large_runs_expensive_requests_in_order_and_lets_cheap_ones_pass():
+def test_expensive_requests_are_sliced_and_cheap_ones_pass_between_slices():
     clock = Clock()
-    ex = FakeExecutor(clock, {"s": 1, "l": 1}, {"s": 0.01, "l": 0.5})
-    sched = Scheduler(ex, hbm_budget=1000, max_inflight=4, max_batch=24, clock=clock,
-                      max_batch_cost=0.045, one_large=True)
-    keys = ["l", "l", "s", "s", "l", "s"]
-    for r in _reqs(keys, [0.0] * len(keys)):
+    # l: 10 blocks of 0.01 s = 0.1 s of work, quantum 0.03 s -> slices of 3 blocks
+    ex = FakeExecutor(clock, {"s": (1, 1, 1, 0.01), "l": (5, 2, 10, 0.01)})
+    sched = Scheduler(ex, hbm_budget=1000, max_inflight=2, max_batch=24, clock=clock,
+                      quantum=0.03)
+    reqs = _reqs(["l", "l"], [0.0, 0.0])
+    for r in reqs:
         sched.submit(r)
     sched.step()
-    # the first expensive request runs; the second waits, the cheap ones behind it start
-    assert [h["ids"] for h in ex.launches] == [[0], [2, 3], [5]]
-    assert [r.rid for r in sched.queue] == [1, 4]
-    clock.t = 0.6
+    # one launch slot stays free for cheap arrivals: one slice of the oldest request
+    assert [h["items"] for h in ex.launches] == [[(0, 0, 3)]]
+    cheap = Request(2, 0.0, "s")
+    sched.submit(cheap)
     sched.step()
-    assert [h["ids"] for h in ex.launches][3:] == [[1]]
-    clock.t = 1.2
+    assert ex.launches[-1]["items"] == [(2, 0, 1)]
+    _drive(sched, clock, [])
+    slices = [it for h in ex.launches for it in h["items"]]
+    # every block of each expensive request launched exactly once, oldest request first
+    for rid in (0, 1):
+        got = sorted((b0, b1) for r, b0, b1 in slices if r == rid)
+        assert got == [(0, 3), (3, 6), (6, 9), (9, 10)]
+    first1 = min(k for k, (r, _, _) in enumerate(slices) if r == 1)
+    last0 = max(k for k, (r, _, _) in enumerate(slices) if r == 0)
+    assert first1 > last0
+    assert cheap.done < reqs[0].done
+    assert all(r.done >= r.admitted for r in reqs) and sched.used == 0
+    assert sorted(ex.completed) == [0, 1, 2]
+
+
+def test_slices_of_one_request_charge_its_inputs_once():
+    clock = Clock()
+    ex = FakeExecutor(clock, {"l": (50, 10, 8, 0.01)})
+    sched = Scheduler(ex, hbm_budget=75, max_inflight=3, max_batch=4, clock=clock, quantum=0.02)
+    r = Request(0, 0.0, "l")
+    sched.submit(r)
     sched.step()
-    assert [h["ids"] for h in ex.launches][4:] == [[4]]
+    # inputs (50) once plus two slices' scratch (10 each) fit in 75; a third would not
+    assert sched.used == 70 and len(sched.inflight) == 2
+    _drive(sched, clock, [])
+    assert r.done > 0 and sched.used == 0
 
 
 def test_invalid_limits():
     with pytest.raises(ValueError):
         Scheduler(None, 10, max_inflight=0)
+    with pytest.raises(ValueError):
+        Scheduler(None, 10, quantum=0.0)
 
 
 def test_summary_percentiles():
@@ -167,3 +197,20 @@ def test_summary_percentiles():
     assert s["requests"] == 100
     assert math.isclose(s["p50_ms"], 50.0) and math.isclose(s["p99_ms"], 99.0)
     assert math.isclose(s["patterns_per_s"], 1000.0)
+
+
+def test_slices_are_whole_device_waves():
+    # 40 blocks, 4 run at once (one wave = 4 x 0.01 s): a 0.09 s quantum gives slices
+    # of two waves (8 blocks); a quantum below one wave still gives one whole wave
+    clock = Clock()
+    ex = FakeExecutor(clock, {"l": (5, 2, 40, 0.01, 4), "m": (5, 2, 10, 0.01, 4)})
+    sched = Scheduler(ex, hbm_budget=1000, max_inflight=2, max_batch=4, clock=clock, quantum=0.09)
+    sched.submit(Request(0, 0.0, "l"))
+    _drive(sched, clock, [])
+    sizes = [b1 - b0 for h in ex.launches for _, b0, b1 in h["items"]]
+    assert sizes == [8, 8, 8, 8, 8]
+    ex.launches.clear()
+    sched = Scheduler(ex, hbm_budget=1000, max_inflight=2, max_batch=4, clock=clock, quantum=0.015)
+    sched.submit(Request(1, clock.t, "m"))
+    _drive(sched, clock, [])
+    assert [b1 - b0 for h in ex.launches for _, b0, b1 in h["items"]] == [4, 4, 2]
