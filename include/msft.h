@@ -225,6 +225,24 @@ msft_status msft_simulate_batch(const msft_request* reqs, int32_t n, void* works
                                 size_t ws_bytes, void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under stream capture,
+ * serving loops, harnesses that forbid allocation): msft_simulate with its
+ * workspace in a fixed array of MSFT_NOALLOC_MAX_BYTES that the library keeps on
+ * each device it runs on, from the first call on that device until the process
+ * ends.  Same arguments, kernels and results (bit for bit) as msft_simulate
+ * without the workspace; the caller still owns delta, beta, intensity and
+ * amplitude.  The call itself allocates nothing.  Every call on one device
+ * shares that device's array: calls that overlap on one device (on different
+ * streams, or from different threads) race and must not be issued.  A plan
+ * whose workspace_bytes-sized forward scratch exceeds MSFT_NOALLOC_MAX_BYTES is
+ * refused with MSFT_ERR_UNSUPPORTED (for example 192^3 voxels in FP32); nothing is
+ * launched then.
+ */
+#define MSFT_NOALLOC_MAX_BYTES (64u << 20)
+msft_status msft_simulate_noalloc(msft_plan_t plan, const float* delta, const float* beta,
+                                  float* intensity, float* amplitude, void* stream);
+
+/*
  * Adjoint of the forward model: given the amplitudes A saved by msft_simulate
  * and g = dL/dI for a real loss L, write dL/d delta and dL/d beta (device
  * float32 [nx][ny][nz]).  With R_v = sum_p g_p conj(A_p) exp(-i q_p . r_v) the

@@ -21,7 +21,8 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wextra", "-Wno-unused-parameter"]
 
 SOURCES_HOST = ["geometry.cpp", "abi.cpp"]
-SOURCES_HIP = ["kernels.hip", "gauss.hip", "backward.hip", "render.hip", "detector.hip"]
+SOURCES_HIP = ["kernels.hip", "gauss.hip", "backward.hip", "render.hip", "detector.hip",
+               "noalloc.hip"]
 
 
 def _run(cmd, verbose):

@@ -655,6 +655,29 @@ msft_status msft_simulate(msft_plan_t plan, const float* delta, const float* bet
     return simulate_launch(plan, delta, beta, intensity, amplitude, workspace, stream);
 }
 
+msft_status msft_simulate_noalloc(msft_plan_t plan, const float* delta, const float* beta,
+                                  float* intensity, float* amplitude, void* stream)
+{
+    if (!plan) return fail(MSFT_ERR_INVALID, "plan is NULL");
+    if (plan->fwd_workspace > (size_t)MSFT_NOALLOC_MAX_BYTES) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf,
+                      "the plan's forward scratch is %zu bytes; the fixed scratch holds %zu",
+                      plan->fwd_workspace, (size_t)MSFT_NOALLOC_MAX_BYTES);
+        return fail(MSFT_ERR_UNSUPPORTED, buf);
+    }
+    msft_status st = check_runnable(plan);
+    if (st != MSFT_OK) return st;
+    if (!delta || !beta || !intensity)
+        return fail(MSFT_ERR_INVALID, "delta, beta and intensity must be non-NULL");
+    DeviceScope ds(plan->device);
+    if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice");
+    void* scratch = nullptr;
+    const int e = static_scratch(plan->device, &scratch);
+    if (e) return hip_fail((hipError_t)e, "fixed scratch address");
+    return simulate_launch(plan, delta, beta, intensity, amplitude, scratch, stream);
+}
+
 msft_status msft_simulate_scan(msft_plan_t plan, const float* delta, const float* beta, void* workspace,
                                size_t ws_bytes, void* stream)
 {

@@ -290,6 +290,9 @@ int launch_detect_ideal(const IdealArgs& a, const float* intensity, float* count
 int launch_render_volume(const VolArgs& a, const float* sd, const float* sb, float* delta,
                          float* beta, void* stream);
 int launch_forward_batch(int precision, const BatchArgs& b, void* stream);
+// Device address of the fixed scratch array on `device` (which must be current),
+// looked up on the first call per device; returns a HIP error code.
+int static_scratch(int device, void** ptr);
 
 }  // namespace msft
 

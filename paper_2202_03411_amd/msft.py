@@ -22,6 +22,7 @@ MSFT_FP32, MSFT_BF16X3, MSFT_BF16 = 0, 1, 2
 MSFT_STRENGTH_MSFT, MSFT_STRENGTH_BORN, MSFT_STRENGTH_DENSITY = 0, 1, 2
 MSFT_ALLOW_ALIAS = 1
 MSFT_DETECTOR_UNIFORM_Q = 2
+MSFT_NOALLOC_MAX_BYTES = 64 << 20
 DETECTORS = {"flat": 0, "uniform_q": MSFT_DETECTOR_UNIFORM_Q}
 
 PRECISIONS = {"fp32": MSFT_FP32, "bf16x3": MSFT_BF16X3, "bf16": MSFT_BF16}
@@ -94,6 +95,7 @@ def _load():
     lib.msft_simulate.argtypes = [VP, VP, VP, VP, VP, VP, S, VP]
     lib.msft_simulate_scan.argtypes = [VP, VP, VP, VP, S, VP]
     lib.msft_simulate_contract.argtypes = [VP, VP, S, VP, VP, VP]
+    lib.msft_simulate_noalloc.argtypes = [VP, VP, VP, VP, VP, VP]
     lib.msft_pixel_block.argtypes = []
     lib.msft_batch_query.argtypes = [P(msft_request), I32, P(S)]
     lib.msft_simulate_batch.argtypes = [P(msft_request), I32, VP, S, VP]
@@ -111,7 +113,7 @@ def _load():
     lib.msft_last_error.restype = ctypes.c_char_p
     for name in ("msft_plan", "msft_plan_qlist", "msft_plan_destroy", "msft_plan_query",
                  "msft_plan_qmap", "msft_plan_grid", "msft_simulate", "msft_simulate_scan",
-                 "msft_simulate_contract", "msft_pixel_block", "msft_batch_query", "msft_simulate_batch",
+                 "msft_simulate_contract", "msft_simulate_noalloc", "msft_pixel_block", "msft_batch_query", "msft_simulate_batch",
                  "msft_backward", "msft_render_sh", "msft_render_sh_query", "msft_render_sh_backward",
                  "msft_render_ellipsoid", "msft_render_volume", "msft_detect_ideal"):
         getattr(lib, name).restype = ctypes.c_int
@@ -124,7 +126,7 @@ LIBRARY_PATH = _build.LIB
 # every symbol the C header declares
 EXPORTS = ("msft_plan", "msft_plan_qlist", "msft_plan_destroy", "msft_plan_query", "msft_plan_qmap",
            "msft_plan_grid", "msft_simulate", "msft_simulate_scan", "msft_simulate_contract",
-           "msft_pixel_block",
+           "msft_simulate_noalloc", "msft_pixel_block",
            "msft_batch_query",
            "msft_simulate_batch", "msft_backward", "msft_render_sh", "msft_render_sh_query",
            "msft_render_sh_backward", "msft_render_ellipsoid", "msft_render_volume",
@@ -293,6 +295,15 @@ def msft_simulate_contract(plan, workspace, intensity, amplitude, stream=None) -
     _check(_lib.msft_simulate_contract(ctypes.c_void_p(plan), _ptr(workspace), nbytes,
                                        _ptr(intensity), _ptr(amplitude), _stream(stream)),
            "msft_simulate_contract")
+
+
+def msft_simulate_noalloc(plan, delta, beta, intensity, amplitude, stream=None) -> None:
+    """msft_simulate with the library's fixed per-device scratch (no workspace, no
+    allocation in the call); calls that overlap on one device race."""
+    _check_io(plan, delta, beta, intensity, amplitude)
+    _check(_lib.msft_simulate_noalloc(ctypes.c_void_p(plan), _ptr(delta), _ptr(beta),
+                                      _ptr(intensity), _ptr(amplitude), _stream(stream)),
+           "msft_simulate_noalloc")
 
 
 def msft_pixel_block() -> int:

@@ -199,3 +199,25 @@ def test_binding_checks_buffers_before_the_call():
     finally:
         msft.msft_plan_destroy(h)
 
+
+def test_noalloc_refuses_plans_beyond_its_fixed_scratch():
+    # 176^3 in FP32: 6 * 6 * 176 three-plane tiles of 12 KiB = 74.25 MiB of forward
+    # scratch, more than the fixed 64 MiB; refused before anything else is looked at
+    g = msft.make_geometry(45.0, 30.0, 16, (176, 176, 176), (4.0, 4.0, 4.0))
+    h = msft.msft_plan(g, -1)
+    try:
+        s = msft._lib.msft_simulate_noalloc(ctypes.c_void_p(h), None, None, None, None, None)
+        assert s == msft.MSFT_ERR_UNSUPPORTED
+        assert "fixed scratch" in msft.msft_last_error()
+    finally:
+        msft.msft_plan_destroy(h)
+    # 128^3 fits (4 * 4 * 128 tiles of 12 KiB = 24 MiB): a host-only plan is then
+    # refused only because it has no device
+    g = msft.make_geometry(45.0, 30.0, 16, (128, 128, 128), (4.0, 4.0, 4.0))
+    h = msft.msft_plan(g, -1)
+    try:
+        s = msft._lib.msft_simulate_noalloc(ctypes.c_void_p(h), None, None, None, None, None)
+        assert s == msft.MSFT_ERR_UNSUPPORTED
+        assert "host-only" in msft.msft_last_error()
+    finally:
+        msft.msft_plan_destroy(h)
