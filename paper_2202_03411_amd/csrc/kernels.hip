@@ -4,7 +4,7 @@
 //  scan_kernel   column scan of the incident field along z and the effective
 //                strength w = dV (n^2 - 1) T (Eqs. (6)-(9)), written in the
 //                contraction's LDS tile layout.
-//  fwd_block     the x-sum as a real-ified complex MFMA contraction (BF16
+//  fwd_pair_*    the x-sum as a real-ified complex MFMA contraction (BF16
 //                precisions) with the y/z phase-weighted reduction and |A|^2
 //                fused behind it.
 //  sep_*         the two stages of the separable (uniform-q) detector and its
@@ -18,6 +18,7 @@ namespace msft {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // Pixel of wave tile wt held by lane half h, slot m (0..7) of the MFMA output:
 // accumulator rows 8j + 4h + u, u = 0..3, are (pixel 4j + 2h + u/2, re|im).
@@ -201,20 +202,26 @@ int launch_sep_twiddles(int precision, const Dims& d, const SepDims& sd, const d
 // ---------------------------------------------------------------------------
 // Column scan (Eq. (8)) and effective strength (Eqs. (6), (9)).
 //
-// Workgroup (xc, y) owns the 64 columns x = xc*64 + lane at one y; wave k owns
-// z block k (32 slices), looping by SCAN_WAVES when there are more blocks.
-// Phase 1: each lane reads its column's 32 slices (two 128-byte runs, delta and
-// beta) and sums them; the block totals go through LDS and every lane forms the
-// exclusive prefix of the blocks before its own (the carry).  Phase 2: the lane
-// walks its slices in beam order, keeping the running exclusive sum
-// S = sum_{s'<s} (beta + i delta), and writes
+// Workgroup (x chunk xc of 64 columns, y), 8 waves, four z blocks of 32 slices
+// per round: wave w takes z block zb0 + w / 2 of the columns 32 (w & 1) .. + 31.
+// Lanes run along z: the 8 lanes of a group hold 4 consecutive slices each of
+// one column (together one 128-byte line of delta and one of beta), and a lane
+// holds 4 columns 8 apart, so every load instruction reads whole lines.  The
+// exclusive prefix S = sum_{s'<s} (beta + i delta) of a slice is the carry of
+// the earlier rounds, plus the totals of the earlier z blocks of the round
+// (through LDS), plus an inclusive shuffle scan over the 8 lanes of the group,
+// plus the lane's own earlier slices.  Then
 //   T = exp(-k0 dz (S_beta + i S_delta)),   w = dV chi T,
 //   chi = n^2 - 1 = delta (delta - 2) - beta^2 + 2 i beta (1 - delta)
-// (chi written without the cancelling "+1 -1") straight into the tile rows:
-// the 64 lanes of a row are 64 consecutive x, so each row store is one
-// contiguous 256-byte (FP32) or 2 x 128-byte (BF16 hi, lo) segment.
+// (chi written without the cancelling "+1 -1") goes into an LDS copy of the W
+// tiles in their final layout, which the workgroup writes out with whole
+// 16-byte stores (each tile is one contiguous run in the workspace).
 // ---------------------------------------------------------------------------
-constexpr int SCAN_WAVES = 8;
+#ifndef MSFT_SCAN_TRIVIAL
+#define MSFT_SCAN_TRIVIAL 0
+#endif
+constexpr int SCAN_THREADS = 512;
+constexpr int SCAN_ZROUND = 4;   // z blocks per round, two waves each
 
 template <int PREC>
 __device__ __forceinline__ void store_w(uint8_t* tile, int lane, int zl, float wr, float wi)
@@ -246,92 +253,137 @@ __device__ __forceinline__ void store_w_g3(uint8_t* tile, int xl, int zl, float 
 }
 
 template <int PREC, bool G3>
-__global__ __launch_bounds__(64 * SCAN_WAVES) void scan_kernel(ScanArgs a)
+__global__ __launch_bounds__(SCAN_THREADS) void scan_kernel(ScanArgs a)
 {
-    __shared__ float tot_b[SCAN_WAVES][64], tot_d[SCAN_WAVES][64];
+    // one z block of the workgroup's 64 columns: one W tile, or two Gauss tiles
+    constexpr int STAGE_BYTES = G3 ? 2 * G3_TILE_BYTES : TILE_BYTES;
+    constexpr int STAGE_F4 = SCAN_ZROUND * STAGE_BYTES / 16;
+    constexpr int TILE_F4 = (G3 ? G3_TILE_BYTES : TILE_BYTES) / 16;
+    static_assert(STAGE_F4 % SCAN_THREADS == 0, "the staged tiles are copied in whole pieces");
+    __shared__ float tot[2][SCAN_ZROUND][XC];   // block totals of beta and delta per column
+    __shared__ __attribute__((aligned(16))) uint8_t stage[SCAN_ZROUND * STAGE_BYTES];
     const int xc = blockIdx.x, y = blockIdx.y;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int x = xc * XC + lane;
-    const bool xin = x < a.nx;
-    const size_t col = ((size_t)x * a.ny + y) * a.nz;
-    float carry_b = 0.0f, carry_d = 0.0f;   // sum over all earlier rounds
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int half = wave & 1, zr = wave >> 1;
+    const int g = lane & 7, cc = lane >> 3;
+    const bool vec = (a.nz & 3) == 0;
+    float carry_b[4], carry_d[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) carry_b[i] = carry_d[i] = 0.0f;
 
-    for (int zb0 = 0; zb0 < a.nzb; zb0 += SCAN_WAVES) {
-        const int zb = zb0 + wave;
+    for (int zb0 = 0; zb0 < a.nzb; zb0 += SCAN_ZROUND) {
+        const int zb = zb0 + zr;
         const bool active = zb < a.nzb;
-        const int z0 = zb * ZB;
-        const int nzl = active ? min(ZB, a.nz - z0) : 0;   // slices of this block inside the grid
-        float d[ZB], b[ZB];
-        if (xin && nzl == ZB && (a.nz & 3) == 0) {
+        const int z0 = zb * ZB + 4 * g;
+        float d[4][4], b[4][4], sb[4], sd[4], ib[4], id[4];
 #pragma unroll
-            for (int k = 0; k < ZB / 4; ++k) {
-                const float4 dv = ((const float4*)(a.delta + col + z0))[k];
-                const float4 bv = ((const float4*)(a.beta + col + z0))[k];
-                d[4 * k] = dv.x; d[4 * k + 1] = dv.y; d[4 * k + 2] = dv.z; d[4 * k + 3] = dv.w;
-                b[4 * k] = bv.x; b[4 * k + 1] = bv.y; b[4 * k + 2] = bv.z; b[4 * k + 3] = bv.w;
-            }
-        } else {
-#pragma unroll
-            for (int k = 0; k < ZB; ++k) {
-                const bool in = xin && k < nzl;
-                d[k] = in ? a.delta[col + z0 + k] : 0.0f;
-                b[k] = in ? a.beta[col + z0 + k] : 0.0f;
-            }
-        }
-        float sb = 0.0f, sd = 0.0f;
-#pragma unroll
-        for (int k = 0; k < ZB; ++k) {
-            sb += b[k];
-            sd += d[k];
-        }
-        tot_b[wave][lane] = sb;
-        tot_d[wave][lane] = sd;
-        __syncthreads();
-        float Sb = carry_b, Sd = carry_d;
-        for (int k = 0; k < wave; ++k) {
-            Sb += tot_b[k][lane];
-            Sd += tot_d[k][lane];
-        }
-        float rb = 0.0f, rd = 0.0f;
-        for (int k = 0; k < SCAN_WAVES && zb0 + k < a.nzb; ++k) {
-            rb += tot_b[k][lane];
-            rd += tot_d[k][lane];
-        }
-        __syncthreads();
-        carry_b += rb;
-        carry_d += rd;
-        if (!active) continue;
-
-        // Gauss tiles hold G3_XC x: the lane's x chunk is 2 xc + lane / 32 (none past nxc3)
-        const int xc3 = 2 * xc + (lane >> 5);
-        if (G3 && xc3 >= a.nxc3) continue;
-        uint8_t* tile = G3 ? a.wtiles + ((size_t)(xc3 * a.nzb + zb) * a.ny + y) * G3_TILE_BYTES
-                           : a.wtiles + ((size_t)(xc * a.nzb + zb) * a.ny + y) * TILE_BYTES;
-#pragma unroll
-        for (int k = 0; k < ZB; ++k) {
-            float wr, wi;
-            if (a.strength == MSFT_STRENGTH_DENSITY) {
-                wr = a.dV * d[k];
-                wi = a.dV * b[k];
+        for (int i = 0; i < 4; ++i) {
+            const int x = xc * XC + half * 32 + cc + 8 * i;
+            const size_t col = ((size_t)x * a.ny + y) * a.nz;
+            if (active && x < a.nx && vec && z0 + 4 <= a.nz) {
+                const float4 dv = *(const float4*)(a.delta + col + z0);
+                const float4 bv = *(const float4*)(a.beta + col + z0);
+                d[i][0] = dv.x; d[i][1] = dv.y; d[i][2] = dv.z; d[i][3] = dv.w;
+                b[i][0] = bv.x; b[i][1] = bv.y; b[i][2] = bv.z; b[i][3] = bv.w;
             } else {
-                const float chr = d[k] * (d[k] - 2.0f) - b[k] * b[k];
-                const float chi = 2.0f * b[k] * (1.0f - d[k]);
-                float tr = 1.0f, ti = 0.0f;
-                if (a.strength == MSFT_STRENGTH_MSFT) {
-                    const float mag = expf(-a.k0dz * Sb);
-                    float sn, cs;
-                    sincosf(-a.k0dz * Sd, &sn, &cs);
-                    tr = mag * cs;
-                    ti = mag * sn;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const bool in = active && x < a.nx && z0 + k < a.nz;
+                    d[i][k] = in ? a.delta[col + z0 + k] : 0.0f;
+                    b[i][k] = in ? a.beta[col + z0 + k] : 0.0f;
                 }
-                wr = a.dV * (chr * tr - chi * ti);
-                wi = a.dV * (chr * ti + chi * tr);
             }
-            if (G3) store_w_g3(tile, lane & 31, k, wr, wi);
-            else store_w<PREC>(tile, lane, k, wr, wi);
-            Sb += b[k];
-            Sd += d[k];
+            sb[i] = (b[i][0] + b[i][1]) + (b[i][2] + b[i][3]);
+            sd[i] = (d[i][0] + d[i][1]) + (d[i][2] + d[i][3]);
+            // inclusive scan over the 8 lanes (z segments) of the column's group
+            ib[i] = sb[i];
+            id[i] = sd[i];
+#pragma unroll
+            for (int off = 1; off < 8; off <<= 1) {
+                const float tb = __shfl_up(ib[i], off, 8), td = __shfl_up(id[i], off, 8);
+                if (g >= off) {
+                    ib[i] += tb;
+                    id[i] += td;
+                }
+            }
+            if (g == 7) {
+                tot[0][zr][half * 32 + cc + 8 * i] = ib[i];
+                tot[1][zr][half * 32 + cc + 8 * i] = id[i];
+            }
         }
+        __syncthreads();
+        float pb[4], pd[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int xl = half * 32 + cc + 8 * i;
+            float eb = carry_b[i], ed = carry_d[i];
+            for (int k = 0; k < zr; ++k) {
+                eb += tot[0][k][xl];
+                ed += tot[1][k][xl];
+            }
+            pb[i] = eb + (ib[i] - sb[i]);
+            pd[i] = ed + (id[i] - sd[i]);
+            for (int k = zr; k < SCAN_ZROUND && zb0 + k < a.nzb; ++k) {
+                eb += tot[0][k][xl];
+                ed += tot[1][k][xl];
+            }
+            carry_b[i] = eb;
+            carry_d[i] = ed;
+        }
+        if (active) {
+            uint8_t* st = stage + zr * STAGE_BYTES + (G3 ? half * G3_TILE_BYTES : 0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int xl = cc + 8 * i;   // column within the half
+                float Sb = pb[i], Sd = pd[i];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    float wr, wi;
+                    if (MSFT_SCAN_TRIVIAL || a.strength == MSFT_STRENGTH_DENSITY) {
+                        wr = a.dV * d[i][k] + (MSFT_SCAN_TRIVIAL ? Sb : 0.0f);
+                        wi = a.dV * b[i][k] + (MSFT_SCAN_TRIVIAL ? Sd : 0.0f);
+                    } else {
+                        const float chr = d[i][k] * (d[i][k] - 2.0f) - b[i][k] * b[i][k];
+                        const float chi = 2.0f * b[i][k] * (1.0f - d[i][k]);
+                        float tr = 1.0f, ti = 0.0f;
+                        if (a.strength == MSFT_STRENGTH_MSFT) {
+                            const float mag = expf(-a.k0dz * Sb);
+                            float sn, cs;
+                            sincosf(-a.k0dz * Sd, &sn, &cs);
+                            tr = mag * cs;
+                            ti = mag * sn;
+                        }
+                        wr = a.dV * (chr * tr - chi * ti);
+                        wi = a.dV * (chr * ti + chi * tr);
+                    }
+                    if (G3) store_w_g3(st, xl, 4 * g + k, wr, wi);
+                    else store_w<PREC>(st, half * 32 + xl, 4 * g + k, wr, wi);
+                    Sb += b[i][k];
+                    Sd += d[i][k];
+                }
+            }
+        }
+        __syncthreads();
+        // the round's tiles, LDS -> workspace
+#pragma unroll
+        for (int u = 0; u < STAGE_F4 / SCAN_THREADS; ++u) {
+            const int q = u * SCAN_THREADS + tid;
+            const int tt = q / TILE_F4, off = q - tt * TILE_F4;
+            const int zk = G3 ? tt >> 1 : tt;
+            const int zbo = zb0 + zk;
+            if (zbo < a.nzb) {
+                if (G3) {
+                    const int xc3 = 2 * xc + (tt & 1);
+                    if (xc3 < a.nxc3)
+                        ((uint4*)(a.wtiles + ((size_t)(xc3 * a.nzb + zbo) * a.ny + y) * G3_TILE_BYTES))[off] =
+                            ((const uint4*)stage)[q];
+                } else {
+                    ((uint4*)(a.wtiles + ((size_t)(xc * a.nzb + zbo) * a.ny + y) * TILE_BYTES))[off] =
+                        ((const uint4*)stage)[q];
+                }
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -339,28 +391,27 @@ int launch_scan(int precision, const ScanArgs& a, void* stream)
 {
     hipStream_t s = (hipStream_t)stream;
     dim3 grid(a.nxc, a.ny);
-    const int waves = a.nzb < SCAN_WAVES ? a.nzb : SCAN_WAVES;
     if (precision == MSFT_FP32 && a.g3)
-        hipLaunchKernelGGL((scan_kernel<MSFT_FP32, true>), grid, dim3(64 * waves), 0, s, a);
+        hipLaunchKernelGGL((scan_kernel<MSFT_FP32, true>), grid, dim3(SCAN_THREADS), 0, s, a);
     else if (precision == MSFT_FP32)
-        hipLaunchKernelGGL((scan_kernel<MSFT_FP32, false>), grid, dim3(64 * waves), 0, s, a);
+        hipLaunchKernelGGL((scan_kernel<MSFT_FP32, false>), grid, dim3(SCAN_THREADS), 0, s, a);
     else
-        hipLaunchKernelGGL((scan_kernel<MSFT_BF16X3, false>), grid, dim3(64 * waves), 0, s, a);
+        hipLaunchKernelGGL((scan_kernel<MSFT_BF16X3, false>), grid, dim3(SCAN_THREADS), 0, s, a);
     return (int)hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // Forward contraction for one pixel block (BLOCK_PIX pixels, one workgroup).
 //
-//   for each x chunk xc:     A operand (Tx of the wave's 16 pixels) -> registers
+//   for each x chunk xc:     A operand (Tx of a wave tile's 16 pixels) -> registers
 //     for each z block zb:   G = 0
 //       for each y:          C = A . W(xc, zb, y)           (MFMA, K = 2 * 64)
 //                            G += exp(-i q_y y) C           (per pixel, lane = z)
 //       acc += exp(-i q_z z) G
 //   A_p = sum over the 32 z lanes of acc;  I_p = |A_p|^2
 //
-// W tiles stream through a double-buffered LDS ring shared by the 8 waves.  The
-// order of every sum depends only on the plan, never on the launch.
+// W tiles stream through a double-buffered LDS ring shared by the workgroup's
+// waves.  The order of every sum depends only on the plan, never on the launch.
 // ---------------------------------------------------------------------------
 // C += A . B for one W tile: the wave's A operand (registers) times the tile's
 // column `col` of lane half h (LDS row `row`), over the first `nx` x values.
@@ -472,175 +523,235 @@ __device__ __forceinline__ void rotate_add(float* G, const f32x16& C, const f32x
     }
 }
 
-// All z blocks of one x chunk; t is the next tile, k the next pipeline stage.
-// Two tiles (y, y + 1) per stage in a double-buffered ring of 2 x 2 tiles, so one
-// barrier serves two tiles, each wave runs two independent MFMA chains, and the
-// first tile's Ty rotation can issue under the second chain.  A lone last tile
-// (odd ny) is paired with whatever tile follows and its partner's rotation is
-// scaled by 0 (a branch there measured slower).
-// FULL: the chunk holds XC x values, decided per chunk, which keeps the tile loop
-// free of branches (measured faster).
-template <int PREC, bool FULL>
-__device__ __forceinline__ void fwd_chunk(const FwdArgs& a, int64_t wt, int64_t ntiles, const uint4* gw,
-                                          uint8_t* lds, int xlen, const f32x4* Af, const bf16x8* Ahi,
-                                          const bf16x8* Alo, int64_t& t, int& k, float* acc)
-{
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int h = lane >> 5, col = lane & 31;
-    for (int zb = 0; zb < a.nzb; ++zb) {
-        float G[16];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) G[q] = 0.0f;
-        const f32x4* tzp = (const f32x4*)(a.tz + 2 * ((((wt * a.nzb + zb) * 2 + h) * ZB + col) * 8));
-        for (int y = 0; y < a.ny; y += 2) {
-            const int cnt = min(2, a.ny - y);
-            const int64_t tn = t + cnt;
-            const bool has_next = tn < ntiles;
-            uint4 n0, n1, n2, n3;
-            if (has_next) {
-                const int64_t tn1 = min(tn + 1, ntiles - 1);
-                n0 = gw[tn * (TILE_BYTES / 16) + tid];
-                n1 = gw[tn * (TILE_BYTES / 16) + 512 + tid];
-                n2 = gw[tn1 * (TILE_BYTES / 16) + tid];
-                n3 = gw[tn1 * (TILE_BYTES / 16) + 512 + tid];
-            }
-            const f32x4* typ0 = (const f32x4*)(a.ty + 2 * ((wt * a.ny + y) * WAVE_PIX + h * 8));
-            const f32x4* typ1 = (const f32x4*)(a.ty + 2 * ((wt * a.ny + y + cnt - 1) * WAVE_PIX + h * 8));
-            const float s1 = cnt == 2 ? 1.0f : 0.0f;
-            const f32x4 ty0[4] = {typ0[0], typ0[1], typ0[2], typ0[3]};
-            const f32x4 ty1[4] = {typ1[0] * s1, typ1[1] * s1, typ1[2] * s1, typ1[3] * s1};
+// ---------------------------------------------------------------------------
+// The flat detector's BF16 contraction, two wave tiles per wave.  A workgroup of
+// PW_WAVES waves takes one pixel block; wave v owns the wave tiles wt0 = 8 block +
+// 2 v and wt0 + 1 (32 pixels, two MFMA row tiles) and keeps both A operands of an
+// x chunk in registers, so each B fragment read from LDS feeds six MFMAs instead of
+// three.  Two workgroups share a CU (256 registers per lane), so that one
+// workgroup's barrier and Ty rotation run under the other's matrix work.  Each slot
+// of a two-slot LDS ring holds one W tile and the Ty rows of the block's 8 wave
+// tiles at that tile's y; the next slot is filled by direct global -> LDS loads
+// issued at the start of each stage, under the stage's MFMA chain.  The per-lane
+// sums over z blocks live in LDS.  Measured against one workgroup of 8 waves with
+// one wave tile each (128³ / 512², BF16 split): 7.33 ms against 8.29; a third
+// ring slot with the z-lane sums taken per z block measured 7.66 ms.
+// ---------------------------------------------------------------------------
+constexpr int PW_WAVES = 4;
+constexpr int PW_THREADS = 64 * PW_WAVES;
+constexpr int PW_COPY = (TILE_BYTES / 16) / PW_THREADS;   // 16-byte pieces per thread per W tile
+constexpr int PW_TY_BYTES = WAVES * WAVE_PIX * 8;         // Ty of a block's wave tiles at one y
+constexpr int PW_SLOT = TILE_BYTES + PW_TY_BYTES;
+static_assert(PW_COPY * PW_THREADS == TILE_BYTES / 16, "a tile is copied in whole pieces");
+static_assert(2 * PW_WAVES == WAVES && PW_TY_BYTES == 64 * 16, "one wave gathers the Ty rows");
+// s_waitcnt immediates (gfx9 encoding: vmcnt in bits 3:0 and 15:14, expcnt 6:4,
+// lgkmcnt 11:8): wait until at most n vector-memory operations are outstanding
+constexpr int waitcnt_vm(int n) { return (n & 15) | (7 << 4) | (15 << 8) | ((n >> 4) << 14); }
 
-            const uint8_t* row = lds + (size_t)(k & 1) * 2 * TILE_BYTES + (h * ZB + col) * ROW_BYTES;
-            const f32x16 C0 = tile_product<PREC, FULL>(row, col, xlen, Af, Ahi, Alo);
-            const f32x16 C1 = tile_product<PREC, FULL>(row + TILE_BYTES, col, xlen, Af, Ahi, Alo);
-            rotate_add(G, C0, ty0);
-            rotate_add(G, C1, ty1);
-            if (has_next) {
-                uint4* nb = (uint4*)(lds + (size_t)((k + 1) & 1) * 2 * TILE_BYTES);
-                nb[tid] = n0;
-                nb[tid + 512] = n1;
-                nb[1024 + tid] = n2;
-                nb[1024 + tid + 512] = n3;
-            }
-            __syncthreads();
-            t += cnt;
-            ++k;
-        }
-        // acc[m] += Tz[m] * G[m]
+// One 16-byte piece per lane from global memory straight into LDS: lane l of the
+// wave writes dst_wave + 16 l (dst_wave uniform over the wave).  Written as inline
+// assembly so that the compiler does not wait for it before every read of the other
+// ring slots (it cannot tell the slots apart); it produces no register result, and
+// the caller waits for the memory counter before the barrier that publishes a slot.
+// M0 is set inside the block; the compiler reserves M0 and uses it in none of the
+// kernels that call this (their code has no other M0 access), so the clobber is
+// declared for the reader only and its "reserved register" warning is silenced.
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
+__device__ __forceinline__ void lds_dma16(const void* src, uint8_t* dst_wave)
+{
+    const uint32_t m0 = __builtin_amdgcn_readfirstlane(
+        (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t*)dst_wave);
+    asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
+                 :
+                 : "v"(src), "s"(m0)
+                 : "memory", "m0");
+}
+#pragma clang diagnostic pop
+
+// Slot contents for tile tn: the W tile and, from wave 0, the block's Ty rows at
+// y(tn).  Wave 0 issues PW_COPY + 1 loads, the others PW_COPY.
+__device__ __forceinline__ void pw_fill(const FwdArgs& a, int64_t wtb, int64_t tn, const u32x4* gw,
+                                        uint8_t* slot)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const f32x4 v = tzp[q];
+    for (int c = 0; c < PW_COPY; ++c)
+        lds_dma16(gw + tn * (TILE_BYTES / 16) + c * PW_THREADS + wave * 64 + lane,
+                  slot + (c * PW_THREADS + wave * 64) * 16);
+    if (wave == 0) {
+        const int64_t yn = tn % a.ny;
+        lds_dma16(a.ty + 2 * ((wtb + (lane >> 3)) * a.ny + yn) * WAVE_PIX + (lane & 7) * 4, slot + TILE_BYTES);
+    }
+}
+
+// C0, C1 = the wave's two row tiles against one W tile; each B fragment read once.
+template <int PREC, bool FULL>
+__device__ __forceinline__ void tile_product2(const uint8_t* row, int col, int xlen, const bf16x8* Ah0,
+                                              const bf16x8* Al0, const bf16x8* Ah1, const bf16x8* Al1,
+                                              f32x16& C0, f32x16& C1)
+{
+    const int sw = col & 15;
+    C0 = f32x16{};
+    C1 = f32x16{};
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int m = 2 * q + u;
-                const float tr = v[2 * u], ti = v[2 * u + 1];
-                acc[2 * m] += tr * G[2 * m] - ti * G[2 * m + 1];
-                acc[2 * m + 1] += tr * G[2 * m + 1] + ti * G[2 * m];
+    for (int s = 0; s < XC / 8; ++s) {
+        if (FULL || 8 * s < xlen) {
+            const bf16x8 bh = *(const bf16x8*)(row + ((s ^ sw) << 4));
+            C0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah0[s], bh, C0, 0, 0, 0);
+            C1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah1[s], bh, C1, 0, 0, 0);
+            if (PREC == MSFT_BF16X3) {
+                const bf16x8 bl = *(const bf16x8*)(row + (((8 + s) ^ sw) << 4));
+                C0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah0[s], bl, C0, 0, 0, 0);
+                C1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah1[s], bl, C1, 0, 0, 0);
+                C0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al0[s], bh, C0, 0, 0, 0);
+                C1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al1[s], bh, C1, 0, 0, 0);
             }
         }
     }
 }
 
-// One pixel block (BLOCK_PIX pixels) of the contraction.
-template <int PREC>
-__device__ __forceinline__ void fwd_block(const FwdArgs& a, int64_t block, uint8_t* lds)
+// All z blocks of one x chunk; tile t sits in slot t & 1.  accl: the lane's 32 sums
+// in LDS, stride 64 floats ([row tile][16]).
+template <int PREC, bool FULL>
+__device__ __forceinline__ void chunk_pair(const FwdArgs& a, int64_t wt0, int64_t ntiles, const u32x4* gw,
+                                           uint8_t* lds, int xlen, const bf16x8* Ah0, const bf16x8* Al0,
+                                           const bf16x8* Ah1, const bf16x8* Al1, int64_t& t, float* accl)
 {
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int64_t wt = block * WAVES + wave;
-    const int64_t ntiles = (int64_t)a.nxc * a.nzb * a.ny;
-    const uint4* gw = (const uint4*)a.wtiles;
-
-    // first stage: tiles 0 and 1 -> LDS buffer 0
-    {
-        const uint4 r0 = gw[tid], r1 = gw[tid + 512];
-        ((uint4*)lds)[tid] = r0;
-        ((uint4*)lds)[tid + 512] = r1;
-        const int64_t t1 = ntiles > 1 ? 1 : 0;
-        const uint4 r2 = gw[t1 * (TILE_BYTES / 16) + tid], r3 = gw[t1 * (TILE_BYTES / 16) + 512 + tid];
-        ((uint4*)lds)[1024 + tid] = r2;
-        ((uint4*)lds)[1024 + tid + 512] = r3;
-    }
-    __syncthreads();
-
-    float acc[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) acc[q] = 0.0f;
-
-    int64_t t = 0;
-    int k = 0;
-    for (int xc = 0; xc < a.nxc; ++xc) {
-        const int xlen = min(XC, a.x_pad - xc * XC);
-        f32x4 Af[16];
-        bf16x8 Ahi[8], Alo[8];
-        load_a<PREC>(a.txa + (size_t)(wt * a.nxc + xc) * TILE_BYTES, lane, Af, Ahi, Alo);
-        // Wait for the A operand here, once per chunk.  The memory counter is in
-        // order, so without this the waits the compiler places for A inside the
-        // tile loop would also wait for the next tile's prefetch, mid-chain.
-        __builtin_amdgcn_s_waitcnt(0);
-        if (xlen == XC)
-            fwd_chunk<PREC, true>(a, wt, ntiles, gw, lds, xlen, Af, Ahi, Alo, t, k, acc);
-        else
-            fwd_chunk<PREC, false>(a, wt, ntiles, gw, lds, xlen, Af, Ahi, Alo, t, k, acc);
-    }
     const int h = lane >> 5, col = lane & 31;
-
-    // sum over the 32 z lanes of each half (fixed butterfly order)
+    const int64_t wtb = wt0 - 2 * wave;
+    for (int zb = 0; zb < a.nzb; ++zb) {
+        float G0[16], G1[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        float v = acc[q];
-        v += __shfl_xor(v, 16, 32);
-        v += __shfl_xor(v, 8, 32);
-        v += __shfl_xor(v, 4, 32);
-        v += __shfl_xor(v, 2, 32);
-        v += __shfl_xor(v, 1, 32);
-        acc[q] = v;
-    }
-    if (col == 0) {
+        for (int q = 0; q < 16; ++q) G0[q] = G1[q] = 0.0f;
+        for (int y = 0; y < a.ny; ++y, ++t) {
+            // the next slot (the last tile again at the very end: a slot nobody reads again)
+            pw_fill(a, wtb, min(t + 1, ntiles - 1), gw, lds + (size_t)((t + 1) & 1) * PW_SLOT);
+            const uint8_t* cur = lds + (size_t)(t & 1) * PW_SLOT;
+            f32x16 C0, C1;
+            tile_product2<PREC, FULL>(cur + (h * ZB + col) * ROW_BYTES, col, xlen, Ah0, Al0, Ah1, Al1, C0, C1);
+            const f32x4* ty0 = (const f32x4*)(cur + TILE_BYTES + (2 * wave) * 128 + h * 64);
+            const f32x4 t0[4] = {ty0[0], ty0[1], ty0[2], ty0[3]};
+            rotate_add(G0, C0, t0);
+            const f32x4* ty1 = (const f32x4*)(cur + TILE_BYTES + (2 * wave + 1) * 128 + h * 64);
+            const f32x4 t1[4] = {ty1[0], ty1[1], ty1[2], ty1[3]};
+            rotate_add(G1, C1, t1);
+            // the next slot's loads have landed (the compiler does not track them)
+            __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+            __syncthreads();
+        }
+        // acc[r][m] += Tz[m] * G_r[m] for the two wave tiles
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            const int64_t pix = slot_pixel(wt, h, m);
-            if (pix < a.npix) {
-                const float re = acc[2 * m], im = acc[2 * m + 1];
-                a.intensity[pix] = re * re + im * im;
-                if (a.amplitude) ((float2*)a.amplitude)[pix] = make_float2(re, im);
+        for (int r = 0; r < 2; ++r) {
+            const f32x4* tzp = (const f32x4*)(a.tz + 2 * (((((wt0 + r) * a.nzb + zb) * 2 + h) * ZB + col) * 8));
+            const float* G = r == 0 ? G0 : G1;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const f32x4 v = tzp[q];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int m = 2 * q + u;
+                    const float tr = v[2 * u], ti = v[2 * u + 1];
+                    accl[(16 * r + 2 * m) * 64] += tr * G[2 * m] - ti * G[2 * m + 1];
+                    accl[(16 * r + 2 * m + 1) * 64] += tr * G[2 * m + 1] + ti * G[2 * m];
+                }
             }
         }
     }
 }
 
 template <int PREC>
-__global__ __launch_bounds__(512) void fwd_kernel(FwdArgs a, int64_t block_begin)
+__device__ __forceinline__ void fwd_pair_block(const FwdArgs& a, int64_t block, uint8_t* lds, float* accs)
 {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[4 * TILE_BYTES];
-    fwd_block<PREC>(a, block_begin + blockIdx.x, lds);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int64_t wtb = block * WAVES;
+    const int64_t wt0 = wtb + 2 * wave;
+    const int64_t ntiles = (int64_t)a.nxc * a.nzb * a.ny;
+    const u32x4* gw = (const u32x4*)a.wtiles;
+
+    pw_fill(a, wtb, 0, gw, lds);
+    float* accl = accs + wave * 32 * 64 + lane;
+#pragma unroll
+    for (int q = 0; q < 32; ++q) accl[q * 64] = 0.0f;
+    __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+    __syncthreads();
+
+    int64_t t = 0;
+    for (int xc = 0; xc < a.nxc; ++xc) {
+        const int xlen = min(XC, a.x_pad - xc * XC);
+        f32x4 Af[16];
+        bf16x8 Ah0[8], Al0[8], Ah1[8], Al1[8];
+        load_a<PREC>(a.txa + (size_t)(wt0 * a.nxc + xc) * TILE_BYTES, lane, Af, Ah0, Al0);
+        load_a<PREC>(a.txa + (size_t)((wt0 + 1) * a.nxc + xc) * TILE_BYTES, lane, Af, Ah1, Al1);
+        // one wait for the A operands per chunk (the memory counter is in order)
+        __builtin_amdgcn_s_waitcnt(0);
+        if (xlen == XC)
+            chunk_pair<PREC, true>(a, wt0, ntiles, gw, lds, xlen, Ah0, Al0, Ah1, Al1, t, accl);
+        else
+            chunk_pair<PREC, false>(a, wt0, ntiles, gw, lds, xlen, Ah0, Al0, Ah1, Al1, t, accl);
+    }
+    const int h = lane >> 5, col = lane & 31;
+    // sum over the 32 z lanes of each half (fixed butterfly order)
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        float acc[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            float v = accl[(16 * r + q) * 64];
+            v += __shfl_xor(v, 16, 32);
+            v += __shfl_xor(v, 8, 32);
+            v += __shfl_xor(v, 4, 32);
+            v += __shfl_xor(v, 2, 32);
+            v += __shfl_xor(v, 1, 32);
+            acc[q] = v;
+        }
+        if (col == 0) {
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                const int64_t pix = slot_pixel(wt0 + r, h, m);
+                if (pix < a.npix) {
+                    const float re = acc[2 * m], im = acc[2 * m + 1];
+                    a.intensity[pix] = re * re + im * im;
+                    if (a.amplitude) ((float2*)a.amplitude)[pix] = make_float2(re, im);
+                }
+            }
+        }
+    }
 }
 
-// Batched form: one workgroup per (request, pixel block) item, items numbered in
-// the host's cost order, so the hardware dispatches the most expensive blocks
-// first.  (A persistent form pulling items from a counter measured 10% slower:
-// its loop state pushes the paired-tile contraction past its register budget.)
 template <int PREC>
-__global__ __launch_bounds__(512) void fwd_batch_kernel(BatchArgs b)
+__global__ __launch_bounds__(PW_THREADS, 2) void fwd_pair_kernel(FwdArgs a, int64_t block_begin)
 {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[4 * TILE_BYTES];
+    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * PW_SLOT];
+    __shared__ float accs[PW_WAVES * 32 * 64];
+    fwd_pair_block<PREC>(a, block_begin + blockIdx.x, lds, accs);
+}
+
+// Batched form: one workgroup per (request, pixel block) item, in the host's order.
+template <int PREC>
+__global__ __launch_bounds__(PW_THREADS, 2) void fwd_pair_batch_kernel(BatchArgs b)
+{
+    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * PW_SLOT];
+    __shared__ float accs[PW_WAVES * 32 * 64];
     const int32_t it = blockIdx.x;
     int r = 0;
     while (r + 1 < b.nreq && b.item_begin[r + 1] <= it) ++r;
-    fwd_block<PREC>(b.req[r], (int64_t)b.block_begin[r] + (it - b.item_begin[r]), lds);
+    fwd_pair_block<PREC>(b.req[r], (int64_t)b.block_begin[r] + (it - b.item_begin[r]), lds, accs);
 }
 
-// Flat detector, BF16 precisions (FP32 runs the three-product kernel of gauss.hip).
 int launch_forward(int precision, const FwdArgs& a, int64_t block_begin, int64_t nblocks, void* stream)
 {
     if (nblocks <= 0) return 0;
     if (precision == MSFT_FP32) return (int)hipErrorInvalidValue;
     hipStream_t s = (hipStream_t)stream;
+    const dim3 grid((unsigned)nblocks);
     if (precision == MSFT_BF16X3)
-        hipLaunchKernelGGL(fwd_kernel<MSFT_BF16X3>, dim3((unsigned)nblocks), dim3(512), 0, s, a, block_begin);
+        hipLaunchKernelGGL(fwd_pair_kernel<MSFT_BF16X3>, grid, dim3(PW_THREADS), 0, s, a, block_begin);
     else
-        hipLaunchKernelGGL(fwd_kernel<MSFT_BF16>, dim3((unsigned)nblocks), dim3(512), 0, s, a, block_begin);
+        hipLaunchKernelGGL(fwd_pair_kernel<MSFT_BF16>, grid, dim3(PW_THREADS), 0, s, a, block_begin);
     return (int)hipGetLastError();
 }
 
@@ -651,9 +762,9 @@ int launch_forward_batch(int precision, const BatchArgs& b, void* stream)
     if (items <= 0) return 0;
     if (precision == MSFT_FP32) return (int)hipErrorInvalidValue;   // three-product kernel
     if (precision == MSFT_BF16X3)
-        hipLaunchKernelGGL(fwd_batch_kernel<MSFT_BF16X3>, dim3(items), dim3(512), 0, s, b);
+        hipLaunchKernelGGL(fwd_pair_batch_kernel<MSFT_BF16X3>, dim3(items), dim3(PW_THREADS), 0, s, b);
     else
-        hipLaunchKernelGGL(fwd_batch_kernel<MSFT_BF16>, dim3(items), dim3(512), 0, s, b);
+        hipLaunchKernelGGL(fwd_pair_batch_kernel<MSFT_BF16>, dim3(items), dim3(PW_THREADS), 0, s, b);
     return (int)hipGetLastError();
 }
 

@@ -508,11 +508,12 @@ def serve(torch, msft, plans, requests, batched=True, hbm_budget=16 << 30, slots
 
 
 def benchmark(count=96, precision="fp32", loads=(0.8,), seed=20220205, device=0, plain=True,
-              log=None):
+              log=None, capacity=None):
     """The mixed-size stream served three ways: offline (all requests at t = 0),
     whose batched throughput is the measured capacity, then Poisson arrivals at
     each offered load rho * capacity.  Every stream runs batched and, if `plain`,
-    as one pattern per launch on one stream."""
+    as one pattern per launch on one stream.  A given capacity (patterns/s, from an
+    earlier offline run of the same stream) skips the offline runs."""
     import torch
 
     from . import msft
@@ -537,10 +538,13 @@ def benchmark(count=96, precision="fp32", loads=(0.8,), seed=20220205, device=0,
                 f"p99 {s['p99_ms']:.1f} ms")
         return s
 
-    cap = run("offline", None, True)["patterns_per_s"]
+    if capacity is None:
+        cap = run("offline", None, True)["patterns_per_s"]
+        if plain:
+            run("offline", None, False)
+    else:
+        cap = float(capacity)
     out["capacity_patterns_per_s"] = cap
-    if plain:
-        run("offline", None, False)
     for rho in loads:
         rate = rho * cap
         out[f"offered_rate_rho{rho:g}_per_s"] = rate
@@ -561,7 +565,10 @@ if __name__ == "__main__":
     ap.add_argument("--loads", type=float, nargs="+", default=[0.8],
                     help="offered loads as fractions of the measured batched capacity")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-pattern-per-launch runs")
+    ap.add_argument("--capacity", type=float, default=None,
+                    help="batched capacity (patterns/s) of an earlier offline run: skip the offline runs")
     args = ap.parse_args()
     res = benchmark(args.requests, args.precision, tuple(args.loads), plain=not args.no_plain,
-                    log=lambda m: print(f"[serving] {m}", file=sys.stderr, flush=True))
+                    log=lambda m: print(f"[serving] {m}", file=sys.stderr, flush=True),
+                    capacity=args.capacity)
     print(json.dumps(res))
