@@ -116,6 +116,69 @@ def test_parity_pattern_sampled(msft, precision):
     assert _rel(I[ring], Io[ring]) <= TOL[precision]
 
 
+# Per-pixel error model: the contraction's rounding leaves an absolute amplitude
+# error of a few units in the last place of the brightest amplitude |A|_max (the
+# partial sums are of that size), so a pixel's relative intensity error grows as the
+# pixel gets darker: |dI| / I <= 2 |dA| / |A| = c sqrt(I_max / I).  Measured on the
+# 128^3 body, c reaches 1.8e-7 (FP32) and 1.1e-6 (BF16 split); the bounds below are
+# 16 and 128 units of FP32 rounding (2^-24), five to seven times that.  The same
+# FP32 bound holds on the fit's 32^3 body, whose darkest pixels (1e-12 of the peak)
+# come out within about 4e-3 of the oracle; accumulating the y and z sums in FP64
+# instead moved none of those dark-pixel errors (they come from the FP32 operands
+# and the matrix cores' FP32 sums over x).
+PIXEL_C = {"fp32": 16 * 2.0 ** -24, "bf16x3": 128 * 2.0 ** -24}
+
+
+def _decades(I, Io):
+    """max relative error per decade of I / I_max (I_max: brightest sampled pixel)."""
+    imax = Io.max()
+    rel = np.abs(I - Io) / Io
+    dec = np.floor(-np.log10(Io / imax)).astype(int)
+    return {int(k): (int((dec == k).sum()), float(rel[dec == k].max()),
+                     float(np.max(rel[dec == k] * np.sqrt(Io[dec == k] / imax))))
+            for k in np.unique(dec)}, rel, imax
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_pixel_error_by_intensity_decade(msft, precision):
+    # the 128^3 star body on the 512^2 detector: 16384 seeded pixels plus the forward
+    # pixel, every one within c sqrt(I_max / I) of the FP64 oracle
+    wl = inputs.pattern_workload()
+    n = wl.det_n
+    pix = np.unique(np.concatenate([inputs.random_pixels(n, 16384, seed=91),
+                                    [(n // 2) * n + n // 2]]))
+    I, _ = _run(msft, wl, precision, pixels=pix)
+    Io, _ = _oracle(wl, pixels=pix)
+    table, rel, imax = _decades(I, Io)
+    for k, (cnt, mx, scaled) in table.items():
+        print(f"  I/I_max 1e-{k}: {cnt:5d} px  max rel {mx:.2e}  max rel*sqrt(I/I_max) {scaled:.2e}")
+    bound = PIXEL_C[precision] * np.sqrt(imax / Io)
+    worst = int(np.argmax(rel / bound))
+    assert np.all(rel <= bound), (pix[worst], rel[worst], bound[worst])
+
+
+def test_pixel_error_floor_of_the_fit_case(msft):
+    # the fit's 32^3 soft star on a 48^2 detector in nm, whose pattern spans 13
+    # decades: every pixel within the FP32 bound above
+    import torch
+
+    from paper_2202_03411_amd import fit
+    star = fit.SoftStar(32, 680.0, 4, r0=200.0, device="cuda")
+    rng = np.random.default_rng(10)
+    c = torch.tensor(rng.normal(0, 0.08, star.ncoef), dtype=torch.float32, device="cuda")
+    c[0] = 0.0
+    d, b = star.voxelize(c)
+    wl = inputs.Workload("fit32", 45.0, 60.0, 48, (star.pitch,) * 3, inputs.MODE_MSFT,
+                         d.cpu().numpy(), b.cpu().numpy())
+    I, _ = _run(msft, wl, "fp32")
+    Io, _ = _oracle(wl)
+    table, rel, imax = _decades(I, Io)
+    for k, (cnt, mx, scaled) in table.items():
+        print(f"  I/I_max 1e-{k}: {cnt:5d} px  max rel {mx:.2e}  max rel*sqrt(I/I_max) {scaled:.2e}")
+    assert max(table) >= 12
+    assert np.all(rel <= PIXEL_C["fp32"] * np.sqrt(imax / Io))
+
+
 def test_plain_bf16_is_the_unsplit_reference(msft):
     # single BF16 products: about 1e-3 of the intensity, clearly behind the split form
     wl = inputs.pattern_workload()
