@@ -43,7 +43,7 @@ def profiled_traffic(prec):
     summary, or None when the kernel source has changed since it was counted."""
     import hashlib
     import re
-    kernel = "fwd_g3_kernel_fp32" if prec == "fp32" else f"fwd_kernel_{prec}"
+    kernel = "fwd_g3_kernel_fp32" if prec == "fp32" else f"fwd_pair_kernel_{prec}"
     path = os.path.join(ROOT, "profiles", f"{kernel}_star128_det512_traffic.md")
     if not os.path.exists(path):
         return None
@@ -480,7 +480,7 @@ def main():
                      "frac": head["contract_tflops"] * EXEC_PER_TERM[head_prec] / 8.0
                      / PEAK_TFLOPS[head_prec],
                      "traffic": profiled_traffic(head_prec),
-                     "kernel": "fwd_g3_kernel" if head_prec == "fp32" else f"fwd_kernel<{head_prec}>",
+                     "kernel": "fwd_g3_kernel" if head_prec == "fp32" else f"fwd_pair_kernel<{head_prec}>",
                      "per_launch": f"{flops * EXEC_PER_TERM[head_prec] / 8.0:.4e} executed flops "
                                    f"({EXEC_PER_TERM[head_prec]} per voxel-pixel term, {P * V:.4e} terms)",
                      "achieved_algorithmic": head["contract_tflops"],
