@@ -111,8 +111,10 @@ msft_status build_device_tables(msft_plan_s* p)
     MSFT_TRY(dev_alloc(&p->ys_dev, sizeof(double) * d.ny, &total), "hipMalloc y");
     MSFT_TRY(dev_alloc(&p->zs_dev, sizeof(double) * d.nz, &total), "hipMalloc z");
     if (p->separable) {
-        MSFT_TRY(dev_alloc(&p->txa, p->sep.txa1_bytes(d.nxc), &total), "hipMalloc Tx");
-        MSFT_TRY(dev_alloc(&p->txa2, p->sep.txa2_bytes(), &total), "hipMalloc Ty");
+        const SepDims& sd = p->sep;
+        MSFT_TRY(dev_alloc(&p->txa, sd.gauss ? sd.txa1g_bytes(d.nxc3) : sd.txa1_bytes(d.nxc), &total),
+                 "hipMalloc Tx");
+        MSFT_TRY(dev_alloc(&p->txa2, sd.gauss ? sd.txa2g_bytes() : sd.txa2_bytes(), &total), "hipMalloc Ty");
         MSFT_TRY(dev_alloc(&p->tz, p->sep.tz_bytes(d.nzb), &total), "hipMalloc Tz");
         MSFT_TRY(dev_alloc(&p->txT, p->sep.txT_bytes(d.nx), &total), "hipMalloc adjoint Tx");
         MSFT_TRY(dev_alloc(&p->tyT, p->sep.tyT_bytes(d.ny), &total), "hipMalloc adjoint Ty");
@@ -156,8 +158,12 @@ msft_status build_device_tables(msft_plan_s* p)
         }
         if (e == hipSuccess)
             e = (hipError_t)launch_sep_twiddles(p->geo.g.precision, d, sd, dev[0], dev[1], dev[2],
-                                                p->xs_dev, p->ys_dev, p->zs_dev, p->txa, p->txa2,
-                                                p->tz, s);
+                                                p->xs_dev, p->ys_dev, p->zs_dev,
+                                                sd.gauss ? nullptr : p->txa,
+                                                sd.gauss ? nullptr : p->txa2, p->tz, s);
+        if (e == hipSuccess && sd.gauss)
+            e = (hipError_t)launch_sepg_twiddles(sd, d.nx, d.ny, d.nxc3, dev[3], dev[4], p->xs_dev,
+                                                 p->ys_dev, p->txa, p->txa2, s);
         if (e == hipSuccess)
             e = (hipError_t)launch_sep_adj_tables(sd, d.nx, d.ny, dev[5], dev[3], dev[6], dev[4],
                                                   p->txT, p->tyT, s);
@@ -258,13 +264,18 @@ msft_status make_plan(const msft_geometry* g, const double* q_host, int64_t npix
         return fail(MSFT_ERR_UNDERSAMPLED, buf);
     }
     p->dims = make_dims(p->geo.npix, g->nx, g->ny, g->nz);
-    // FP32 without the separable detector runs the Gauss (three-product) contraction
-    p->dims.g3 = g->precision == MSFT_FP32 && !p->separable;
+    if (p->separable) {
+        p->sep = make_sep_dims(g->det_n, g->ny);
+        p->sep.nyc2 = (int32_t)ceil_div(g->ny, 32);
+        p->sep.gauss = g->precision == MSFT_FP32 && p->sep.nyc2 <= SG2_MAXYC;
+    }
+    // FP32 runs the Gauss (three-product) contractions: the flat detector and q
+    // lists always, the separable detector up to SG2_MAXYC * 32 rows y
+    p->dims.g3 = g->precision == MSFT_FP32 && (!p->separable || p->sep.gauss);
     size_t fwd_ws = align256(p->dims.wtile_bytes());
     size_t adj_ws = align256(make_adj_dims(p->dims).bytes());
     if (p->separable) {
-        p->sep = make_sep_dims(g->det_n, g->ny);
-        fwd_ws += align256(p->sep.h_bytes(p->dims.nzb));
+        fwd_ws += align256(p->sep.gauss ? p->sep.hg_bytes(p->dims.nzb) : p->sep.h_bytes(p->dims.nzb));
         adj_ws = sep_adj_layout(p, nullptr, nullptr);
     }
     p->fwd_workspace = fwd_ws;
@@ -351,6 +362,28 @@ FwdArgs sep_stage2_args(const msft_plan_s* p, const void* workspace, float* inte
     return a;
 }
 
+// Both stages in the Gauss form: H tiles after the W tiles in the workspace.
+SepG3Args sepg_args(const msft_plan_s* p, const void* workspace, float* intensity, float* amplitude)
+{
+    const SepDims& sd = p->sep;
+    SepG3Args a;
+    a.wtiles = (const uint8_t*)workspace;
+    a.txa1 = p->txa;
+    a.htiles = (uint8_t*)workspace + align256(p->dims.wtile_bytes());
+    a.txa2 = p->txa2;
+    a.tz = p->tz;
+    a.intensity = intensity;
+    a.amplitude = amplitude;
+    a.n = sd.n;
+    a.npad = sd.npad;
+    a.ny = p->dims.ny;
+    a.nxc3 = p->dims.nxc3;
+    a.nyc2 = sd.nyc2;
+    a.nzb = p->dims.nzb;
+    a.nblk1 = sd.nblk1;
+    return a;
+}
+
 Stage1Args sep_stage1_args(const msft_plan_s* p, const void* workspace)
 {
     Stage1Args a;
@@ -372,6 +405,7 @@ int launch_contraction(const msft_plan_s* p, const void* workspace, float* inten
                        float* amplitude, void* stream)
 {
     const int prec = p->geo.g.precision;
+    if (p->separable && p->sep.gauss) return launch_sepg(sepg_args(p, workspace, intensity, amplitude), stream);
     if (p->dims.g3)
         return launch_forward_g3(forward_args(p, workspace, intensity, amplitude), 0, p->dims.nblocks,
                                  stream);

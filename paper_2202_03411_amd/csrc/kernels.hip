@@ -11,6 +11,7 @@
 //                adjoint.
 #include <hip/hip_runtime.h>
 
+#include "lds_dma.h"
 #include "msft_internal.h"
 
 namespace msft {
@@ -190,8 +191,9 @@ int launch_sep_twiddles(int precision, const Dims& d, const SepDims& sd, const d
 {
     hipStream_t s = (hipStream_t)stream;
     const int B = 256;
-    launch_txa(precision, txa1, sd.nblk1 * WAVES, sd.n, d.nx, d.nxc, qcol, xs, s);
-    launch_txa(precision, txa2, sd.npad / WAVE_PIX, sd.n, d.ny, sd.nyc, qrow, ys, s);
+    // (the Gauss form has its own A tables: txa1 and txa2 null)
+    if (txa1) launch_txa(precision, txa1, sd.nblk1 * WAVES, sd.n, d.nx, d.nxc, qcol, xs, s);
+    if (txa2) launch_txa(precision, txa2, sd.npad / WAVE_PIX, sd.n, d.ny, sd.nyc, qrow, ys, s);
     const int64_t nwt2 = (int64_t)sd.n * (sd.npad / WAVE_PIX);
     const int64_t ntz = nwt2 * d.nzb * 2 * ZB * 8;
     hipLaunchKernelGGL(twiddle_tz, dim3(grid_for(ntz, B)), dim3(B), 0, s, (float2*)tz, ntz,
@@ -204,9 +206,10 @@ int launch_sep_twiddles(int precision, const Dims& d, const SepDims& sd, const d
 //
 // Workgroup (x chunk xc of 64 columns, y), 8 waves, four z blocks of 32 slices
 // per round: wave w takes z block zb0 + w / 2 of the columns 32 (w & 1) .. + 31.
-// Lanes run along z: the 8 lanes of a group hold 4 consecutive slices each of
-// one column (together one 128-byte line of delta and one of beta), and a lane
-// holds 4 columns 8 apart, so every load instruction reads whole lines.  The
+// Lanes run along z: a lane holds 4 consecutive slices of 4 columns 8 apart, and
+// the 8 lanes of a group cover the block's 32 slices of those columns (one
+// 128-byte line of delta and one of beta each), so every load instruction reads
+// whole lines.  The
 // exclusive prefix S = sum_{s'<s} (beta + i delta) of a slice is the carry of
 // the earlier rounds, plus the totals of the earlier z blocks of the round
 // (through LDS), plus an inclusive shuffle scan over the 8 lanes of the group,
@@ -544,31 +547,6 @@ constexpr int PW_TY_BYTES = WAVES * WAVE_PIX * 8;         // Ty of a block's wav
 constexpr int PW_SLOT = TILE_BYTES + PW_TY_BYTES;
 static_assert(PW_COPY * PW_THREADS == TILE_BYTES / 16, "a tile is copied in whole pieces");
 static_assert(2 * PW_WAVES == WAVES && PW_TY_BYTES == 64 * 16, "one wave gathers the Ty rows");
-// s_waitcnt immediates (gfx9 encoding: vmcnt in bits 3:0 and 15:14, expcnt 6:4,
-// lgkmcnt 11:8): wait until at most n vector-memory operations are outstanding
-constexpr int waitcnt_vm(int n) { return (n & 15) | (7 << 4) | (15 << 8) | ((n >> 4) << 14); }
-
-// One 16-byte piece per lane from global memory straight into LDS: lane l of the
-// wave writes dst_wave + 16 l (dst_wave uniform over the wave).  Written as inline
-// assembly so that the compiler does not wait for it before every read of the other
-// ring slots (it cannot tell the slots apart); it produces no register result, and
-// the caller waits for the memory counter before the barrier that publishes a slot.
-// M0 is set inside the block; the compiler reserves M0 and uses it in none of the
-// kernels that call this (their code has no other M0 access), so the clobber is
-// declared for the reader only and its "reserved register" warning is silenced.
-#pragma clang diagnostic push
-#pragma clang diagnostic ignored "-Winline-asm"
-__device__ __forceinline__ void lds_dma16(const void* src, uint8_t* dst_wave)
-{
-    const uint32_t m0 = __builtin_amdgcn_readfirstlane(
-        (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t*)dst_wave);
-    asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
-                 :
-                 : "v"(src), "s"(m0)
-                 : "memory", "m0");
-}
-#pragma clang diagnostic pop
-
 // Slot contents for tile tn: the W tile and, from wave 0, the block's Ty rows at
 // y(tn).  Wave 0 issues PW_COPY + 1 loads, the others PW_COPY.
 __device__ __forceinline__ void pw_fill(const FwdArgs& a, int64_t wtb, int64_t tn, const u32x4* gw,

@@ -111,6 +111,12 @@ struct FwdArgs {
     int32_t group_blocks, group_tiles, out_n, out_npad;
 };
 
+// Gauss form of the separable detector (FP32): the second stage keeps its A
+// operand for at most SG2_MAXYC chunks of 32 y in registers; one (row tile of 16
+// j, y chunk) of it is SG2_A_BYTES.
+constexpr int SG2_MAXYC = 4;
+constexpr int SG2_A_BYTES = 3 * 2 * 64 * 16;
+
 // Separable (uniform transverse q) detector: q_x depends on the column i only,
 // q_y on the row j only.  Stage 1 forms H = Tx W per column (N x ny x nz); stage 2
 // contracts H over y against Ty per row with the z phase behind it.
@@ -131,6 +137,14 @@ struct SepDims {
     size_t tyT_bytes(int ny) const { return (size_t)ceil_div(ny, BLOCK_PIX) * WAVES * njc * TILE_BYTES; }
     size_t txT_bytes(int nx) const { return (size_t)ceil_div(nx, BLOCK_PIX) * WAVES * nic * TILE_BYTES; }
     size_t k_bytes(int ny, int nzb) const { return (size_t)nic * nzb * ny * TILE_BYTES; }
+    // FP32 with ny <= SG2_MAXYC * 32: the Gauss (three-product) form of both stages.
+    // H tiles [i][y chunk of 32][z block] of G3_TILE_BYTES; A operands of stage 1
+    // [wave of 32 columns][x chunk of 32] (G3 layout), of stage 2 [16 rows j][y chunk].
+    bool gauss = false;
+    int32_t nyc2 = 0;   // y chunks of 32
+    size_t hg_bytes(int nzb) const { return (size_t)n * nyc2 * nzb * G3_TILE_BYTES; }
+    size_t txa1g_bytes(int nxc3) const { return (size_t)nblk1 * G3_WAVES * nxc3 * G3_TILE_BYTES; }
+    size_t txa2g_bytes() const { return (size_t)(npad / WAVE_PIX) * nyc2 * SG2_A_BYTES; }
 };
 SepDims make_sep_dims(int32_t n, int ny);
 
@@ -142,6 +156,19 @@ struct Stage1Args {
     uint8_t* htiles;        // TILE: H tiles [i][y chunk][z block]
     float* rplain;          // PLAIN: [row][ny][nz2] complex
     int32_t n, ny, nxc, nzb, x_pad, nyc, nz2;
+};
+
+// Both stages of the separable detector in the Gauss form (see SepDims).
+struct SepG3Args {
+    const uint8_t* wtiles;  // W tiles in the G3 layout, index (xc * nzb + zb) * ny + y
+    const uint8_t* txa1;    // stage 1 A tiles [wave of 32 columns][xc]
+    uint8_t* htiles;        // H tiles [i][yc][zb]
+    const uint8_t* txa2;    // stage 2 A tables [16 rows j][yc]
+    const float* tz;        // the plan's Tz over stage 2's pixel order (16-row tiles)
+    float* intensity;       // [N * N], pixel j * N + i
+    float* amplitude;       // [N * N] complex or null
+    int32_t n, npad, ny, nxc3, nyc2, nzb;
+    int64_t nblk1;
 };
 
 // The adjoint's contraction over the detector rows j (see SepDims).
@@ -274,6 +301,10 @@ int launch_sep_twiddles(int precision, const Dims& d, const SepDims& sd, const d
 int launch_sep_stage1(int precision, const Stage1Args& a, int64_t nblk, void* stream);
 // a: second-stage arguments (group_blocks, group_tiles, out_n, out_npad set)
 int launch_sep_stage2(int precision, const FwdArgs& a, void* stream);
+int launch_sepg_twiddles(const SepDims& sd, int nx, int ny, int nxc3, const double* qx,
+                         const double* qy, const double* xs, const double* ys, uint8_t* txa1,
+                         uint8_t* txa2, void* stream);
+int launch_sepg(const SepG3Args& a, void* stream);
 int launch_sep_adjoint(const SepAdjArgs& ka, const Stage1Args& ra, int64_t nblk_rows, void* stream);
 int launch_sep_adj_tables(const SepDims& sd, int nx, int ny, const double* xq3, const double* qx,
                           const double* yq3, const double* qy, uint8_t* txT, uint8_t* tyT,

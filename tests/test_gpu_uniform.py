@@ -69,6 +69,8 @@ SMALL = [
     ("two_blocks", (24, 24, 24), 150, (10.0, 10.0, 10.0), inputs.MODE_BORN, 53, 30.0),
     ("tiny", (1, 1, 1), 1, (10.0, 10.0, 10.0), inputs.MODE_MSFT, 54, 60.0),
     ("thin_z", (9, 70, 3), 31, (6.0, 5.0, 12.0), inputs.MODE_DENSITY, 55, 80.0),
+    # more than 128 rows y: FP32 leaves the three-product form for the four-product one
+    ("tall_y", (10, 140, 20), 24, (6.0, 5.0, 7.0), inputs.MODE_MSFT, 56, 60.0),
 ]
 
 
@@ -122,10 +124,11 @@ def test_uniform_pattern_sampled(env, precision):
 
 @pytest.mark.parametrize("n", [511, 383, 255])
 def test_uniform_column_groups(env, n):
-    # Detector sides whose second stage runs 2, 2 and 1 columns per workgroup (the
-    # odd sides leave a last group of one column); 511 and 383 also differ in their
-    # row blocks (4 and 3).  ny = 70 gives a full and a partial y chunk.  Seeded
-    # pixels plus every row of the last three columns and of column 0.
+    # Detector sides whose second stage leaves a last, partial group of columns: the
+    # BF16 split runs 2, 2 and 1 columns per workgroup (row blocks of 128: 4, 3, 2),
+    # the FP32 three-product form 8, 4 and 2 (row blocks of 64: 8, 6, 4; last groups
+    # of 7, 3 and 1 columns).  ny = 70 gives full and partial y chunks in both.
+    # Seeded pixels plus every row of the last three columns and of column 0.
     d, b = _field((20, 70, 33), 60 + n)
     wl = inputs.Workload(f"cols{n}", 45.0, 60.0, n, (9.0, 7.0, 8.0), inputs.MODE_MSFT, d, b)
     rows = np.arange(n)
