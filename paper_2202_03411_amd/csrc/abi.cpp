@@ -116,8 +116,10 @@ msft_status build_device_tables(msft_plan_s* p)
                  "hipMalloc Tx");
         MSFT_TRY(dev_alloc(&p->txa2, sd.gauss ? sd.txa2g_bytes() : sd.txa2_bytes(), &total), "hipMalloc Ty");
         MSFT_TRY(dev_alloc(&p->tz, p->sep.tz_bytes(d.nzb), &total), "hipMalloc Tz");
-        MSFT_TRY(dev_alloc(&p->txT, p->sep.txT_bytes(d.nx), &total), "hipMalloc adjoint Tx");
-        MSFT_TRY(dev_alloc(&p->tyT, p->sep.tyT_bytes(d.ny), &total), "hipMalloc adjoint Ty");
+        MSFT_TRY(dev_alloc(&p->txT, sd.gauss ? sd.txTg_bytes(d.nx) : sd.txT_bytes(d.nx), &total),
+                 "hipMalloc adjoint Tx");
+        MSFT_TRY(dev_alloc(&p->tyT, sd.gauss ? sd.tyTg_bytes(d.ny) : sd.tyT_bytes(d.ny), &total),
+                 "hipMalloc adjoint Ty");
     } else {
         MSFT_TRY(dev_alloc(&p->txa, d.txa_bytes(), &total), "hipMalloc Tx");
         MSFT_TRY(dev_alloc(&p->ty, d.ty_bytes(), &total), "hipMalloc Ty");
@@ -165,8 +167,10 @@ msft_status build_device_tables(msft_plan_s* p)
             e = (hipError_t)launch_sepg_twiddles(sd, d.nx, d.ny, d.nxc3, dev[3], dev[4], p->xs_dev,
                                                  p->ys_dev, p->txa, p->txa2, s);
         if (e == hipSuccess)
-            e = (hipError_t)launch_sep_adj_tables(sd, d.nx, d.ny, dev[5], dev[3], dev[6], dev[4],
-                                                  p->txT, p->tyT, s);
+            e = sd.gauss ? (hipError_t)launch_sepg_adj_tables(sd, d.nx, d.ny, p->xs_dev, dev[3], p->ys_dev,
+                                                              dev[4], p->txT, p->tyT, s)
+                         : (hipError_t)launch_sep_adj_tables(sd, d.nx, d.ny, dev[5], dev[3], dev[6], dev[4],
+                                                             p->txT, p->tyT, s);
         hipError_t e2 = hipStreamSynchronize(s);
         if (e == hipSuccess) e = e2;
         for (double* t : dev)
@@ -198,8 +202,8 @@ size_t sep_adj_layout(const msft_plan_s* p, size_t* k_off, size_t* r_off)
 {
     const Dims& d = p->dims;
     const size_t hb = align256((size_t)d.npix * 8);
-    const size_t kb = align256(p->sep.k_bytes(d.ny, d.nzb));
-    const size_t rb = align256((size_t)d.nxc * XC * d.ny * d.nzb * ZB * 8);
+    const size_t kb = align256(p->sep.gauss ? p->sep.kg_bytes(d.ny, d.nzb) : p->sep.k_bytes(d.ny, d.nzb));
+    const size_t rb = align256((size_t)(p->sep.gauss ? SEPG_ADJ_SPLIT : 1) * d.nxc * XC * d.ny * d.nzb * ZB * 8);
     if (k_off) *k_off = hb;
     if (r_off) *r_off = hb + kb;
     return hb + kb + rb;
@@ -268,6 +272,7 @@ msft_status make_plan(const msft_geometry* g, const double* q_host, int64_t npix
         p->sep = make_sep_dims(g->det_n, g->ny);
         p->sep.nyc2 = (int32_t)ceil_div(g->ny, 32);
         p->sep.gauss = g->precision == MSFT_FP32 && p->sep.nyc2 <= SG2_MAXYC;
+        p->sep.nic3 = (int32_t)ceil_div(g->det_n, 32);
     }
     // FP32 runs the Gauss (three-product) contractions: the flat detector and q
     // lists always, the separable detector up to SG2_MAXYC * 32 rows y
@@ -898,6 +903,31 @@ msft_status msft_backward(msft_plan_t plan, const float* delta, const float* bet
         size_t k_off = 0, r_off = 0;
         sep_adj_layout(plan, &k_off, &r_off);
         const SepDims& sd = plan->sep;
+        if (sd.gauss) {
+            SepG3AdjArgs ga;
+            ga.h = (const float*)ws;
+            ga.tz = plan->tz;
+            ga.tyT = plan->tyT;
+            ga.txT = plan->txT;
+            ga.kplain = (float*)(ws + k_off);
+            ga.rpart = (float*)(ws + r_off);
+            ga.n = sd.n;
+            ga.npad = sd.npad;
+            ga.nx = d.nx;
+            ga.ny = d.ny;
+            ga.nzb = d.nzb;
+            ga.nz2 = d.nzb * ZB;
+            ga.njc2 = sd.nic3;
+            ga.nic3 = sd.nic3;
+            ga.rows_pad = d.nxc * XC;
+            f.rpart = ga.rpart;
+            f.nsplit = SEPG_ADJ_SPLIT;
+            int e = launch_adj_prep(amplitude, grad_intensity, (float*)ws, d.npix, d.npix, stream);
+            if (!e) e = launch_sepg_adjoint(ga, stream);
+            if (!e) e = launch_adj_finalize(f, stream);
+            if (e) return hip_fail((hipError_t)e, "backward launch");
+            return ok();
+        }
         SepAdjArgs ka;
         ka.h = (const float*)ws;
         ka.tz = plan->tz;

@@ -145,6 +145,12 @@ struct SepDims {
     size_t hg_bytes(int nzb) const { return (size_t)n * nyc2 * nzb * G3_TILE_BYTES; }
     size_t txa1g_bytes(int nxc3) const { return (size_t)nblk1 * G3_WAVES * nxc3 * G3_TILE_BYTES; }
     size_t txa2g_bytes() const { return (size_t)(npad / WAVE_PIX) * nyc2 * SG2_A_BYTES; }
+    // ... and of its adjoint: chunks of 32 columns i (and of 32 rows j), K in three
+    // planes [i][y][z], A tables of the two passes.
+    int32_t nic3 = 0;
+    size_t kg_bytes(int ny, int nzb) const { return (size_t)3 * nic3 * 32 * ny * nzb * ZB * 4; }
+    size_t tyTg_bytes(int ny) const { return (size_t)ceil_div(ny, 64) * 4 * nic3 * SG2_A_BYTES; }
+    size_t txTg_bytes(int nx) const { return (size_t)ceil_div(nx, 128) * 4 * nic3 * G3_TILE_BYTES; }
 };
 SepDims make_sep_dims(int32_t n, int ny);
 
@@ -169,6 +175,19 @@ struct SepG3Args {
     float* amplitude;       // [N * N] complex or null
     int32_t n, npad, ny, nxc3, nyc2, nzb;
     int64_t nblk1;
+};
+
+// The Gauss form's adjoint (see SepDims): pass 2 splits its sum over the columns
+// i in SEPG_ADJ_SPLIT partial sums.
+constexpr int SEPG_ADJ_SPLIT = 2;
+struct SepG3AdjArgs {
+    const float* h;         // [N * N] complex, h_p = g_p conj(A_p), p = j * N + i
+    const float* tz;        // the plan's Tz over stage 2's pixel order (16-row tiles)
+    const uint8_t* tyT;     // pass 1 A tables [16 rows y][j chunk of 32]
+    const uint8_t* txT;     // pass 2 A tiles [32 rows x][i chunk of 32]
+    float* kplain;          // K in three planes Kr, Ki, Kr + Ki of [nic3 * 32][ny][nz2] floats
+    float* rpart;           // [SEPG_ADJ_SPLIT][rows_pad][ny][nz2] complex
+    int32_t n, npad, nx, ny, nzb, nz2, njc2, nic3, rows_pad;
 };
 
 // The adjoint's contraction over the detector rows j (see SepDims).
@@ -305,6 +324,9 @@ int launch_sepg_twiddles(const SepDims& sd, int nx, int ny, int nxc3, const doub
                          const double* qy, const double* xs, const double* ys, uint8_t* txa1,
                          uint8_t* txa2, void* stream);
 int launch_sepg(const SepG3Args& a, void* stream);
+int launch_sepg_adj_tables(const SepDims& sd, int nx, int ny, const double* xs, const double* qx,
+                           const double* ys, const double* qy, uint8_t* txT, uint8_t* tyT, void* stream);
+int launch_sepg_adjoint(const SepG3AdjArgs& a, void* stream);
 int launch_sep_adjoint(const SepAdjArgs& ka, const Stage1Args& ra, int64_t nblk_rows, void* stream);
 int launch_sep_adj_tables(const SepDims& sd, int nx, int ny, const double* xq3, const double* qx,
                           const double* yq3, const double* qy, uint8_t* txT, uint8_t* tyT,

@@ -108,12 +108,22 @@ __global__ void sg_twiddle_a2(float* t, int64_t total, int n, int ny, int nyc2, 
 // Stage 1.
 // ---------------------------------------------------------------------------
 
-// W tile (xc, zb, y) into an LDS slot: three 16-byte pieces per thread (wave:
-// the wave index as a wave-uniform value, so the addresses stay scalar).
-__device__ __forceinline__ void sg1_fill(const SepG3Args& a, int xc, int zb, int y, int wave, uint8_t* slot)
+// Stage 1, H(i, y, z) = sum_x A(i, x) W(x, y, z): rows i of 32 per wave and 128 per
+// workgroup, two consecutive y per pass and `pairs` passes per workgroup, one z
+// block; H goes to stage 2's tiles.
+struct SG1Args {
+    const uint8_t* btiles;  // W tiles (G3 layout), index (kc * nzb + zb) * ny + y
+    const uint8_t* atab;    // A tiles [wave of 32 rows][kc], G3_TILE_BYTES each
+    uint8_t* htiles;        // H tiles [row][yc][zb]
+    int32_t nrows, ny, nkc, nzb, nyc2, pairs;
+};
+
+// B tile (kc, zb, y) into an LDS slot: three 16-byte pieces per thread (wave: the
+// wave index as a wave-uniform value, so the addresses stay scalar).
+__device__ __forceinline__ void sg1_fill(const SG1Args& a, int kc, int zb, int y, int wave, uint8_t* slot)
 {
     const int lane = threadIdx.x & 63;
-    const u32x4* src = (const u32x4*)(a.wtiles + ((size_t)(xc * a.nzb + zb) * a.ny + y) * G3_TILE_BYTES);
+    const u32x4* src = (const u32x4*)(a.btiles + ((size_t)(kc * a.nzb + zb) * a.ny + y) * G3_TILE_BYTES);
 #pragma unroll
     for (int c = 0; c < SG1_COPY; ++c) {
         const int q = c * SG_THREADS + wave * 64;   // piece of the wave's lane 0
@@ -146,13 +156,11 @@ __device__ __forceinline__ void sg1_tile(const uint8_t* row, int col, const f32x
     }
 }
 
-// Grid (column blocks of 128, groups of SG1_PAIRS y pairs over nyc2 * 32, z
-// blocks): the workgroup walks its y pairs one after the other with the tile ring
-// running on across them.  Rows y >= ny of the H tiles are written as zeros;
-// columns i >= N are not stored.
-constexpr int SG1_PAIRS = 2;
-
-__global__ __launch_bounds__(SG_THREADS, 2) void sepg_stage1_kernel(SepG3Args a)
+// Grid (row blocks of 128, groups of `pairs` y pairs over nyc2 * 32, z blocks): the
+// workgroup walks its y pairs one after the other with the tile ring running on
+// across them.  Rows y >= ny of the H tiles are written as zeros; rows i >= nrows
+// are not stored.
+__global__ __launch_bounds__(SG_THREADS, 2) void sg1_kernel(SG1Args a)
 {
     __shared__ __attribute__((aligned(16))) uint8_t lds[2 * G3_TILE_BYTES];
     const int tid = threadIdx.x;
@@ -161,32 +169,31 @@ __global__ __launch_bounds__(SG_THREADS, 2) void sepg_stage1_kernel(SepG3Args a)
     const int h = lane >> 5, col = lane & 31;
     const int64_t wt = (int64_t)blockIdx.x * SG_WAVES + wave;
     const int zb = blockIdx.z;
-    const int ybase = 2 * SG1_PAIRS * blockIdx.y;
-    // y rows of the pairs inside the grid: tiles (xc, y) in the order (pair, xc, y)
-    const int nyw = max(0, min(2 * SG1_PAIRS, a.ny - ybase));
-    // the stage after (pair p, xc, u): its W tile
-    auto next_tile = [&](int p, int xc, int u, int& xn, int& yn) {
-        const int y = ybase + 2 * p + u;
-        const int nyh = min(2, a.ny - (ybase + 2 * p));
+    const int kc0 = 0, kc1 = a.nkc;
+    const int ybase = 2 * a.pairs * blockIdx.y;
+    const int yend = min(a.ny, ybase + 2 * a.pairs);   // rows y of this workgroup: [ybase, yend)
+    // the tile after (pair p, kc, u) in the order (pair, kc, y)
+    auto next_tile = [&](int y0, int kc, int u, int& kn, int& yn) {
+        const int nyh = min(2, a.ny - y0);
         if (u + 1 < nyh) {
-            xn = xc;
-            yn = y + 1;
-        } else if (xc + 1 < a.nxc3) {
-            xn = xc + 1;
-            yn = ybase + 2 * p;
+            kn = kc;
+            yn = y0 + u + 1;
+        } else if (kc + 1 < kc1) {
+            kn = kc + 1;
+            yn = y0;
         } else {
-            xn = 0;
-            yn = ybase + 2 * p + 2;
+            kn = kc0;
+            yn = y0 + 2;
         }
     };
-    if (nyw > 0) {
-        sg1_fill(a, 0, zb, ybase, wave, lds);
+    if (ybase < yend && kc0 < kc1) {
+        sg1_fill(a, kc0, zb, ybase, wave, lds);
         __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
         __syncthreads();
     }
     int k = 0;   // tiles consumed so far; tile k sits in slot k & 1
 #pragma unroll 1
-    for (int p = 0; p < SG1_PAIRS; ++p) {
+    for (int p = 0; p < a.pairs; ++p) {
         const int y0 = ybase + 2 * p;
         const int nyh = max(0, min(2, a.ny - y0));   // y of this pair inside the grid
         f32x16 P[2][3];
@@ -194,18 +201,17 @@ __global__ __launch_bounds__(SG_THREADS, 2) void sepg_stage1_kernel(SepG3Args a)
         for (int u = 0; u < 2; ++u)
 #pragma unroll
             for (int q = 0; q < 3; ++q) P[u][q] = f32x16{};
-        for (int xc = 0; xc < a.nxc3 && nyh > 0; ++xc) {
+        for (int kc = kc0; kc < kc1 && nyh > 0; ++kc) {
             f32x4 Af[12];
-            const f32x4* ta = (const f32x4*)(a.txa1 + (size_t)(wt * a.nxc3 + xc) * G3_TILE_BYTES);
+            const f32x4* ta = (const f32x4*)(a.atab + (size_t)(wt * a.nkc + kc) * G3_TILE_BYTES);
 #pragma unroll
             for (int q = 0; q < 12; ++q) Af[q] = ta[q * 64 + lane];
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
                 if (u < nyh) {
-                    int xn, yn;
-                    next_tile(p, xc, u, xn, yn);
-                    if (yn < min(a.ny, ybase + 2 * SG1_PAIRS))
-                        sg1_fill(a, xn, zb, yn, wave, lds + ((k + 1) & 1) * G3_TILE_BYTES);
+                    int kn, yn;
+                    next_tile(y0, kc, u, kn, yn);
+                    if (yn < yend) sg1_fill(a, kn, zb, yn, wave, lds + ((k + 1) & 1) * G3_TILE_BYTES);
                     sg1_tile(lds + (k & 1) * G3_TILE_BYTES + (h * ZB + col) * G3_ROW_BYTES, col, Af, P[u]);
                     // the next slot's loads have landed (the compiler does not track them)
                     __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
@@ -222,7 +228,7 @@ __global__ __launch_bounds__(SG_THREADS, 2) void sepg_stage1_kernel(SepG3Args a)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int64_t i = wt * G3_WAVE_PIX + 8 * (r >> 2) + 4 * h + (r & 3);
-            if (i < a.n) {
+            if (i < a.nrows) {
                 float hr[2], hi[2];
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
@@ -411,6 +417,274 @@ __global__ __launch_bounds__(SG_THREADS, 2) void sepg_stage2_kernel(SepG3Args a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Adjoint.  With h = g conj(A) the strength gradient needs
+//   R(x, y, z) = sum_{i,j} h(i, j) exp(-i (q_x(i) x + q_y(j) y + q_z(i, j) z)),
+// the transposed two-stage sum:
+//   K(i, y, z) = sum_j exp(-i q_y(j) y) [h(i, j) exp(-i q_z(i, j) z)]   (pass 1)
+//   R(x, y, z) = sum_i exp(-i q_x(i) x) K(i, y, z)                      (pass 2)
+// Pass 1 (v_mfma_f32_16x16x4_f32): rows are a wave's 16 y, columns 16 z, K four
+// rows j; a workgroup takes 64 y, SGA_COLS columns i and one z block, forms the B
+// tiles h Tz of the next chunk of 32 j in LDS (three planes) behind the current
+// chunk's MFMAs, and writes K as three planes of [i][y][z] floats (16 lanes store
+// 16 consecutive z).  Pass 2 (sepg_adj_cols_kernel) has the shape of stage 1 with
+// rows x and K over the columns i, split in two halves whose partial sums the
+// column walk adds.
+// ---------------------------------------------------------------------------
+constexpr int SGA_COLS = 2;
+
+// P[c] += the three products of the B tiles of 32 j of NC columns (the H tile
+// layout, j in place of y; column c at tiles + c G3_TILE_BYTES) with the wave's A
+// operand for that chunk: Af[2 plane + g], step 4 g + e.  Groups (column, g, plane)
+// of eight MFMAs; the next group's B fragments are read from LDS before the current
+// group's MFMAs are issued.
+template <int NC>
+__device__ __forceinline__ void sga_tiles(const uint8_t* tiles, int kk, int n16, const f32x4 (&Af)[6],
+                                          f32x4 (&P)[SGA_COLS][3][2])
+{
+    constexpr int NG = NC * 6;
+    const uint8_t* base = tiles + kk * 1024 + n16 * 16;
+    // group k: column k / 6, g = (k / 3) % 2, plane k % 3
+    auto frag = [&](int k, int nt) {
+        return *(const f32x4*)(base + (k / 6) * G3_TILE_BYTES + (k % 3) * SG_PLANE_BYTES + ((k / 3) % 2) * 512 +
+                               nt * 256);
+    };
+    f32x4 b[2][2];
+    b[0][0] = frag(0, 0);
+    b[0][1] = frag(0, 1);
+#pragma unroll
+    for (int k = 0; k < NG; ++k) {
+        if (k + 1 < NG) {
+            b[(k + 1) & 1][0] = frag(k + 1, 0);
+            b[(k + 1) & 1][1] = frag(k + 1, 1);
+        }
+        // keep the next group's reads ahead of this group's MFMAs
+        __builtin_amdgcn_sched_barrier(0);
+        const int c = k / 6, g = (k / 3) % 2, p = k % 3;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt)
+                P[c][p][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(Af[2 * p + g][e], b[k & 1][nt][e], P[c][p][nt], 0,
+                                                                   0, 0);
+    }
+}
+
+// Grid: (blocks of 64 y) x (column groups over nic3 * 32) x (z blocks), blocks of y
+// fastest; the y blocks of one column group run on one XCD, so their Tz comes from
+// HBM about once.  Columns i >= N (up to nic3 * 32) store zeros; rows y >= ny are
+// not stored.
+__global__ __launch_bounds__(SG_THREADS, 2) void sepg_adj_rows_kernel(SepG3AdjArgs a)
+{
+    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * SGA_COLS * G3_TILE_BYTES];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int kk = lane >> 4, n16 = lane & 15;
+    // workgroup b runs on XCD b % 8: consecutive L share an XCD
+    const int64_t G = gridDim.x, b = blockIdx.x;
+    const int64_t L = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+    const int nyb = (a.ny + SG2_WG_ROWS - 1) / SG2_WG_ROWS, ncg = a.nic3 * 32 / SGA_COLS;
+    const int64_t yt = (L % nyb) * SG_WAVES + wave;   // row tile of 16 y
+    const int i0 = (int)(SGA_COLS * ((L / nyb) % ncg)), zb = (int)(L / ((int64_t)nyb * ncg));
+    const int ncol = max(0, min(SGA_COLS, a.n - i0));           // columns inside the detector
+    // the thread's slot of each B tile: rows j = 8 fk + 4 fg + e (e = 0..3) at z = fz
+    const int fk = tid >> 6, fg = (tid >> 5) & 1, fz = tid & 31;
+    f32x4 P[SGA_COLS][3][2];
+#pragma unroll
+    for (int c = 0; c < SGA_COLS; ++c)
+#pragma unroll
+        for (int p = 0; p < 3; ++p) P[c][p][0] = P[c][p][1] = f32x4{};
+    if (ncol > 0) {
+        // h and Tz of chunk jc: Tz entries (w16, zb, hp, z, m) of the 16-row tile w16
+        // hold row 4 (m / 2) + 2 hp + (m % 2); rows 8 fk + 4 fg + e sit at hp = e / 2,
+        // m = 4 (fk % 2) + 2 fg + e % 2.  Loaded two chunks ahead of their use.
+        typedef f32x4 TzBuf[SGA_COLS][2];
+        typedef float2 HBuf[SGA_COLS][4];
+        // (a column beyond the detector, i >= N, gets zero tiles)
+        auto load_b = [&](int jc, TzBuf& tz, HBuf& hv) {
+#pragma unroll
+            for (int c = 0; c < SGA_COLS; ++c) {
+                const int64_t i = min(i0 + c, a.n - 1);
+                const int64_t w16 = i * (a.npad / SG2_ROWS) + 2 * jc + (fk >> 1);
+#pragma unroll
+                for (int hp = 0; hp < 2; ++hp)
+                    tz[c][hp] = *(const f32x4*)(a.tz + 2 * ((((w16 * a.nzb + zb) * 2 + hp) * ZB + fz) * 8 +
+                                                            4 * (fk & 1) + 2 * fg));
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    // always a load (from row j clamped into the detector); form_b
+                    // zeroes the rows beyond it
+                    const int64_t j = 32 * jc + 8 * fk + 4 * fg + e;
+                    hv[c][e] = ((const float2*)a.h)[min(j, (int64_t)a.n - 1) * a.n + i];
+                }
+            }
+        };
+        // B = h Tz of chunk jc in three planes, rows j = 8 fk + 4 fg + e of the tile at
+        // z = fz (zero for rows j >= N and columns i >= N)
+        auto form_b = [&](int jc, uint8_t* slot, const TzBuf& tz, const HBuf& hv) {
+#pragma unroll
+            for (int c = 0; c < SGA_COLS; ++c) {
+                f32x4 br, bi, bs;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const bool in = 32 * jc + 8 * fk + 4 * fg + e < a.n && c < ncol;
+                    const float hr = in ? hv[c][e].x : 0.0f, hi = in ? hv[c][e].y : 0.0f;
+                    const float tr = tz[c][e >> 1][2 * (e & 1)], ti = tz[c][e >> 1][2 * (e & 1) + 1];
+                    br[e] = hr * tr - hi * ti;
+                    bi[e] = hr * ti + hi * tr;
+                    bs[e] = br[e] + bi[e];
+                }
+                uint8_t* q = slot + c * G3_TILE_BYTES + ((fk * 2 + fg) * 32 + fz) * 16;
+                *(f32x4*)q = br;
+                *(f32x4*)(q + SG_PLANE_BYTES) = bi;
+                *(f32x4*)(q + 2 * SG_PLANE_BYTES) = bs;
+            }
+        };
+        const f32x4* ta = (const f32x4*)a.tyT + (size_t)yt * a.njc2 * 6 * 64 + lane;
+        f32x4 Ac[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) Ac[q] = ta[q * 64];
+        // chunk m's h and Tz live in buffer m % 2
+        TzBuf tz0, tz1;
+        HBuf h0, h1;
+        load_b(0, tz0, h0);
+        if (a.njc2 > 1) load_b(1, tz1, h1);
+        form_b(0, lds, tz0, h0);
+        __syncthreads();
+        // step jc: the MFMAs on the formed tiles of chunk jc, then chunk jc + 1's tiles
+        // formed from tzN, hN into the other LDS buffer; chunk jc + 2 loaded into the
+        // registers chunk jc left free
+        auto step = [&](int jc, const TzBuf& tzN, const HBuf& hN, TzBuf& tzF, HBuf& hF) {
+            const bool more = jc + 1 < a.njc2;
+            // the A operand first: waiting for it at the end of the step leaves the
+            // loads of chunk jc + 2 in flight
+            f32x4 An[6];
+            if (more) {
+#pragma unroll
+                for (int q = 0; q < 6; ++q) An[q] = ta[((jc + 1) * 6 + q) * 64];
+            }
+            if (jc + 2 < a.njc2) load_b(jc + 2, tzF, hF);
+            const uint8_t* cur = lds + (jc & 1) * SGA_COLS * G3_TILE_BYTES;
+            sga_tiles<SGA_COLS>(cur, kk, n16, Ac, P);
+            // the other buffer was last read before the previous barrier
+            if (more) form_b(jc + 1, lds + ((jc + 1) & 1) * SGA_COLS * G3_TILE_BYTES, tzN, hN);
+            __syncthreads();
+            if (more) {
+#pragma unroll
+                for (int q = 0; q < 6; ++q) Ac[q] = An[q];
+            }
+        };
+        for (int jc = 0; jc < a.njc2; jc += 2) {
+            step(jc, tz1, h1, tz0, h0);
+            if (jc + 1 < a.njc2) step(jc + 1, tz0, h0, tz1, h1);
+        }
+    }
+    // K = (P1 - P2) + i (P3 - P1 - P2) and Kr + Ki, planes of [i][y][z2] floats: 16
+    // lanes write 16 consecutive z
+    const size_t plane = (size_t)a.nic3 * 32 * a.ny * a.nz2;
+#pragma unroll
+    for (int c = 0; c < SGA_COLS; ++c) {
+        const int i = i0 + c;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t y = yt * SG2_ROWS + 4 * kk + r;
+            if (y < a.ny) {
+                float* k = a.kplain + ((size_t)i * a.ny + y) * a.nz2 + zb * ZB + n16;
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt) {
+                    const float kr = P[c][0][nt][r] - P[c][1][nt][r];
+                    const float ki = (P[c][2][nt][r] - P[c][0][nt][r]) - P[c][1][nt][r];
+                    k[16 * nt] = kr;
+                    k[plane + 16 * nt] = ki;
+                    k[2 * plane + 16 * nt] = kr + ki;
+                }
+            }
+        }
+    }
+}
+
+// Pass 2: R(x, y, z) = sum_i exp(-i q_x(i) x) K(i, y, z), as sg1_kernel (rows x of 32
+// per wave, 128 per workgroup, one y pair, one z block, one half of the i chunks)
+// with the B tiles built in LDS from the plain K planes: a thread gathers, for one
+// row (plane, i parity h, z) of a tile, the four i of one 16-byte slot (coalesced
+// over z across the lanes) and writes the slot with one LDS store.  The next tile's
+// values are loaded during the current tile's MFMAs.
+__global__ __launch_bounds__(SG_THREADS, 2) void sepg_adj_cols_kernel(SepG3AdjArgs a)
+{
+    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * G3_TILE_BYTES];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int h = lane >> 5, col = lane & 31;
+    const int64_t wt = (int64_t)blockIdx.x * SG_WAVES + wave;
+    const int zb = (int)(blockIdx.z % a.nzb), split = (int)(blockIdx.z / a.nzb);
+    const int per = (a.nic3 + SEPG_ADJ_SPLIT - 1) / SEPG_ADJ_SPLIT;
+    const int kc0 = split * per, kc1 = min(a.nic3, kc0 + per);
+    const int y0 = 2 * blockIdx.y;
+    const int nyh = min(2, a.ny - y0);   // >= 1
+    const size_t plane = (size_t)a.nic3 * 32 * a.ny * a.nz2;
+    // the thread's slots: (plane q, h, z = col, g = wave); i = 32 kc + 8 g + 2 e + h
+    auto load_tile = [&](int kc, int y, float (&v)[3][4]) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                v[q][e] = a.kplain[q * plane + ((size_t)(32 * kc + 8 * wave + 2 * e + h) * a.ny + y) * a.nz2 +
+                                   zb * ZB + col];
+    };
+    auto store_tile = [&](uint8_t* slot, const float (&v)[3][4]) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            *(f32x4*)(slot + q * SG_PLANE_BYTES + (h * ZB + col) * G3_ROW_BYTES + ((wave ^ ((col >> 1) & 3)) << 4)) =
+                f32x4{v[q][0], v[q][1], v[q][2], v[q][3]};
+    };
+    f32x16 P[2][3];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) P[u][q] = f32x16{};
+    if (kc0 < kc1) {
+        float v[3][4];
+        load_tile(kc0, y0, v);
+        store_tile(lds, v);
+        __syncthreads();
+        int k = 0;   // tiles consumed so far, in the order (kc, y); tile k sits in slot k & 1
+        for (int kc = kc0; kc < kc1; ++kc) {
+            f32x4 Af[12];
+            const f32x4* ta = (const f32x4*)(a.txT + (size_t)(wt * a.nic3 + kc) * G3_TILE_BYTES);
+#pragma unroll
+            for (int q = 0; q < 12; ++q) Af[q] = ta[q * 64 + lane];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                if (u < nyh) {
+                    const bool same = u + 1 < nyh;
+                    const bool more = same || kc + 1 < kc1;
+                    if (more) load_tile(same ? kc : kc + 1, same ? y0 + u + 1 : y0, v);
+                    sg1_tile(lds + (k & 1) * G3_TILE_BYTES + (h * ZB + col) * G3_ROW_BYTES, col, Af, P[u]);
+                    // the other slot was last read before the previous barrier
+                    if (more) store_tile(lds + ((k + 1) & 1) * G3_TILE_BYTES, v);
+                    __syncthreads();
+                    ++k;
+                }
+            }
+        }
+    }
+    // R = (P1 - P2) + i (P3 - P1 - P2): 32 lanes write 32 consecutive z
+    float2* out = (float2*)a.rpart + (size_t)split * a.rows_pad * a.ny * a.nz2 + zb * ZB + col;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int64_t x = wt * G3_WAVE_PIX + 8 * (r >> 2) + 4 * h + (r & 3);
+        if (x < a.nx) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                if (u < nyh)
+                    out[((size_t)x * a.ny + y0 + u) * a.nz2] =
+                        make_float2(P[u][0][r] - P[u][1][r], (P[u][2][r] - P[u][0][r]) - P[u][1][r]);
+        }
+    }
+}
+
 int grid_for(int64_t total, int block) { return (int)ceil_div(total, block); }
 
 template <int CPW>
@@ -438,19 +712,59 @@ int launch_sepg_twiddles(const SepDims& sd, int nx, int ny, int nxc3, const doub
     return (int)hipGetLastError();
 }
 
-// Both stages.  Stage 2 takes as many columns per workgroup as still leave two
-// workgroups per CU.
+// Both stages.  Stage 1 walks two y pairs per workgroup; stage 2 takes as many
+// columns per workgroup as still leave two workgroups per CU.
 int launch_sepg(const SepG3Args& a, void* stream)
 {
     hipStream_t s = (hipStream_t)stream;
     if (a.n <= 0 || a.nyc2 <= 0 || a.nyc2 > SG2_MAXYC || a.npad % SG2_WG_ROWS) return (int)hipErrorInvalidValue;
-    const dim3 g1((unsigned)a.nblk1, (unsigned)(a.nyc2 * 16 / SG1_PAIRS), (unsigned)a.nzb);
-    hipLaunchKernelGGL(sepg_stage1_kernel, g1, dim3(SG_THREADS), 0, s, a);
+    SG1Args g;
+    g.btiles = a.wtiles;
+    g.atab = a.txa1;
+    g.htiles = a.htiles;
+    g.nrows = a.n;
+    g.ny = a.ny;
+    g.nkc = a.nxc3;
+    g.nzb = a.nzb;
+    g.nyc2 = a.nyc2;
+    g.pairs = 2;
+    const dim3 g1((unsigned)a.nblk1, (unsigned)(a.nyc2 * 16 / g.pairs), (unsigned)a.nzb);
+    hipLaunchKernelGGL(sg1_kernel, g1, dim3(SG_THREADS), 0, s, g);
     const int64_t nrb = a.npad / SG2_WG_ROWS;
     if (ceil_div(a.n, 8) * nrb >= 2 * CHIP_CUS) launch_stage2<8>(a, s);
     else if (ceil_div(a.n, 4) * nrb >= 2 * CHIP_CUS) launch_stage2<4>(a, s);
     else if (ceil_div(a.n, 2) * nrb >= 2 * CHIP_CUS) launch_stage2<2>(a, s);
     else launch_stage2<1>(a, s);
+    return (int)hipGetLastError();
+}
+
+// The adjoint's tables: pass 1 A [16 rows y][j chunk] exp(-i q_y(j) y), pass 2 A
+// [32 rows x][i chunk] exp(-i q_x(i) x); ys, xs the voxel coordinates, qy, qx the
+// per-row and per-column components.
+int launch_sepg_adj_tables(const SepDims& sd, int nx, int ny, const double* xs, const double* qx,
+                           const double* ys, const double* qy, uint8_t* txT, uint8_t* tyT, void* stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    const int B = 256;
+    const int64_t n1 = (int64_t)sd.tyTg_bytes(ny) / 4;
+    hipLaunchKernelGGL(sg_twiddle_a2, dim3(grid_for(n1, B)), dim3(B), 0, s, (float*)tyT, n1, ny, sd.n, sd.nic3,
+                       ys, qy);
+    const int64_t n2 = (int64_t)sd.txTg_bytes(nx) / 4;
+    hipLaunchKernelGGL(sg_twiddle_a1, dim3(grid_for(n2, B)), dim3(B), 0, s, (float*)txT, n2, nx, sd.n, sd.nic3,
+                       xs, qx);
+    return (int)hipGetLastError();
+}
+
+// Both passes of the adjoint; R goes to a.rpart as two partial sums.
+int launch_sepg_adjoint(const SepG3AdjArgs& a, void* stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    if (a.n <= 0 || a.njc2 <= 0 || a.nic3 <= 0) return (int)hipErrorInvalidValue;
+    const dim3 g1((unsigned)(ceil_div(a.ny, SG2_WG_ROWS) * (a.nic3 * 32 / SGA_COLS) * a.nzb));
+    hipLaunchKernelGGL(sepg_adj_rows_kernel, g1, dim3(SG_THREADS), 0, s, a);
+    const dim3 g2((unsigned)ceil_div(a.nx, SG_WAVES * G3_WAVE_PIX), (unsigned)ceil_div(a.ny, 2),
+                  (unsigned)(a.nzb * SEPG_ADJ_SPLIT));
+    hipLaunchKernelGGL(sepg_adj_cols_kernel, g2, dim3(SG_THREADS), 0, s, a);
     return (int)hipGetLastError();
 }
 

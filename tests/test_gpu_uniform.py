@@ -151,11 +151,14 @@ def test_uniform_repeatable(env):
     assert np.array_equal(I1, I2)
 
 
-def test_uniform_backward_matches_oracle(env):
-    # the separable adjoint on a ragged uniform-q plan (pixels beyond the rim carry
-    # A = 0, N not a multiple of the column chunk)
+@pytest.mark.parametrize("grid,det,pitch", [((30, 26, 35), 24, (9.0, 8.0, 7.0)),
+                                             ((10, 140, 20), 37, (6.0, 5.0, 7.0))],
+                         ids=["three_product", "tall_y"])
+def test_uniform_backward_matches_oracle(env, grid, det, pitch):
+    # the separable adjoint on ragged uniform-q plans (pixels beyond the rim carry
+    # A = 0, N not a multiple of the column chunk); more than 128 rows y take FP32
+    # out of the three-product form
     torch, msft = env
-    grid, det, pitch = (30, 26, 35), 24, (9.0, 8.0, 7.0)
     d, b = _field(grid, 58)
     g = np.random.default_rng(59).normal(size=det * det)
     with msft.Plan(45.0, 60.0, det, grid, pitch, "fp32", "msft", detector="uniform_q") as plan:
