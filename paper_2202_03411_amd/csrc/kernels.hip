@@ -201,199 +201,186 @@ int launch_sep_twiddles(int precision, const Dims& d, const SepDims& sd, const d
     return (int)hipGetLastError();
 }
 
+// Four BF16 values as one 8-byte piece, first value lowest.
+__device__ __forceinline__ uint2 pack_bf16x4(__bf16 a, __bf16 b, __bf16 c, __bf16 d)
+{
+    union { __bf16 h[4]; uint2 u; } v;
+    v.h[0] = a;
+    v.h[1] = b;
+    v.h[2] = c;
+    v.h[3] = d;
+    return v.u;
+}
+
 // ---------------------------------------------------------------------------
 // Column scan (Eq. (8)) and effective strength (Eqs. (6), (9)).
 //
-// Workgroup (x chunk xc of 64 columns, y), 8 waves, four z blocks of 32 slices
-// per round: wave w takes z block zb0 + w / 2 of the columns 32 (w & 1) .. + 31.
-// Lanes run along z: a lane holds 4 consecutive slices of 4 columns 8 apart, and
-// the 8 lanes of a group cover the block's 32 slices of those columns (one
-// 128-byte line of delta and one of beta each), so every load instruction reads
-// whole lines.  The
-// exclusive prefix S = sum_{s'<s} (beta + i delta) of a slice is the carry of
-// the earlier rounds, plus the totals of the earlier z blocks of the round
-// (through LDS), plus an inclusive shuffle scan over the 8 lanes of the group,
-// plus the lane's own earlier slices.  Then
+// Workgroup (block of 32 columns x, y), 4 waves, four z blocks of 32 slices per
+// round: wave w takes z block zb0 + w of the 32 columns.  Lanes run along z: lane
+// (zs, cc) holds slices 4 zs .. 4 zs + 3 of the block for 4 columns, so the 8 lanes
+// of a group read one 128-byte line of delta and one of beta per column.  The
+// exclusive prefix S = sum_{s'<s} (beta + i delta) of a slice is the carry of the
+// earlier rounds, plus the totals of the earlier z blocks of the round (through
+// LDS), plus an inclusive shuffle scan over the 8 lanes of the group, plus the
+// lane's own earlier slices.  Then
 //   T = exp(-k0 dz (S_beta + i S_delta)),   w = dV chi T,
 //   chi = n^2 - 1 = delta (delta - 2) - beta^2 + 2 i beta (1 - delta)
-// (chi written without the cancelling "+1 -1") goes into an LDS copy of the W
-// tiles in their final layout, which the workgroup writes out with whole
-// 16-byte stores (each tile is one contiguous run in the workspace).
+// (chi written without the cancelling "+1 -1").  The lane's 4 columns are the 4 x
+// of one 16-byte slot of the W tile layout (x = 8 g + 2 e + h in the Gauss layout,
+// 4 consecutive x otherwise), so it writes w straight to the workspace: per slice,
+// one 16-byte slot per plane (Gauss, FP32) or per re/im row (FP32), two 8-byte
+// pieces per row (BF16 hi, lo).  Workgroups are small and need no staging, so
+// several share a CU and their loads, arithmetic and stores overlap.
 // ---------------------------------------------------------------------------
-#ifndef MSFT_SCAN_TRIVIAL
-#define MSFT_SCAN_TRIVIAL 0
-#endif
-constexpr int SCAN_THREADS = 512;
-constexpr int SCAN_ZROUND = 4;   // z blocks per round, two waves each
-
-template <int PREC>
-__device__ __forceinline__ void store_w(uint8_t* tile, int lane, int zl, float wr, float wi)
-{
-    if (PREC == MSFT_FP32) {
-        const int sub = (lane & 3) * 4;
-        *(float*)(tile + tile_slot_offset(0, zl, lane >> 2) + sub) = wr;
-        *(float*)(tile + tile_slot_offset(1, zl, lane >> 2) + sub) = wi;
-    } else {
-        const int sub = (lane & 7) * 2;
-        const __bf16 rh = (__bf16)wr, ih = (__bf16)wi;
-        const __bf16 rl = (__bf16)(wr - (float)rh), il = (__bf16)(wi - (float)ih);
-        *(__bf16*)(tile + tile_slot_offset(0, zl, lane >> 3) + sub) = rh;
-        *(__bf16*)(tile + tile_slot_offset(0, zl, 8 + (lane >> 3)) + sub) = rl;
-        *(__bf16*)(tile + tile_slot_offset(1, zl, lane >> 3) + sub) = ih;
-        *(__bf16*)(tile + tile_slot_offset(1, zl, 8 + (lane >> 3)) + sub) = il;
-    }
-}
-
-// The Gauss tile layout: rows (plane, h, z) of 4 slots of 4 floats, x = 8 g + 2 e + h
-// within the tile's G3_XC, slot g XOR-swizzled with (z / 2) % 4; planes Wr, Wi, Wr + Wi.
-__device__ __forceinline__ void store_w_g3(uint8_t* tile, int xl, int zl, float wr, float wi)
-{
-    const int h = xl & 1, e = (xl >> 1) & 3, g = xl >> 3;
-    const int off = (h * ZB + zl) * G3_ROW_BYTES + ((g ^ ((zl >> 1) & 3)) << 4) + 4 * e;
-    *(float*)(tile + off) = wr;
-    *(float*)(tile + 2 * ZB * G3_ROW_BYTES + off) = wi;
-    *(float*)(tile + 4 * ZB * G3_ROW_BYTES + off) = wr + wi;
-}
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_ZROUND = 4;   // z blocks per round, one wave each
+constexpr int SCAN_XB = 32;      // columns per workgroup
 
 template <int PREC, bool G3>
 __global__ __launch_bounds__(SCAN_THREADS) void scan_kernel(ScanArgs a)
 {
-    // one z block of the workgroup's 64 columns: one W tile, or two Gauss tiles
-    constexpr int STAGE_BYTES = G3 ? 2 * G3_TILE_BYTES : TILE_BYTES;
-    constexpr int STAGE_F4 = SCAN_ZROUND * STAGE_BYTES / 16;
-    constexpr int TILE_F4 = (G3 ? G3_TILE_BYTES : TILE_BYTES) / 16;
-    static_assert(STAGE_F4 % SCAN_THREADS == 0, "the staged tiles are copied in whole pieces");
-    __shared__ float tot[2][SCAN_ZROUND][XC];   // block totals of beta and delta per column
-    __shared__ __attribute__((aligned(16))) uint8_t stage[SCAN_ZROUND * STAGE_BYTES];
-    const int xc = blockIdx.x, y = blockIdx.y;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int half = wave & 1, zr = wave >> 1;
-    const int g = lane & 7, cc = lane >> 3;
+    __shared__ float tot[2][SCAN_ZROUND][SCAN_XB];   // block totals of beta and delta per column
+    const int xb = blockIdx.x, y = blockIdx.y;
+    const int tid = threadIdx.x, lane = tid & 63, zr = tid >> 6;
+    const int zs = lane & 7, cc = lane >> 3;
+    // the lane's columns within the block: one tile slot
+    auto col_of = [&](int e) { return G3 ? 8 * (cc >> 1) + 2 * e + (cc & 1) : 4 * cc + e; };
     const bool vec = (a.nz & 3) == 0;
     float carry_b[4], carry_d[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) carry_b[i] = carry_d[i] = 0.0f;
+    for (int e = 0; e < 4; ++e) carry_b[e] = carry_d[e] = 0.0f;
 
     for (int zb0 = 0; zb0 < a.nzb; zb0 += SCAN_ZROUND) {
         const int zb = zb0 + zr;
         const bool active = zb < a.nzb;
-        const int z0 = zb * ZB + 4 * g;
+        const int z0 = zb * ZB + 4 * zs;
         float d[4][4], b[4][4], sb[4], sd[4], ib[4], id[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int x = xc * XC + half * 32 + cc + 8 * i;
+        for (int e = 0; e < 4; ++e) {
+            const int x = xb * SCAN_XB + col_of(e);
             const size_t col = ((size_t)x * a.ny + y) * a.nz;
             if (active && x < a.nx && vec && z0 + 4 <= a.nz) {
                 const float4 dv = *(const float4*)(a.delta + col + z0);
                 const float4 bv = *(const float4*)(a.beta + col + z0);
-                d[i][0] = dv.x; d[i][1] = dv.y; d[i][2] = dv.z; d[i][3] = dv.w;
-                b[i][0] = bv.x; b[i][1] = bv.y; b[i][2] = bv.z; b[i][3] = bv.w;
+                d[e][0] = dv.x; d[e][1] = dv.y; d[e][2] = dv.z; d[e][3] = dv.w;
+                b[e][0] = bv.x; b[e][1] = bv.y; b[e][2] = bv.z; b[e][3] = bv.w;
             } else {
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     const bool in = active && x < a.nx && z0 + k < a.nz;
-                    d[i][k] = in ? a.delta[col + z0 + k] : 0.0f;
-                    b[i][k] = in ? a.beta[col + z0 + k] : 0.0f;
+                    d[e][k] = in ? a.delta[col + z0 + k] : 0.0f;
+                    b[e][k] = in ? a.beta[col + z0 + k] : 0.0f;
                 }
             }
-            sb[i] = (b[i][0] + b[i][1]) + (b[i][2] + b[i][3]);
-            sd[i] = (d[i][0] + d[i][1]) + (d[i][2] + d[i][3]);
+            sb[e] = (b[e][0] + b[e][1]) + (b[e][2] + b[e][3]);
+            sd[e] = (d[e][0] + d[e][1]) + (d[e][2] + d[e][3]);
             // inclusive scan over the 8 lanes (z segments) of the column's group
-            ib[i] = sb[i];
-            id[i] = sd[i];
+            ib[e] = sb[e];
+            id[e] = sd[e];
 #pragma unroll
             for (int off = 1; off < 8; off <<= 1) {
-                const float tb = __shfl_up(ib[i], off, 8), td = __shfl_up(id[i], off, 8);
-                if (g >= off) {
-                    ib[i] += tb;
-                    id[i] += td;
+                const float tb = __shfl_up(ib[e], off, 8), td = __shfl_up(id[e], off, 8);
+                if (zs >= off) {
+                    ib[e] += tb;
+                    id[e] += td;
                 }
             }
-            if (g == 7) {
-                tot[0][zr][half * 32 + cc + 8 * i] = ib[i];
-                tot[1][zr][half * 32 + cc + 8 * i] = id[i];
+            if (zs == 7) {
+                tot[0][zr][col_of(e)] = ib[e];
+                tot[1][zr][col_of(e)] = id[e];
             }
         }
         __syncthreads();
         float pb[4], pd[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int xl = half * 32 + cc + 8 * i;
-            float eb = carry_b[i], ed = carry_d[i];
+        for (int e = 0; e < 4; ++e) {
+            const int xl = col_of(e);
+            float eb = carry_b[e], ed = carry_d[e];
             for (int k = 0; k < zr; ++k) {
                 eb += tot[0][k][xl];
                 ed += tot[1][k][xl];
             }
-            pb[i] = eb + (ib[i] - sb[i]);
-            pd[i] = ed + (id[i] - sd[i]);
+            pb[e] = eb + (ib[e] - sb[e]);
+            pd[e] = ed + (id[e] - sd[e]);
             for (int k = zr; k < SCAN_ZROUND && zb0 + k < a.nzb; ++k) {
                 eb += tot[0][k][xl];
                 ed += tot[1][k][xl];
             }
-            carry_b[i] = eb;
-            carry_d[i] = ed;
+            carry_b[e] = eb;
+            carry_d[e] = ed;
         }
-        if (active) {
-            uint8_t* st = stage + zr * STAGE_BYTES + (G3 ? half * G3_TILE_BYTES : 0);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int xl = cc + 8 * i;   // column within the half
-                float Sb = pb[i], Sd = pd[i];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    float wr, wi;
-                    if (MSFT_SCAN_TRIVIAL || a.strength == MSFT_STRENGTH_DENSITY) {
-                        wr = a.dV * d[i][k] + (MSFT_SCAN_TRIVIAL ? Sb : 0.0f);
-                        wi = a.dV * b[i][k] + (MSFT_SCAN_TRIVIAL ? Sd : 0.0f);
-                    } else {
-                        const float chr = d[i][k] * (d[i][k] - 2.0f) - b[i][k] * b[i][k];
-                        const float chi = 2.0f * b[i][k] * (1.0f - d[i][k]);
-                        float tr = 1.0f, ti = 0.0f;
-                        if (a.strength == MSFT_STRENGTH_MSFT) {
-                            const float mag = expf(-a.k0dz * Sb);
-                            float sn, cs;
-                            sincosf(-a.k0dz * Sd, &sn, &cs);
-                            tr = mag * cs;
-                            ti = mag * sn;
-                        }
-                        wr = a.dV * (chr * tr - chi * ti);
-                        wi = a.dV * (chr * ti + chi * tr);
-                    }
-                    if (G3) store_w_g3(st, xl, 4 * g + k, wr, wi);
-                    else store_w<PREC>(st, half * 32 + xl, 4 * g + k, wr, wi);
-                    Sb += b[i][k];
-                    Sd += d[i][k];
-                }
-            }
-        }
+        // the next round rewrites tot only after every wave has read it
         __syncthreads();
-        // the round's tiles, LDS -> workspace
+        if (!active) continue;
+        float wr[4][4], wi[4][4];   // [slice k][column e]
 #pragma unroll
-        for (int u = 0; u < STAGE_F4 / SCAN_THREADS; ++u) {
-            const int q = u * SCAN_THREADS + tid;
-            const int tt = q / TILE_F4, off = q - tt * TILE_F4;
-            const int zk = G3 ? tt >> 1 : tt;
-            const int zbo = zb0 + zk;
-            if (zbo < a.nzb) {
-                if (G3) {
-                    const int xc3 = 2 * xc + (tt & 1);
-                    if (xc3 < a.nxc3)
-                        ((uint4*)(a.wtiles + ((size_t)(xc3 * a.nzb + zbo) * a.ny + y) * G3_TILE_BYTES))[off] =
-                            ((const uint4*)stage)[q];
+        for (int e = 0; e < 4; ++e) {
+            float Sb = pb[e], Sd = pd[e];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (a.strength == MSFT_STRENGTH_DENSITY) {
+                    wr[k][e] = a.dV * d[e][k];
+                    wi[k][e] = a.dV * b[e][k];
                 } else {
-                    ((uint4*)(a.wtiles + ((size_t)(xc * a.nzb + zbo) * a.ny + y) * TILE_BYTES))[off] =
-                        ((const uint4*)stage)[q];
+                    const float chr = d[e][k] * (d[e][k] - 2.0f) - b[e][k] * b[e][k];
+                    const float chi = 2.0f * b[e][k] * (1.0f - d[e][k]);
+                    float tr = 1.0f, ti = 0.0f;
+                    if (a.strength == MSFT_STRENGTH_MSFT) {
+                        const float mag = expf(-a.k0dz * Sb);
+                        float sn, cs;
+                        sincosf(-a.k0dz * Sd, &sn, &cs);
+                        tr = mag * cs;
+                        ti = mag * sn;
+                    }
+                    wr[k][e] = a.dV * (chr * tr - chi * ti);
+                    wi[k][e] = a.dV * (chr * ti + chi * tr);
+                }
+                Sb += b[e][k];
+                Sd += d[e][k];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int zl = 4 * zs + k;
+            if (G3) {
+                // Gauss tile (xb, zb, y): rows (plane, h, z) of 4 slots, slot g ^ ((z / 2) % 4)
+                uint8_t* row = a.wtiles + ((size_t)(xb * a.nzb + zb) * a.ny + y) * G3_TILE_BYTES +
+                               ((cc & 1) * ZB + zl) * G3_ROW_BYTES + (((cc >> 1) ^ ((zl >> 1) & 3)) << 4);
+                *(f32x4*)row = f32x4{wr[k][0], wr[k][1], wr[k][2], wr[k][3]};
+                *(f32x4*)(row + 2 * ZB * G3_ROW_BYTES) = f32x4{wi[k][0], wi[k][1], wi[k][2], wi[k][3]};
+                *(f32x4*)(row + 4 * ZB * G3_ROW_BYTES) = f32x4{wr[k][0] + wi[k][0], wr[k][1] + wi[k][1],
+                                                              wr[k][2] + wi[k][2], wr[k][3] + wi[k][3]};
+            } else {
+                // W tile (xb / 2, zb, y): x = 32 (xb % 2) + 4 cc + e of its 64
+                uint8_t* tile = a.wtiles + ((size_t)((xb >> 1) * a.nzb + zb) * a.ny + y) * TILE_BYTES;
+                const int xl = 32 * (xb & 1) + 4 * cc;
+                if (PREC == MSFT_FP32) {
+                    *(f32x4*)(tile + tile_slot_offset(0, zl, xl >> 2)) = f32x4{wr[k][0], wr[k][1], wr[k][2], wr[k][3]};
+                    *(f32x4*)(tile + tile_slot_offset(1, zl, xl >> 2)) = f32x4{wi[k][0], wi[k][1], wi[k][2], wi[k][3]};
+                } else {
+                    __bf16 rh[4], rl[4], ih[4], il[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        rh[e] = (__bf16)wr[k][e];
+                        rl[e] = (__bf16)(wr[k][e] - (float)rh[e]);
+                        ih[e] = (__bf16)wi[k][e];
+                        il[e] = (__bf16)(wi[k][e] - (float)ih[e]);
+                    }
+                    const int sub = (xl & 7) * 2;
+                    *(uint2*)(tile + tile_slot_offset(0, zl, xl >> 3) + sub) = pack_bf16x4(rh[0], rh[1], rh[2], rh[3]);
+                    *(uint2*)(tile + tile_slot_offset(0, zl, 8 + (xl >> 3)) + sub) = pack_bf16x4(rl[0], rl[1], rl[2], rl[3]);
+                    *(uint2*)(tile + tile_slot_offset(1, zl, xl >> 3) + sub) = pack_bf16x4(ih[0], ih[1], ih[2], ih[3]);
+                    *(uint2*)(tile + tile_slot_offset(1, zl, 8 + (xl >> 3)) + sub) = pack_bf16x4(il[0], il[1], il[2], il[3]);
                 }
             }
         }
-        __syncthreads();
     }
 }
 
 int launch_scan(int precision, const ScanArgs& a, void* stream)
 {
     hipStream_t s = (hipStream_t)stream;
-    dim3 grid(a.nxc, a.ny);
+    dim3 grid((unsigned)ceil_div(a.nx, SCAN_XB), a.ny);
     if (precision == MSFT_FP32 && a.g3)
         hipLaunchKernelGGL((scan_kernel<MSFT_FP32, true>), grid, dim3(SCAN_THREADS), 0, s, a);
     else if (precision == MSFT_FP32)
@@ -760,15 +747,6 @@ int launch_forward_batch(int precision, const BatchArgs& b, void* stream)
 // ---------------------------------------------------------------------------
 constexpr int S1_Y = 4;
 
-__device__ __forceinline__ uint2 pack_bf16x4(__bf16 a, __bf16 b, __bf16 c, __bf16 d)
-{
-    union { __bf16 h[4]; uint2 u; } v;
-    v.h[0] = a;
-    v.h[1] = b;
-    v.h[2] = c;
-    v.h[3] = d;
-    return v.u;
-}
 
 // Row (h, zl) of an H tile, y = yl .. yl + 3 (yl a multiple of 4).
 template <int PREC>
