@@ -139,11 +139,11 @@ struct SepDims {
     size_t k_bytes(int ny, int nzb) const { return (size_t)nic * nzb * ny * TILE_BYTES; }
     // FP32 with ny <= SG2_MAXYC * 32: the Gauss (three-product) form of both stages.
     // H tiles [i][y chunk of 32][z block] of G3_TILE_BYTES; A operands of stage 1
-    // [wave of 32 columns][x chunk of 32] (G3 layout), of stage 2 [16 rows j][y chunk].
+    // [16 columns i][x chunk of 32], of stage 2 [16 rows j][y chunk].
     bool gauss = false;
     int32_t nyc2 = 0;   // y chunks of 32
     size_t hg_bytes(int nzb) const { return (size_t)n * nyc2 * nzb * G3_TILE_BYTES; }
-    size_t txa1g_bytes(int nxc3) const { return (size_t)nblk1 * G3_WAVES * nxc3 * G3_TILE_BYTES; }
+    size_t txa1g_bytes(int nxc3) const { return (size_t)ceil_div(n, 64) * 4 * nxc3 * SG2_A_BYTES; }
     size_t txa2g_bytes() const { return (size_t)(npad / WAVE_PIX) * nyc2 * SG2_A_BYTES; }
     // ... and of its adjoint: chunks of 32 columns i (and of 32 rows j), K in three
     // planes [i][y][z], A tables of the two passes.

@@ -85,10 +85,13 @@ __global__ void sg_twiddle_a1(float* t, int64_t total, int n, int nx, int nxc3, 
     t[idx] = (i < n && x < nx) ? plane_value(-(qx[i] * xs[x]), plane) : 0.0f;
 }
 
-// Stage 2: [jt][yc][plane 3][g 2][lane 64][e 4]; lane (kk, m) holds row
-// j = 16 jt + m at y = 32 yc + 8 kk + 4 g + e for MFMA step 4 g + e of chunk yc.
+// 16x16x4 A operand [jt][chunk kc][plane 3][g 2][lane 64][e 4]: lane (kk, m) holds row
+// r = 16 jt + m at K index k = 32 kc + 8 kk + 4 g + e (the H tile order; stage 2, and
+// the adjoint's first pass) or, with wlay, k = 32 kc + 8 (2 g + kk / 2) + 2 e + kk % 2
+// (the Gauss W tile order; stage 1), for MFMA step 4 g + e of chunk kc.  Value: the
+// plane of exp(-i qy[r] ys[k]).
 __global__ void sg_twiddle_a2(float* t, int64_t total, int n, int ny, int nyc2, const double* qy,
-                              const double* ys)
+                              const double* ys, int wlay)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total) return;
@@ -100,36 +103,14 @@ __global__ void sg_twiddle_a2(float* t, int64_t total, int n, int ny, int nyc2, 
     const int yc = (int)(tile % nyc2);
     const int64_t jt = tile / nyc2;
     const int64_t j = jt * SG2_ROWS + (lane & 15);
-    const int y = yc * 32 + 8 * (lane >> 4) + 4 * g + e;
+    const int kk = lane >> 4;
+    const int y = yc * 32 + (wlay ? 8 * (2 * g + (kk >> 1)) + 2 * e + (kk & 1) : 8 * kk + 4 * g + e);
     t[idx] = (j < n && y < ny) ? plane_value(-(qy[j] * ys[y]), plane) : 0.0f;
 }
 
 // ---------------------------------------------------------------------------
 // Stage 1.
 // ---------------------------------------------------------------------------
-
-// Stage 1, H(i, y, z) = sum_x A(i, x) W(x, y, z): rows i of 32 per wave and 128 per
-// workgroup, two consecutive y per pass and `pairs` passes per workgroup, one z
-// block; H goes to stage 2's tiles.
-struct SG1Args {
-    const uint8_t* btiles;  // W tiles (G3 layout), index (kc * nzb + zb) * ny + y
-    const uint8_t* atab;    // A tiles [wave of 32 rows][kc], G3_TILE_BYTES each
-    uint8_t* htiles;        // H tiles [row][yc][zb]
-    int32_t nrows, ny, nkc, nzb, nyc2, pairs;
-};
-
-// B tile (kc, zb, y) into an LDS slot: three 16-byte pieces per thread (wave: the
-// wave index as a wave-uniform value, so the addresses stay scalar).
-__device__ __forceinline__ void sg1_fill(const SG1Args& a, int kc, int zb, int y, int wave, uint8_t* slot)
-{
-    const int lane = threadIdx.x & 63;
-    const u32x4* src = (const u32x4*)(a.btiles + ((size_t)(kc * a.nzb + zb) * a.ny + y) * G3_TILE_BYTES);
-#pragma unroll
-    for (int c = 0; c < SG1_COPY; ++c) {
-        const int q = c * SG_THREADS + wave * 64;   // piece of the wave's lane 0
-        lds_dma16(src + q + lane, slot + q * 16);
-    }
-}
 
 // P += the three products of one W tile (all 32 x; the tables are zero beyond nx).
 // The next step group's B fragments are read from LDS before the current group's
@@ -156,63 +137,113 @@ __device__ __forceinline__ void sg1_tile(const uint8_t* row, int col, const f32x
     }
 }
 
-// Grid (row blocks of 128, groups of `pairs` y pairs over nyc2 * 32, z blocks): the
-// workgroup walks its y pairs one after the other with the tile ring running on
-// across them.  Rows y >= ny of the H tiles are written as zeros; rows i >= nrows
-// are not stored.
-__global__ __launch_bounds__(SG_THREADS, 2) void sg1_kernel(SG1Args a)
+// Stage 1, H(i, y, z) = sum_x Tx(i, x) W(x, y, z), on v_mfma_f32_16x16x4_f32: rows
+// are a wave's 16 columns i, columns 16 z, K four x (lane (kk, n16) reads row (plane,
+// x parity kk % 2, z) of the Gauss W tile, slot 2 g + kk / 2: x = 8 (2 g + kk / 2) +
+// 2 e + kk % 2).  A workgroup of 4 waves takes 64 columns, one z block and SG1_QUADS
+// quads of 4 consecutive y in turn; per quad the x chunks run through the two-slot
+// LDS ring two tiles (two y) per stage, the sums over x stay in the accumulators,
+// and each lane then holds, for its 4 columns and 2 z, the quad's 4 y: one 16-byte
+// slot of an H tile per plane, 16 lanes writing 256 consecutive bytes.
+constexpr int SG1_QUADS = 2;
+
+// The stage (x chunk xc, y pair y, y + 1 of the quad) into an LDS slot of two W
+// tiles: six pieces per thread (the second tile is the first again past ny).
+__device__ __forceinline__ void sg1_fill(const SepG3Args& a, int xc, int zb, int y, int wave, uint8_t* slot)
 {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * G3_TILE_BYTES];
+    const int lane = threadIdx.x & 63;
+    const uint8_t* t0 = a.wtiles + ((size_t)(xc * a.nzb + zb) * a.ny + y) * G3_TILE_BYTES;
+    const uint8_t* t1 = y + 1 < a.ny ? t0 + G3_TILE_BYTES : t0;
+#pragma unroll
+    for (int p = 0; p < SG2_COPY; ++p) {
+        const int q = (p % SG1_COPY) * SG_THREADS + wave * 64;   // piece of the wave's lane 0 in its tile
+        const u32x4* src = (const u32x4*)(p < SG1_COPY ? t0 : t1);
+        lds_dma16(src + q + lane, slot + (p < SG1_COPY ? 0 : G3_TILE_BYTES) + q * 16);
+    }
+}
+
+// P[u][plane][n tile] += the products of the two W tiles of a stage (y of the quad
+// u0, u0 + 1) with the wave's A operand for that x chunk: Af[2 plane + g], step 4 g + e.
+__device__ __forceinline__ void sg1_stage(const uint8_t* slot, int kk, int n16, const f32x4 (&Af)[6],
+                                          f32x4 (&P0)[3][2], f32x4 (&P1)[3][2])
+{
+    // B fragment of lane (kk, n16) for tile t, plane p, g, n tile nt: row (p, kk % 2, z)
+    auto frag = [&](int t, int p, int g, int nt) {
+        const int z = 16 * nt + n16;
+        return *(const f32x4*)(slot + t * G3_TILE_BYTES + p * SG_PLANE_BYTES + ((kk & 1) * ZB + z) * G3_ROW_BYTES +
+                               (((2 * g + (kk >> 1)) ^ ((z >> 1) & 3)) << 4));
+    };
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        f32x4 (&P)[3][2] = t == 0 ? P0 : P1;
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+#pragma unroll
+            for (int p = 0; p < 3; ++p) {
+                const f32x4 b0 = frag(t, p, g, 0), b1 = frag(t, p, g, 1);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    P[p][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(Af[2 * p + g][e], b0[e], P[p][0], 0, 0, 0);
+                    P[p][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(Af[2 * p + g][e], b1[e], P[p][1], 0, 0, 0);
+                }
+            }
+        }
+    }
+}
+
+// Grid (column blocks of 64, groups of SG1_QUADS y quads over nyc2 * 32, z blocks).
+// Rows y >= ny of the H tiles are written as zeros; columns i >= N are not stored.
+__global__ __launch_bounds__(SG_THREADS, 2) void sepg_stage1_kernel(SepG3Args a)
+{
+    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * SG2_STAGE];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int h = lane >> 5, col = lane & 31;
-    const int64_t wt = (int64_t)blockIdx.x * SG_WAVES + wave;
+    const int kk = lane >> 4, n16 = lane & 15;
+    const int64_t wt = (int64_t)blockIdx.x * SG_WAVES + wave;   // 16 columns
     const int zb = blockIdx.z;
-    const int kc0 = 0, kc1 = a.nkc;
-    const int ybase = 2 * a.pairs * blockIdx.y;
-    const int yend = min(a.ny, ybase + 2 * a.pairs);   // rows y of this workgroup: [ybase, yend)
-    // the tile after (pair p, kc, u) in the order (pair, kc, y)
-    auto next_tile = [&](int y0, int kc, int u, int& kn, int& yn) {
-        const int nyh = min(2, a.ny - y0);
-        if (u + 1 < nyh) {
-            kn = kc;
-            yn = y0 + u + 1;
-        } else if (kc + 1 < kc1) {
-            kn = kc + 1;
+    const int ybase = 4 * SG1_QUADS * blockIdx.y;
+    const int yend = min(a.ny, ybase + 4 * SG1_QUADS);   // rows y of this workgroup: [ybase, yend)
+    const f32x4* ta = (const f32x4*)a.txa1 + (size_t)wt * a.nxc3 * 6 * 64 + lane;
+    // stages (quad, xc, y pair) in that order; the one after (quad q, xc, pair v)
+    auto next_stage = [&](int y0, int xc, int v, int& xn, int& yn) {
+        if (v == 0 && y0 + 2 < min(yend, y0 + 4)) {
+            xn = xc;
+            yn = y0 + 2;
+        } else if (xc + 1 < a.nxc3) {
+            xn = xc + 1;
             yn = y0;
         } else {
-            kn = kc0;
-            yn = y0 + 2;
+            xn = 0;
+            yn = y0 + 4;
         }
     };
-    if (ybase < yend && kc0 < kc1) {
-        sg1_fill(a, kc0, zb, ybase, wave, lds);
+    if (ybase < yend) {
+        sg1_fill(a, 0, zb, ybase, wave, lds);
         __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
         __syncthreads();
     }
-    int k = 0;   // tiles consumed so far; tile k sits in slot k & 1
+    int k = 0;   // stages consumed so far; stage k sits in slot k & 1
 #pragma unroll 1
-    for (int p = 0; p < a.pairs; ++p) {
-        const int y0 = ybase + 2 * p;
-        const int nyh = max(0, min(2, a.ny - y0));   // y of this pair inside the grid
-        f32x16 P[2][3];
+    for (int qd = 0; qd < SG1_QUADS; ++qd) {
+        const int y0 = ybase + 4 * qd;
+        const int nyq = max(0, min(4, a.ny - y0));   // y of this quad inside the grid
+        f32x4 P[4][3][2];
 #pragma unroll
-        for (int u = 0; u < 2; ++u)
+        for (int u = 0; u < 4; ++u)
 #pragma unroll
-            for (int q = 0; q < 3; ++q) P[u][q] = f32x16{};
-        for (int kc = kc0; kc < kc1 && nyh > 0; ++kc) {
-            f32x4 Af[12];
-            const f32x4* ta = (const f32x4*)(a.atab + (size_t)(wt * a.nkc + kc) * G3_TILE_BYTES);
+            for (int p = 0; p < 3; ++p) P[u][p][0] = P[u][p][1] = f32x4{};
+        for (int xc = 0; xc < a.nxc3 && nyq > 0; ++xc) {
+            f32x4 Af[6];
 #pragma unroll
-            for (int q = 0; q < 12; ++q) Af[q] = ta[q * 64 + lane];
+            for (int q = 0; q < 6; ++q) Af[q] = ta[(xc * 6 + q) * 64];
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                if (u < nyh) {
-                    int kn, yn;
-                    next_tile(y0, kc, u, kn, yn);
-                    if (yn < yend) sg1_fill(a, kn, zb, yn, wave, lds + ((k + 1) & 1) * G3_TILE_BYTES);
-                    sg1_tile(lds + (k & 1) * G3_TILE_BYTES + (h * ZB + col) * G3_ROW_BYTES, col, Af, P[u]);
+            for (int v = 0; v < 2; ++v) {
+                if (2 * v < nyq) {
+                    int xn, yn;
+                    next_stage(y0, xc, v, xn, yn);
+                    if (yn < yend) sg1_fill(a, xn, zb, yn, wave, lds + ((k + 1) & 1) * SG2_STAGE);
+                    sg1_stage(lds + (k & 1) * SG2_STAGE, kk, n16, Af, P[2 * v], P[2 * v + 1]);
                     // the next slot's loads have landed (the compiler does not track them)
                     __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
                     __syncthreads();
@@ -220,25 +251,31 @@ __global__ __launch_bounds__(SG_THREADS, 2) void sg1_kernel(SG1Args a)
                 }
             }
         }
-        // H = (P1 - P2) + i (P3 - P1 - P2) and Hr + Hi at y0, y0 + 1: 8 bytes per plane
+        // H = (P1 - P2) + i (P3 - P1 - P2) and Hr + Hi at y0 .. y0 + 3 of column i, z:
+        // the 16-byte slot (kk', g') = ((y0 % 32) / 8, (y0 % 8) / 4) of row z
         const int yc = y0 >> 5, yl = y0 & 31;
-        const int off = (((yl >> 3) * 2 + ((yl >> 2) & 1)) * 32 + col) * 16 + 4 * (yl & 3);
-        uint8_t* hcol = a.htiles + ((size_t)yc * a.nzb + zb) * G3_TILE_BYTES + off;
         const size_t col_stride = (size_t)a.nyc2 * a.nzb * G3_TILE_BYTES;
+        uint8_t* hbase = a.htiles + ((size_t)yc * a.nzb + zb) * G3_TILE_BYTES + (((yl >> 3) * 2 + ((yl >> 2) & 1)) * 32 + n16) * 16;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int64_t i = wt * G3_WAVE_PIX + 8 * (r >> 2) + 4 * h + (r & 3);
-            if (i < a.nrows) {
-                float hr[2], hi[2];
+        for (int r = 0; r < 4; ++r) {
+            const int64_t i = wt * SG2_ROWS + 4 * kk + r;
+            if (i < a.n) {
 #pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    hr[u] = P[u][0][r] - P[u][1][r];
-                    hi[u] = (P[u][2][r] - P[u][0][r]) - P[u][1][r];
+                for (int nt = 0; nt < 2; ++nt) {
+                    f32x4 hr, hi, hs;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        // (a y beyond ny summed a repeated tile: its row is zero)
+                        const bool in = u < nyq;
+                        hr[u] = in ? P[u][0][nt][r] - P[u][1][nt][r] : 0.0f;
+                        hi[u] = in ? (P[u][2][nt][r] - P[u][0][nt][r]) - P[u][1][nt][r] : 0.0f;
+                        hs[u] = hr[u] + hi[u];
+                    }
+                    uint8_t* t = hbase + i * col_stride + nt * 256;
+                    *(f32x4*)t = hr;
+                    *(f32x4*)(t + SG_PLANE_BYTES) = hi;
+                    *(f32x4*)(t + 2 * SG_PLANE_BYTES) = hs;
                 }
-                uint8_t* tile = hcol + i * col_stride;
-                *(float2*)tile = make_float2(hr[0], hr[1]);
-                *(float2*)(tile + SG_PLANE_BYTES) = make_float2(hi[0], hi[1]);
-                *(float2*)(tile + 2 * SG_PLANE_BYTES) = make_float2(hr[0] + hi[0], hr[1] + hi[1]);
             }
         }
     }
@@ -604,7 +641,7 @@ __global__ __launch_bounds__(SG_THREADS, 2) void sepg_adj_rows_kernel(SepG3AdjAr
     }
 }
 
-// Pass 2: R(x, y, z) = sum_i exp(-i q_x(i) x) K(i, y, z), as sg1_kernel (rows x of 32
+// Pass 2: R(x, y, z) = sum_i exp(-i q_x(i) x) K(i, y, z), on the 32x32x2 Gauss block (rows x of 32
 // per wave, 128 per workgroup, one y pair, one z block, one half of the i chunks)
 // with the B tiles built in LDS from the plain K planes: a thread gathers, for one
 // row (plane, i parity h, z) of a tile, the four i of one 16-byte slot (coalesced
@@ -704,32 +741,23 @@ int launch_sepg_twiddles(const SepDims& sd, int nx, int ny, int nxc3, const doub
     hipStream_t s = (hipStream_t)stream;
     const int B = 256;
     const int64_t n1 = (int64_t)sd.txa1g_bytes(nxc3) / 4;
-    hipLaunchKernelGGL(sg_twiddle_a1, dim3(grid_for(n1, B)), dim3(B), 0, s, (float*)txa1, n1, sd.n, nx,
-                       nxc3, qx, xs);
+    hipLaunchKernelGGL(sg_twiddle_a2, dim3(grid_for(n1, B)), dim3(B), 0, s, (float*)txa1, n1, sd.n, nx,
+                       nxc3, qx, xs, 1);
     const int64_t n2 = (int64_t)sd.txa2g_bytes() / 4;
     hipLaunchKernelGGL(sg_twiddle_a2, dim3(grid_for(n2, B)), dim3(B), 0, s, (float*)txa2, n2, sd.n, ny,
-                       sd.nyc2, qy, ys);
+                       sd.nyc2, qy, ys, 0);
     return (int)hipGetLastError();
 }
 
-// Both stages.  Stage 1 walks two y pairs per workgroup; stage 2 takes as many
+// Both stages.  Stage 1 walks two y quads per workgroup; stage 2 takes as many
 // columns per workgroup as still leave two workgroups per CU.
 int launch_sepg(const SepG3Args& a, void* stream)
 {
     hipStream_t s = (hipStream_t)stream;
     if (a.n <= 0 || a.nyc2 <= 0 || a.nyc2 > SG2_MAXYC || a.npad % SG2_WG_ROWS) return (int)hipErrorInvalidValue;
-    SG1Args g;
-    g.btiles = a.wtiles;
-    g.atab = a.txa1;
-    g.htiles = a.htiles;
-    g.nrows = a.n;
-    g.ny = a.ny;
-    g.nkc = a.nxc3;
-    g.nzb = a.nzb;
-    g.nyc2 = a.nyc2;
-    g.pairs = 2;
-    const dim3 g1((unsigned)a.nblk1, (unsigned)(a.nyc2 * 16 / g.pairs), (unsigned)a.nzb);
-    hipLaunchKernelGGL(sg1_kernel, g1, dim3(SG_THREADS), 0, s, g);
+    const dim3 g1((unsigned)ceil_div(a.n, SG_WAVES * SG2_ROWS), (unsigned)(a.nyc2 * 32 / (4 * SG1_QUADS)),
+                  (unsigned)a.nzb);
+    hipLaunchKernelGGL(sepg_stage1_kernel, g1, dim3(SG_THREADS), 0, s, a);
     const int64_t nrb = a.npad / SG2_WG_ROWS;
     if (ceil_div(a.n, 8) * nrb >= 2 * CHIP_CUS) launch_stage2<8>(a, s);
     else if (ceil_div(a.n, 4) * nrb >= 2 * CHIP_CUS) launch_stage2<4>(a, s);
@@ -748,7 +776,7 @@ int launch_sepg_adj_tables(const SepDims& sd, int nx, int ny, const double* xs, 
     const int B = 256;
     const int64_t n1 = (int64_t)sd.tyTg_bytes(ny) / 4;
     hipLaunchKernelGGL(sg_twiddle_a2, dim3(grid_for(n1, B)), dim3(B), 0, s, (float*)tyT, n1, ny, sd.n, sd.nic3,
-                       ys, qy);
+                       ys, qy, 0);
     const int64_t n2 = (int64_t)sd.txTg_bytes(nx) / 4;
     hipLaunchKernelGGL(sg_twiddle_a1, dim3(grid_for(n2, B)), dim3(B), 0, s, (float*)txT, n2, nx, sd.n, sd.nic3,
                        xs, qx);
