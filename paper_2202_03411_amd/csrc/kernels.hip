@@ -858,6 +858,150 @@ __global__ __launch_bounds__(512, NY == 1 ? 4 : 2) void sep_stage1_kernel(Stage1
     }
 }
 
+// Four-wave workgroups of the BF16 separable stages: 64 rows (columns i in stage 1,
+// rows j in stage 2), pipeline stages of two W or H tiles.  SR_YC: chunks whose A
+// operands a wave keeps resident.
+constexpr int SR_YC = 2;
+constexpr int SP_WAVES = 4;
+constexpr int SP_THREADS = 64 * SP_WAVES;
+constexpr int SP_ROWS = SP_WAVES * WAVE_PIX;                  // 64 rows j per workgroup
+constexpr int SP_STAGE = 2 * TILE_BYTES;                      // both y chunks
+constexpr int SP_COPY = SP_STAGE / 16 / SP_THREADS;           // 8 pieces per thread, 4 per tile
+static_assert(SP_COPY * SP_THREADS * 16 == SP_STAGE && (TILE_BYTES / 16) % 64 == 0, "whole wave pieces");
+
+// ---------------------------------------------------------------------------
+// First stage for the BF16 precisions: workgroups of 4 waves (64 columns i) walk
+// SP1_PASSES passes of SP1_Y = 8 consecutive y; per pass and x chunk the wave loads
+// its A operand and four pipeline stages follow, each with the W tiles of two y
+// (direct global -> LDS loads into a two-slot ring, 48 MFMAs per wave and
+// barrier).  Each lane then holds 8 consecutive y of its columns at one z: one whole
+// 16-byte slot of an H row per (column, re|im, hi|lo).  Two workgroups share a CU.
+// ---------------------------------------------------------------------------
+constexpr int SP1_Y = 8;
+constexpr int SP1_PASSES = 1;
+
+// The stage (x chunk xc, y and y + 1): two W tiles of z block zb (the first again
+// past ny, so every stage issues SP_COPY pieces).
+__device__ __forceinline__ void sp1_fill(const Stage1Args& a, int xc, int zb, int y, int wave, uint8_t* slot)
+{
+    const int lane = threadIdx.x & 63;
+    const uint8_t* t0 = a.wtiles + ((size_t)(xc * a.nzb + zb) * a.ny + y) * TILE_BYTES;
+    const uint8_t* t1 = y + 1 < a.ny ? t0 + TILE_BYTES : t0;
+    constexpr int PER = SP_COPY / 2;
+#pragma unroll
+    for (int p = 0; p < SP_COPY; ++p) {
+        const int q = (p % PER) * SP_THREADS + wave * 64;   // piece of the wave's lane 0 in its tile
+        lds_dma16((const u32x4*)(p < PER ? t0 : t1) + q + lane, slot + (p < PER ? 0 : TILE_BYTES) + q * 16);
+    }
+}
+
+// Eight values as the BF16 hi and lo slots of one 16-byte piece each (value e in
+// bits 16 (e % 2) of word e / 2).
+__device__ __forceinline__ void split_bf16x8(const float* v, u32x4& hi, u32x4& lo)
+{
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const __bf16 h0 = (__bf16)v[2 * w], h1 = (__bf16)v[2 * w + 1];
+        const __bf16 l0 = (__bf16)(v[2 * w] - (float)h0), l1 = (__bf16)(v[2 * w + 1] - (float)h1);
+        hi[w] = (uint32_t)__builtin_bit_cast(uint16_t, h0) | ((uint32_t)__builtin_bit_cast(uint16_t, h1) << 16);
+        lo[w] = (uint32_t)__builtin_bit_cast(uint16_t, l0) | ((uint32_t)__builtin_bit_cast(uint16_t, l1) << 16);
+    }
+}
+
+// Grid (column blocks of 64, groups of SP1_PASSES passes over nyc * 64, z blocks);
+// rows y >= ny of the H tiles are written as zeros.
+template <int PREC>
+__global__ __launch_bounds__(SP_THREADS, 2) void sep_stage1p_kernel(Stage1Args a)
+{
+    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * SP_STAGE];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int h = lane >> 5, col = lane & 31;
+    const int64_t wt = (int64_t)blockIdx.x * SP_WAVES + wave;   // 16 columns
+    const int zb = blockIdx.z;
+    const int ybase = SP1_Y * SP1_PASSES * blockIdx.y;
+    const int yend = min(a.ny, ybase + SP1_Y * SP1_PASSES);
+    // stages (pass, xc, y pair); the one after (pass from y0, xc, pair v)
+    auto next_stage = [&](int y0, int xc, int v, int& xn, int& yn) {
+        if (y0 + 2 * v + 2 < min(yend, y0 + SP1_Y)) {
+            xn = xc;
+            yn = y0 + 2 * v + 2;
+        } else if (xc + 1 < a.nxc) {
+            xn = xc + 1;
+            yn = y0;
+        } else {
+            xn = 0;
+            yn = y0 + SP1_Y;
+        }
+    };
+    if (ybase < yend) {
+        sp1_fill(a, 0, zb, ybase, wave, lds);
+        __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+        __syncthreads();
+    }
+    int k = 0;   // stages consumed; stage k sits in slot k & 1
+#pragma unroll 1
+    for (int ps = 0; ps < SP1_PASSES; ++ps) {
+        const int y0 = ybase + SP1_Y * ps;
+        const int nyp = max(0, min(SP1_Y, a.ny - y0));
+        f32x16 C[SP1_Y];
+#pragma unroll
+        for (int u = 0; u < SP1_Y; ++u) C[u] = f32x16{};
+        for (int xc = 0; xc < a.nxc && nyp > 0; ++xc) {
+            f32x4 Af[16];
+            bf16x8 Ahi[8], Alo[8];
+            load_a<PREC>(a.txa + (size_t)(wt * a.nxc + xc) * TILE_BYTES, lane, Af, Ahi, Alo);
+            const int xlen = min(XC, a.x_pad - xc * XC);
+#pragma unroll
+            for (int v = 0; v < SP1_Y / 2; ++v) {
+                if (2 * v < nyp) {
+                    int xn, yn;
+                    next_stage(y0, xc, v, xn, yn);
+                    if (yn < yend) sp1_fill(a, xn, zb, yn, wave, lds + ((k + 1) & 1) * SP_STAGE);
+                    const uint8_t* cur = lds + (k & 1) * SP_STAGE + (h * ZB + col) * ROW_BYTES;
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) {
+                        if (xlen == XC)
+                            C[2 * v + t] = tile_mfma<PREC, XC>(C[2 * v + t], cur + t * TILE_BYTES, col, Af, Ahi, Alo);
+                        else
+                            C[2 * v + t] = tile_mfma_partial<PREC>(C[2 * v + t], cur + t * TILE_BYTES, col, xlen, Af,
+                                                                   Ahi, Alo);
+                    }
+                    // the next slot's loads have landed (the compiler does not track them)
+                    __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+                    __syncthreads();
+                    ++k;
+                }
+            }
+        }
+        // H slots: row (re|im, z) of tile (i, y0 / 64, zb), hi slot (y0 % 64) / 8, lo slot 8 + that
+        const int yc = y0 / XC, ys = (y0 - yc * XC) >> 3;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const int64_t i = slot_pixel(wt, h, m);
+            if (i < a.n) {
+                const int r = 4 * (m >> 1) + 2 * (m & 1);
+                float re[SP1_Y], im[SP1_Y];
+#pragma unroll
+                for (int u = 0; u < SP1_Y; ++u) {
+                    // (a y beyond ny summed a repeated tile: its row is zero)
+                    re[u] = u < nyp ? C[u][r] : 0.0f;
+                    im[u] = u < nyp ? C[u][r + 1] : 0.0f;
+                }
+                uint8_t* tile = a.htiles + ((size_t)(i * a.nyc + yc) * a.nzb + zb) * TILE_BYTES;
+                u32x4 hi, lo;
+                split_bf16x8(re, hi, lo);
+                *(u32x4*)(tile + tile_slot_offset(0, col, ys)) = hi;
+                *(u32x4*)(tile + tile_slot_offset(0, col, 8 + ys)) = lo;
+                split_bf16x8(im, hi, lo);
+                *(u32x4*)(tile + tile_slot_offset(1, col, ys)) = hi;
+                *(u32x4*)(tile + tile_slot_offset(1, col, 8 + ys)) = lo;
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Second stage of the separable detector: A(i, j) = sum_z Tz(i, j, z) sum_y
 // exp(-i q_y(j) y) H(i, y, z).  The A operand, exp(-i q_y(j) y) for the 16 rows j
@@ -996,7 +1140,6 @@ __global__ __launch_bounds__(512) void sep_stage2_kernel(FwdArgs a)
 // butterfly and store follow.  H tiles stream through the double-buffered LDS
 // ring in the order (column, z block, y chunk).
 // ---------------------------------------------------------------------------
-constexpr int SR_YC = 2;
 
 template <int PREC, int CPW>
 __global__ __launch_bounds__(512) void sep_stage2r_kernel(FwdArgs a)
@@ -1094,6 +1237,124 @@ __global__ __launch_bounds__(512) void sep_stage2r_kernel(FwdArgs a)
         }
         if (col == 0) {
             const int64_t i = i0 + c;
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                const int64_t j = slot_pixel(wt, h, m) - i * a.out_npad;
+                if (j < a.out_n) {
+                    const int64_t out = j * a.out_n + i;
+                    const float re = acc[2 * m], im = acc[2 * m + 1];
+                    a.intensity[out] = re * re + im * im;
+                    if (a.amplitude) ((float2*)a.amplitude)[out] = make_float2(re, im);
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Second stage for the BF16 precisions with at most two y chunks: workgroups of 4
+// waves (64 rows j, CPW columns i) with both chunks' A operands resident; each
+// pipeline stage is one (column, z block) with the H tiles of both chunks, filled
+// by direct global -> LDS loads into a two-slot ring, so one barrier covers 48
+// MFMAs per wave; two workgroups share a CU, and the row blocks of a column group
+// run on one XCD (workgroup b runs on XCD b % 8) so that each H tile comes from HBM
+// about once.  Same tile products, rotations and butterfly as sep_stage2r_kernel.
+// ---------------------------------------------------------------------------
+
+// The stage of column i, z block zb: tiles (y chunk 0, 1) of the column's group into
+// an LDS slot (with one chunk, its tile twice, so every stage issues SP_COPY pieces).
+__device__ __forceinline__ void sp_fill(const FwdArgs& a, int64_t i, int zb, int wave, uint8_t* slot)
+{
+    const int lane = threadIdx.x & 63;
+    const uint8_t* t0 = a.wtiles + ((size_t)i * a.group_tiles + zb) * TILE_BYTES;
+    const uint8_t* t1 = a.nxc > 1 ? t0 + (size_t)a.nzb * TILE_BYTES : t0;
+    constexpr int PER = SP_COPY / 2;
+#pragma unroll
+    for (int p = 0; p < SP_COPY; ++p) {
+        const int q = (p % PER) * SP_THREADS + wave * 64;   // piece of the wave's lane 0 in its tile
+        lds_dma16((const u32x4*)(p < PER ? t0 : t1) + q + lane, slot + (p < PER ? 0 : TILE_BYTES) + q * 16);
+    }
+}
+
+template <int PREC, int CPW>
+__global__ __launch_bounds__(SP_THREADS, 2) void sep_stage2p_kernel(FwdArgs a)
+{
+    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * SP_STAGE];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int h = lane >> 5, col = lane & 31;
+    const int64_t G = gridDim.x, b = blockIdx.x;
+    const int64_t L = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+    const int nrb = a.out_npad / SP_ROWS;
+    const int64_t cg = L / nrb;
+    const int rb = (int)(L - cg * nrb);
+    const int64_t i0 = cg * CPW;
+    const int ncol = (int)min((int64_t)CPW, (int64_t)a.out_n - i0);   // >= 1, uniform
+    const int64_t jt = (int64_t)rb * SP_WAVES + wave;                  // 16-row tile in the column
+    const int nzb = a.nzb, nyc = a.nxc;
+    const int ylast = a.x_pad - (nyc - 1) * XC;   // y values in the last chunk
+    f32x4 Af[SR_YC][16];
+    bf16x8 Ahi[SR_YC][8], Alo[SR_YC][8];
+#pragma unroll
+    for (int yc = 0; yc < SR_YC; ++yc)
+        if (yc < nyc) load_a<PREC>(a.txa + (size_t)(jt * nyc + yc) * TILE_BYTES, lane, Af[yc], Ahi[yc], Alo[yc]);
+    sp_fill(a, i0, 0, wave, lds);
+    __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+    __syncthreads();
+    int s = 0;   // stages consumed; stage s sits in slot s & 1
+    for (int c = 0; c < ncol; ++c) {
+        const int64_t i = i0 + c;
+        const int64_t wt = i * (a.out_npad / WAVE_PIX) + jt;
+        float acc[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[q] = 0.0f;
+        for (int zb = 0; zb < nzb; ++zb) {
+            const f32x4* tzp = (const f32x4*)(a.tz + 2 * ((((wt * nzb + zb) * 2 + h) * ZB + col) * 8));
+            f32x4 tzv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) tzv[q] = tzp[q];
+            if (zb + 1 < nzb) sp_fill(a, i, zb + 1, wave, lds + ((s + 1) & 1) * SP_STAGE);
+            else if (c + 1 < ncol) sp_fill(a, i + 1, 0, wave, lds + ((s + 1) & 1) * SP_STAGE);
+            const uint8_t* cur = lds + (s & 1) * SP_STAGE + (h * ZB + col) * ROW_BYTES;
+            f32x16 C = {};
+#pragma unroll
+            for (int yc = 0; yc < SR_YC; ++yc) {
+                if (yc < nyc) {
+                    if (yc + 1 < nyc || ylast == XC)
+                        C = tile_mfma<PREC, XC>(C, cur + yc * TILE_BYTES, col, Af[yc], Ahi[yc], Alo[yc]);
+                    else
+                        C = tile_mfma_partial<PREC>(C, cur + yc * TILE_BYTES, col, ylast, Af[yc], Ahi[yc], Alo[yc]);
+                }
+            }
+            // the next slot's loads have landed (the compiler does not track them)
+            __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+            __syncthreads();
+            ++s;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int m = 2 * q + u;
+                    const int r = 4 * (m >> 1) + 2 * (m & 1);
+                    const float tr = tzv[q][2 * u], ti = tzv[q][2 * u + 1];
+                    acc[2 * m] += tr * C[r] - ti * C[r + 1];
+                    acc[2 * m + 1] += tr * C[r + 1] + ti * C[r];
+                }
+            }
+        }
+        // sum over the 32 z lanes of each half (fixed butterfly order)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            float v = acc[q];
+            v += __shfl_xor(v, 16, 32);
+            v += __shfl_xor(v, 8, 32);
+            v += __shfl_xor(v, 4, 32);
+            v += __shfl_xor(v, 2, 32);
+            v += __shfl_xor(v, 1, 32);
+            acc[q] = v;
+        }
+        if (col == 0) {
 #pragma unroll
             for (int m = 0; m < 8; ++m) {
                 const int64_t j = slot_pixel(wt, h, m) - i * a.out_npad;
@@ -1283,11 +1544,30 @@ static void launch_stage2r_cpw(int precision, const FwdArgs& a, hipStream_t s)
 // per uniform-q pattern with 8 columns, 0.425 with 4, 0.428 for the general kernel);
 // otherwise two columns per workgroup when that still leaves STAGE2_MIN_WG
 // workgroups, else one.
+template <int CPW>
+static void launch_stage2p_cpw(int precision, const FwdArgs& a, hipStream_t s)
+{
+    const dim3 grid((unsigned)(ceil_div(a.out_n, CPW) * (a.out_npad / SP_ROWS)));
+    if (precision == MSFT_BF16X3)
+        hipLaunchKernelGGL((sep_stage2p_kernel<MSFT_BF16X3, CPW>), grid, dim3(SP_THREADS), 0, s, a);
+    else
+        hipLaunchKernelGGL((sep_stage2p_kernel<MSFT_BF16, CPW>), grid, dim3(SP_THREADS), 0, s, a);
+}
+
 int launch_sep_stage2(int precision, const FwdArgs& a, void* stream)
 {
     hipStream_t s = (hipStream_t)stream;
     if (a.out_n <= 0 || a.group_blocks <= 0) return (int)hipErrorInvalidValue;
     const int64_t gb = a.group_blocks;
+    if (precision != MSFT_FP32 && a.nxc <= SR_YC) {
+        // BF16: four-wave workgroups, as many columns each as leave two per CU
+        const int64_t nrb = a.out_npad / SP_ROWS;
+        if (ceil_div(a.out_n, 8) * nrb >= 2 * CHIP_CUS) launch_stage2p_cpw<8>(precision, a, s);
+        else if (ceil_div(a.out_n, 4) * nrb >= 2 * CHIP_CUS) launch_stage2p_cpw<4>(precision, a, s);
+        else if (ceil_div(a.out_n, 2) * nrb >= 2 * CHIP_CUS) launch_stage2p_cpw<2>(precision, a, s);
+        else launch_stage2p_cpw<1>(precision, a, s);
+        return (int)hipGetLastError();
+    }
     if (a.nxc <= SR_YC) {
         if (ceil_div(a.out_n, 8) * gb >= CHIP_CUS) launch_stage2r_cpw<8>(precision, a, s);
         else if (ceil_div(a.out_n, 4) * gb >= CHIP_CUS) launch_stage2r_cpw<4>(precision, a, s);
@@ -1303,6 +1583,14 @@ int launch_sep_stage2(int precision, const FwdArgs& a, void* stream)
 int launch_sep_stage1(int precision, const Stage1Args& a, int64_t nblk, void* stream)
 {
     hipStream_t s = (hipStream_t)stream;
+    if (precision != MSFT_FP32) {
+        const dim3 g((unsigned)ceil_div(a.n, SP_ROWS), (unsigned)(a.nyc * XC / (SP1_Y * SP1_PASSES)), (unsigned)a.nzb);
+        if (precision == MSFT_BF16X3)
+            hipLaunchKernelGGL(sep_stage1p_kernel<MSFT_BF16X3>, g, dim3(SP_THREADS), 0, s, a);
+        else
+            hipLaunchKernelGGL(sep_stage1p_kernel<MSFT_BF16>, g, dim3(SP_THREADS), 0, s, a);
+        return (int)hipGetLastError();
+    }
     const dim3 grid((unsigned)nblk, (unsigned)(a.nyc * XC / S1_Y), (unsigned)a.nzb);
     if (precision == MSFT_FP32)
         hipLaunchKernelGGL((sep_stage1_kernel<MSFT_FP32, false, S1_Y>), grid, dim3(512), 0, s, a);
