@@ -1131,134 +1131,14 @@ __global__ __launch_bounds__(512) void sep_stage2_kernel(FwdArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// Second stage with the A operand resident: when the y chunks number at most
-// SR_YC, a wave keeps exp(-i q_y(j) y) of its 16 rows j for all of them in
-// registers for the workgroup's whole life, so a workgroup takes CPW columns with
-// one A load.  Per column and z block the y chunks accumulate in one MFMA
-// accumulator (the y sum is inside A, so no rotation between chunks), then Tz
-// rotates the result into the column's per-lane sums; the column's z-lane
-// butterfly and store follow.  H tiles stream through the double-buffered LDS
-// ring in the order (column, z block, y chunk).
-// ---------------------------------------------------------------------------
-
-template <int PREC, int CPW>
-__global__ __launch_bounds__(512) void sep_stage2r_kernel(FwdArgs a)
-{
-    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * TILE_BYTES];
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    const int h = lane >> 5, col = lane & 31;
-    const int64_t cg = blockIdx.x / a.group_blocks, rb = blockIdx.x - cg * a.group_blocks;
-    const int64_t i0 = cg * CPW;
-    const int ncol = (int)min((int64_t)CPW, (int64_t)a.out_n - i0);   // >= 1, uniform
-    const int64_t wa = rb * WAVES + wave;                                // A operand row
-    const int nzb = a.nzb, nyc = a.nxc;
-    const int ntile = ncol * nzb * nyc;
-    // tile k of this workgroup: column c = k / (nzb nyc), z block, y chunk innermost
-    auto tile_at = [&](int k) {
-        const int c = k / (nzb * nyc), r = k - c * nzb * nyc;
-        const int zb = r / nyc, yc = r - zb * nyc;
-        return (const uint4*)(a.wtiles + ((size_t)(i0 + c) * a.group_tiles + (size_t)yc * nzb + zb) * TILE_BYTES);
-    };
-    {
-        const uint4* g0 = tile_at(0);
-        const uint4 r0 = g0[tid], r1 = g0[tid + 512];
-        ((uint4*)lds)[tid] = r0;
-        ((uint4*)lds)[tid + 512] = r1;
-    }
-    f32x4 Af[SR_YC][16];
-    bf16x8 Ahi[SR_YC][8], Alo[SR_YC][8];
-#pragma unroll
-    for (int yc = 0; yc < SR_YC; ++yc)
-        if (yc < nyc) load_a<PREC>(a.txa + (size_t)(wa * nyc + yc) * TILE_BYTES, lane, Af[yc], Ahi[yc], Alo[yc]);
-    // one wait for the A operands (the memory counter is in order)
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    const int ylast = a.x_pad - (nyc - 1) * XC;   // y values in the last chunk
-
-    int k = 0;
-    for (int c = 0; c < ncol; ++c) {
-        const int64_t wt = ((i0 + c) * a.group_blocks + rb) * WAVES + wave;
-        float acc[16];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] = 0.0f;
-        for (int zb = 0; zb < nzb; ++zb) {
-            const f32x4* tzp = (const f32x4*)(a.tz + 2 * ((((wt * nzb + zb) * 2 + h) * ZB + col) * 8));
-            f32x4 tzv[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) tzv[q] = tzp[q];
-            f32x16 C = {};
-#pragma unroll
-            for (int yc = 0; yc < SR_YC; ++yc) {
-                if (yc < nyc) {
-                    const bool has_next = k + 1 < ntile;
-                    uint4 n0, n1;
-                    if (has_next) {
-                        const uint4* g = tile_at(k + 1);
-                        n0 = g[tid];
-                        n1 = g[tid + 512];
-                    }
-                    const uint8_t* row = lds + (k & 1) * TILE_BYTES + (h * ZB + col) * ROW_BYTES;
-                    if (yc + 1 < nyc || ylast == XC)
-                        C = tile_mfma<PREC, XC>(C, row, col, Af[yc], Ahi[yc], Alo[yc]);
-                    else
-                        C = tile_mfma_partial<PREC>(C, row, col, ylast, Af[yc], Ahi[yc], Alo[yc]);
-                    if (has_next) {
-                        uint4* nb = (uint4*)(lds + ((k + 1) & 1) * TILE_BYTES);
-                        nb[tid] = n0;
-                        nb[tid + 512] = n1;
-                    }
-                    __syncthreads();
-                    ++k;
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-#pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    const int m = 2 * q + u;
-                    const int r = 4 * (m >> 1) + 2 * (m & 1);
-                    const float tr = tzv[q][2 * u], ti = tzv[q][2 * u + 1];
-                    acc[2 * m] += tr * C[r] - ti * C[r + 1];
-                    acc[2 * m + 1] += tr * C[r + 1] + ti * C[r];
-                }
-            }
-        }
-        // sum over the 32 z lanes of each half (fixed butterfly order)
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            float v = acc[q];
-            v += __shfl_xor(v, 16, 32);
-            v += __shfl_xor(v, 8, 32);
-            v += __shfl_xor(v, 4, 32);
-            v += __shfl_xor(v, 2, 32);
-            v += __shfl_xor(v, 1, 32);
-            acc[q] = v;
-        }
-        if (col == 0) {
-            const int64_t i = i0 + c;
-#pragma unroll
-            for (int m = 0; m < 8; ++m) {
-                const int64_t j = slot_pixel(wt, h, m) - i * a.out_npad;
-                if (j < a.out_n) {
-                    const int64_t out = j * a.out_n + i;
-                    const float re = acc[2 * m], im = acc[2 * m + 1];
-                    a.intensity[out] = re * re + im * im;
-                    if (a.amplitude) ((float2*)a.amplitude)[out] = make_float2(re, im);
-                }
-            }
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
 // Second stage for the BF16 precisions with at most two y chunks: workgroups of 4
 // waves (64 rows j, CPW columns i) with both chunks' A operands resident; each
 // pipeline stage is one (column, z block) with the H tiles of both chunks, filled
 // by direct global -> LDS loads into a two-slot ring, so one barrier covers 48
 // MFMAs per wave; two workgroups share a CU, and the row blocks of a column group
 // run on one XCD (workgroup b runs on XCD b % 8) so that each H tile comes from HBM
-// about once.  Same tile products, rotations and butterfly as sep_stage2r_kernel.
+// about once.  Per (column, z block) the y chunks accumulate in one MFMA
+// accumulator, then Tz rotates the result into the column's per-lane sums.
 // ---------------------------------------------------------------------------
 
 // The stage of column i, z block zb: tiles (y chunk 0, 1) of the column's group into
@@ -1527,23 +1407,7 @@ static void launch_stage2_cpw(int precision, const FwdArgs& a, hipStream_t s)
 // and slower in BF16.
 constexpr int64_t STAGE2_MIN_WG = 2 * CHIP_CUS;
 
-template <int CPW>
-static void launch_stage2r_cpw(int precision, const FwdArgs& a, hipStream_t s)
-{
-    const dim3 grid((unsigned)(ceil_div(a.out_n, CPW) * a.group_blocks));
-    if (precision == MSFT_FP32)
-        hipLaunchKernelGGL((sep_stage2r_kernel<MSFT_FP32, CPW>), grid, dim3(512), 0, s, a);
-    else if (precision == MSFT_BF16X3)
-        hipLaunchKernelGGL((sep_stage2r_kernel<MSFT_BF16X3, CPW>), grid, dim3(512), 0, s, a);
-    else
-        hipLaunchKernelGGL((sep_stage2r_kernel<MSFT_BF16, CPW>), grid, dim3(512), 0, s, a);
-}
 
-// Second stage: with the A operand resident (at most SR_YC y chunks), as many
-// columns per workgroup as still leave one workgroup per CU (128^3 / 512^2: 0.418 ms
-// per uniform-q pattern with 8 columns, 0.425 with 4, 0.428 for the general kernel);
-// otherwise two columns per workgroup when that still leaves STAGE2_MIN_WG
-// workgroups, else one.
 template <int CPW>
 static void launch_stage2p_cpw(int precision, const FwdArgs& a, hipStream_t s)
 {
@@ -1554,6 +1418,10 @@ static void launch_stage2p_cpw(int precision, const FwdArgs& a, hipStream_t s)
         hipLaunchKernelGGL((sep_stage2p_kernel<MSFT_BF16, CPW>), grid, dim3(SP_THREADS), 0, s, a);
 }
 
+// Second stage: for BF16 with at most SR_YC y chunks the four-wave kernel with
+// the A operand resident, as many columns per workgroup as still leave two
+// workgroups per CU; otherwise the general kernel, two columns per workgroup when
+// that still leaves STAGE2_MIN_WG workgroups, else one.
 int launch_sep_stage2(int precision, const FwdArgs& a, void* stream)
 {
     hipStream_t s = (hipStream_t)stream;
@@ -1566,13 +1434,6 @@ int launch_sep_stage2(int precision, const FwdArgs& a, void* stream)
         else if (ceil_div(a.out_n, 4) * nrb >= 2 * CHIP_CUS) launch_stage2p_cpw<4>(precision, a, s);
         else if (ceil_div(a.out_n, 2) * nrb >= 2 * CHIP_CUS) launch_stage2p_cpw<2>(precision, a, s);
         else launch_stage2p_cpw<1>(precision, a, s);
-        return (int)hipGetLastError();
-    }
-    if (a.nxc <= SR_YC) {
-        if (ceil_div(a.out_n, 8) * gb >= CHIP_CUS) launch_stage2r_cpw<8>(precision, a, s);
-        else if (ceil_div(a.out_n, 4) * gb >= CHIP_CUS) launch_stage2r_cpw<4>(precision, a, s);
-        else if (ceil_div(a.out_n, 2) * gb >= CHIP_CUS) launch_stage2r_cpw<2>(precision, a, s);
-        else launch_stage2r_cpw<1>(precision, a, s);
         return (int)hipGetLastError();
     }
     if (ceil_div(a.out_n, 2) * gb >= STAGE2_MIN_WG) launch_stage2_cpw<2>(precision, a, s);

@@ -461,9 +461,10 @@ __global__ __launch_bounds__(SG_THREADS, 2) void sepg_stage2_kernel(SepG3Args a)
 //   K(i, y, z) = sum_j exp(-i q_y(j) y) [h(i, j) exp(-i q_z(i, j) z)]   (pass 1)
 //   R(x, y, z) = sum_i exp(-i q_x(i) x) K(i, y, z)                      (pass 2)
 // Pass 1 (v_mfma_f32_16x16x4_f32): rows are a wave's 16 y, columns 16 z, K four
-// rows j; a workgroup takes 64 y, SGA_COLS columns i and one z block, forms the B
-// tiles h Tz of the next chunk of 32 j in LDS (three planes) behind the current
-// chunk's MFMAs, and writes K as three planes of [i][y][z] floats (16 lanes store
+// rows j; a workgroup takes 64 y, SGA_COLS columns i and one z block, loads the
+// next chunk's Tz (direct global -> LDS loads) and h under the current chunk's
+// MFMAs, then forms its B tiles h Tz (three planes) in LDS, and writes K as three
+// planes of [i][y][z] floats (16 lanes store
 // 16 consecutive z).  Pass 2 (sepg_adj_cols_kernel) has the shape of stage 1 with
 // rows x and K over the columns i, split in two halves whose partial sums the
 // column walk adds.
@@ -514,6 +515,8 @@ __device__ __forceinline__ void sga_tiles(const uint8_t* tiles, int kk, int n16,
 __global__ __launch_bounds__(SG_THREADS, 2) void sepg_adj_rows_kernel(SepG3AdjArgs a)
 {
     __shared__ __attribute__((aligned(16))) uint8_t lds[2 * SGA_COLS * G3_TILE_BYTES];
+    __shared__ __attribute__((aligned(16))) uint8_t tzs[SGA_COLS * 2 * 4096];   // Tz of the next chunk
+    __shared__ __attribute__((aligned(16))) uint8_t hs[32 * 16];                // h of the next chunk
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -533,41 +536,44 @@ __global__ __launch_bounds__(SG_THREADS, 2) void sepg_adj_rows_kernel(SepG3AdjAr
 #pragma unroll
         for (int p = 0; p < 3; ++p) P[c][p][0] = P[c][p][1] = f32x4{};
     if (ncol > 0) {
-        // h and Tz of chunk jc: Tz entries (w16, zb, hp, z, m) of the 16-row tile w16
-        // hold row 4 (m / 2) + 2 hp + (m % 2); rows 8 fk + 4 fg + e sit at hp = e / 2,
-        // m = 4 (fk % 2) + 2 fg + e % 2.  Loaded two chunks ahead of their use.
-        typedef f32x4 TzBuf[SGA_COLS][2];
-        typedef float2 HBuf[SGA_COLS][4];
-        // (a column beyond the detector, i >= N, gets zero tiles)
-        auto load_b = [&](int jc, TzBuf& tz, HBuf& hv) {
+        // Tz of chunk jc into LDS by direct loads: per column c the 16-row tiles
+        // w16 = i (npad / 16) + 2 jc + w (w = 0, 1), each a contiguous block (hp, z, m)
+        // of 4 KiB holding row 4 (m / 2) + 2 hp + m % 2 at z; four pieces per thread
+        // (a column beyond the detector loads the last one, and gets zero tiles)
+        auto fill_tz = [&](int jc) {
 #pragma unroll
-            for (int c = 0; c < SGA_COLS; ++c) {
+            for (int p = 0; p < 2 * SGA_COLS; ++p) {
+                const int c = p >> 1, w = p & 1;
                 const int64_t i = min(i0 + c, a.n - 1);
-                const int64_t w16 = i * (a.npad / SG2_ROWS) + 2 * jc + (fk >> 1);
-#pragma unroll
-                for (int hp = 0; hp < 2; ++hp)
-                    tz[c][hp] = *(const f32x4*)(a.tz + 2 * ((((w16 * a.nzb + zb) * 2 + hp) * ZB + fz) * 8 +
-                                                            4 * (fk & 1) + 2 * fg));
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    // always a load (from row j clamped into the detector); form_b
-                    // zeroes the rows beyond it
-                    const int64_t j = 32 * jc + 8 * fk + 4 * fg + e;
-                    hv[c][e] = ((const float2*)a.h)[min(j, (int64_t)a.n - 1) * a.n + i];
-                }
+                const int64_t w16 = i * (a.npad / SG2_ROWS) + 2 * jc + w;
+                lds_dma16((const u32x4*)(a.tz + 2 * (w16 * a.nzb + zb) * (2 * ZB * 8)) + wave * 64 + lane,
+                          tzs + p * 4096 + wave * 1024);
             }
         };
+        // h of chunk jc for the columns i0, i0 + 1: row j = 32 jc + t as one 16-byte
+        // piece, loaded by thread t < 32 (row clamped into the detector; form_b zeroes
+        // the rows and columns beyond it)
+        auto load_h = [&](int jc, u32x4& v) {
+            if (tid < 32) v = *(const u32x4*)((const float2*)a.h + (int64_t)min(32 * jc + tid, a.n - 1) * a.n + i0);
+        };
         // B = h Tz of chunk jc in three planes, rows j = 8 fk + 4 fg + e of the tile at
-        // z = fz (zero for rows j >= N and columns i >= N)
-        auto form_b = [&](int jc, uint8_t* slot, const TzBuf& tz, const HBuf& hv) {
+        // z = fz: Tz row 8 fk + 4 fg + e sits in block w = fk / 2 at hp = e / 2,
+        // m = 4 (fk % 2) + 2 fg + e % 2
+        auto form_b = [&](int jc, uint8_t* slot) {
 #pragma unroll
             for (int c = 0; c < SGA_COLS; ++c) {
+                f32x4 tz[2];
+#pragma unroll
+                for (int hp = 0; hp < 2; ++hp)
+                    tz[hp] = *(const f32x4*)(tzs + (c * 2 + (fk >> 1)) * 4096 +
+                                             ((hp * ZB + fz) * 8 + 4 * (fk & 1) + 2 * fg) * 8);
                 f32x4 br, bi, bs;
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const bool in = 32 * jc + 8 * fk + 4 * fg + e < a.n && c < ncol;
-                    const float hr = in ? hv[c][e].x : 0.0f, hi = in ? hv[c][e].y : 0.0f;
-                    const float tr = tz[c][e >> 1][2 * (e & 1)], ti = tz[c][e >> 1][2 * (e & 1) + 1];
+                    const float2 hv = *(const float2*)(hs + (8 * fk + 4 * fg + e) * 16 + c * 8);
+                    const float hr = in ? hv.x : 0.0f, hi = in ? hv.y : 0.0f;
+                    const float tr = tz[e >> 1][2 * (e & 1)], ti = tz[e >> 1][2 * (e & 1) + 1];
                     br[e] = hr * tr - hi * ti;
                     bi[e] = hr * ti + hi * tr;
                     bs[e] = br[e] + bi[e];
@@ -582,39 +588,38 @@ __global__ __launch_bounds__(SG_THREADS, 2) void sepg_adj_rows_kernel(SepG3AdjAr
         f32x4 Ac[6];
 #pragma unroll
         for (int q = 0; q < 6; ++q) Ac[q] = ta[q * 64];
-        // chunk m's h and Tz live in buffer m % 2
-        TzBuf tz0, tz1;
-        HBuf h0, h1;
-        load_b(0, tz0, h0);
-        if (a.njc2 > 1) load_b(1, tz1, h1);
-        form_b(0, lds, tz0, h0);
+        u32x4 hv = {};
+        fill_tz(0);
+        load_h(0, hv);
+        __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+        if (tid < 32) *(u32x4*)(hs + tid * 16) = hv;
         __syncthreads();
-        // step jc: the MFMAs on the formed tiles of chunk jc, then chunk jc + 1's tiles
-        // formed from tzN, hN into the other LDS buffer; chunk jc + 2 loaded into the
-        // registers chunk jc left free
-        auto step = [&](int jc, const TzBuf& tzN, const HBuf& hN, TzBuf& tzF, HBuf& hF) {
+        form_b(0, lds);
+        __syncthreads();
+        // step jc: Tz and h of chunk jc + 1 are loaded under chunk jc's MFMAs, then
+        // chunk jc + 1's tiles are formed into the other LDS buffer
+        for (int jc = 0; jc < a.njc2; ++jc) {
             const bool more = jc + 1 < a.njc2;
-            // the A operand first: waiting for it at the end of the step leaves the
-            // loads of chunk jc + 2 in flight
             f32x4 An[6];
             if (more) {
+                fill_tz(jc + 1);
+                load_h(jc + 1, hv);
 #pragma unroll
                 for (int q = 0; q < 6; ++q) An[q] = ta[((jc + 1) * 6 + q) * 64];
             }
-            if (jc + 2 < a.njc2) load_b(jc + 2, tzF, hF);
-            const uint8_t* cur = lds + (jc & 1) * SGA_COLS * G3_TILE_BYTES;
-            sga_tiles<SGA_COLS>(cur, kk, n16, Ac, P);
-            // the other buffer was last read before the previous barrier
-            if (more) form_b(jc + 1, lds + ((jc + 1) & 1) * SGA_COLS * G3_TILE_BYTES, tzN, hN);
-            __syncthreads();
+            sga_tiles<SGA_COLS>(lds + (jc & 1) * SGA_COLS * G3_TILE_BYTES, kk, n16, Ac, P);
             if (more) {
+                // Tz landed (the compiler does not track it); h goes to LDS, read by
+                // every wave after the barrier
+                __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+                if (tid < 32) *(u32x4*)(hs + tid * 16) = hv;
+                __syncthreads();
+                // the other B buffer was last read before the previous barrier
+                form_b(jc + 1, lds + ((jc + 1) & 1) * SGA_COLS * G3_TILE_BYTES);
+                __syncthreads();
 #pragma unroll
                 for (int q = 0; q < 6; ++q) Ac[q] = An[q];
             }
-        };
-        for (int jc = 0; jc < a.njc2; jc += 2) {
-            step(jc, tz1, h1, tz0, h0);
-            if (jc + 1 < a.njc2) step(jc + 1, tz0, h0, tz1, h1);
         }
     }
     // K = (P1 - P2) + i (P3 - P1 - P2) and Kr + Ki, planes of [i][y][z2] floats: 16
