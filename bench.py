@@ -348,10 +348,11 @@ def main():
                     help="requests of the mixed-size serving stream (0 = skip)")
     ap.add_argument("--no-large", dest="large", action="store_false",
                     help="skip the 256^3 / 1024^2 pattern (l <= 10 body with voids, 80 deg)")
-    ap.add_argument("--fit", type=int, default=0, metavar="B",
-                    help="also time iterations of the differentiable fit with batch B")
+    ap.add_argument("--fit", type=int, default=256, metavar="B",
+                    help="time iterations of the differentiable fit with batch B on the flat and "
+                         "the uniform-q detector (0 = skip; the flat batch of 256 takes about 35 s)")
     ap.add_argument("--fit-steps", type=int, default=1)
-    ap.add_argument("--fit-detector", choices=["flat", "uniform_q"], default="flat")
+    ap.add_argument("--fit-detector", choices=["flat", "uniform_q", "both"], default="both")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 256 MiB device-to-device copy, the reference for "
                          "scaling hardware byte counters")
@@ -535,10 +536,12 @@ def main():
         line["render"] = time_render(msft, torch, args.steps)
         print(f"[bench] render l<=8 soft star 128^3: {line['render']['render_ms'] * 1e3:.1f} us, "
               f"gradient {line['render']['gradient_ms'] * 1e3:.1f} us", file=sys.stderr, flush=True)
-    if args.fit > 0:
-        line["fit"] = time_fit(torch, args.fit, args.fit_steps, 1 if args.fit_steps else 0,
-                               lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True),
-                               args.fit_detector)
+    if args.fit > 0 and not args.only:
+        dets = ["flat", "uniform_q"] if args.fit_detector == "both" else [args.fit_detector]
+        line["fit"] = {}
+        for det in dets:
+            line["fit"][det] = time_fit(torch, args.fit, args.fit_steps, 1 if args.fit_steps else 0,
+                                        lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True), det)
     if not args.no_cpu_baseline and not args.only:
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(line))
