@@ -133,7 +133,7 @@ template <bool FULL>
 __device__ __forceinline__ void tile_g3(const uint8_t* row, int col, int xlen, const f32x4* Af,
                                         f32x16& P1, f32x16& P2, f32x16& P3)
 {
-    const int sw = (col >> 1) & 3;
+    const int sw = g3_swizzle(col);
     P1 = f32x16{};
     P2 = f32x16{};
     P3 = f32x16{};

@@ -343,9 +343,9 @@ __global__ __launch_bounds__(SCAN_THREADS) void scan_kernel(ScanArgs a)
         for (int k = 0; k < 4; ++k) {
             const int zl = 4 * zs + k;
             if (G3) {
-                // Gauss tile (xb, zb, y): rows (plane, h, z) of 4 slots, slot g ^ ((z / 2) % 4)
+                // Gauss tile (xb, zb, y): rows (plane, h, z) of 4 slots, slot g ^ g3_swizzle(z)
                 uint8_t* row = a.wtiles + ((size_t)(xb * a.nzb + zb) * a.ny + y) * G3_TILE_BYTES +
-                               ((cc & 1) * ZB + zl) * G3_ROW_BYTES + (((cc >> 1) ^ ((zl >> 1) & 3)) << 4);
+                               ((cc & 1) * ZB + zl) * G3_ROW_BYTES + (((cc >> 1) ^ g3_swizzle(zl)) << 4);
                 *(f32x4*)row = f32x4{wr[k][0], wr[k][1], wr[k][2], wr[k][3]};
                 *(f32x4*)(row + 2 * ZB * G3_ROW_BYTES) = f32x4{wi[k][0], wi[k][1], wi[k][2], wi[k][3]};
                 *(f32x4*)(row + 4 * ZB * G3_ROW_BYTES) = f32x4{wr[k][0] + wi[k][0], wr[k][1] + wi[k][1],

@@ -52,6 +52,11 @@ constexpr int G3_WAVE_PIX = 32;
 constexpr int G3_WAVES = 4;
 constexpr int G3_ROW_BYTES = G3_XC / 2 * 4;                 // 64
 constexpr int G3_TILE_BYTES = 3 * 2 * ZB * G3_ROW_BYTES;    // 12 KB: W tile or A tile
+// The 16-byte slot swizzle of a Gauss tile row (plane, h, z): logical slot g sits at
+// g ^ g3_swizzle(z).  The LDS serves a 16-byte read in groups of 16 lanes over 64
+// banks; lanes reading one logical slot of 16 consecutive rows z then hit 16
+// distinct 4-bank groups: 4 (z % 4) + (g ^ (z / 4) % 4).
+constexpr int g3_swizzle(int z) { return (z >> 2) & 3; }
 static_assert(G3_WAVE_PIX * G3_WAVES == BLOCK_PIX, "a Gauss block is one pixel block");
 
 // Host geometry (FP64, built without FMA contraction).

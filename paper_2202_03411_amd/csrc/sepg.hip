@@ -117,7 +117,7 @@ __global__ void sg_twiddle_a2(float* t, int64_t total, int n, int ny, int nyc2, 
 // MFMAs are issued.
 __device__ __forceinline__ void sg1_tile(const uint8_t* row, int col, const f32x4* Af, f32x16 (&P)[3])
 {
-    const int sw = (col >> 1) & 3;
+    const int sw = g3_swizzle(col);
     f32x4 b[2][3];
 #pragma unroll
     for (int p = 0; p < 3; ++p) b[0][p] = *(const f32x4*)(row + p * SG_PLANE_BYTES + ((0 ^ sw) << 4));
@@ -171,7 +171,7 @@ __device__ __forceinline__ void sg1_stage(const uint8_t* slot, int kk, int n16, 
     auto frag = [&](int t, int p, int g, int nt) {
         const int z = 16 * nt + n16;
         return *(const f32x4*)(slot + t * G3_TILE_BYTES + p * SG_PLANE_BYTES + ((kk & 1) * ZB + z) * G3_ROW_BYTES +
-                               (((2 * g + (kk >> 1)) ^ ((z >> 1) & 3)) << 4));
+                               (((2 * g + (kk >> 1)) ^ g3_swizzle(z)) << 4));
     };
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
@@ -678,7 +678,7 @@ __global__ __launch_bounds__(SG_THREADS, 2) void sepg_adj_cols_kernel(SepG3AdjAr
     auto store_tile = [&](uint8_t* slot, const float (&v)[3][4]) {
 #pragma unroll
         for (int q = 0; q < 3; ++q)
-            *(f32x4*)(slot + q * SG_PLANE_BYTES + (h * ZB + col) * G3_ROW_BYTES + ((wave ^ ((col >> 1) & 3)) << 4)) =
+            *(f32x4*)(slot + q * SG_PLANE_BYTES + (h * ZB + col) * G3_ROW_BYTES + ((wave ^ g3_swizzle(col)) << 4)) =
                 f32x4{v[q][0], v[q][1], v[q][2], v[q][3]};
     };
     f32x16 P[2][3];
