@@ -255,16 +255,26 @@ __global__ __launch_bounds__(SCAN_THREADS) void scan_kernel(ScanArgs a)
         const bool active = zb < a.nzb;
         const int z0 = zb * ZB + 4 * zs;
         float d[4][4], b[4][4], sb[4], sd[4], ib[4], id[4];
+        // A wave whose 32 x 32 block lies inside the grid issues its 8 loads at once
+        // under one branch (a guard per column would wait for each column in turn).
+        if (active && vec && (xb + 1) * SCAN_XB <= a.nx && (zb + 1) * ZB <= a.nz) {
+            float4 dv[4], bv[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int x = xb * SCAN_XB + col_of(e);
-            const size_t col = ((size_t)x * a.ny + y) * a.nz;
-            if (active && x < a.nx && vec && z0 + 4 <= a.nz) {
-                const float4 dv = *(const float4*)(a.delta + col + z0);
-                const float4 bv = *(const float4*)(a.beta + col + z0);
-                d[e][0] = dv.x; d[e][1] = dv.y; d[e][2] = dv.z; d[e][3] = dv.w;
-                b[e][0] = bv.x; b[e][1] = bv.y; b[e][2] = bv.z; b[e][3] = bv.w;
-            } else {
+            for (int e = 0; e < 4; ++e) {
+                const size_t col = ((size_t)(xb * SCAN_XB + col_of(e)) * a.ny + y) * a.nz + z0;
+                dv[e] = *(const float4*)(a.delta + col);
+                bv[e] = *(const float4*)(a.beta + col);
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                d[e][0] = dv[e].x; d[e][1] = dv[e].y; d[e][2] = dv[e].z; d[e][3] = dv[e].w;
+                b[e][0] = bv[e].x; b[e][1] = bv[e].y; b[e][2] = bv[e].z; b[e][3] = bv[e].w;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int x = xb * SCAN_XB + col_of(e);
+                const size_t col = ((size_t)x * a.ny + y) * a.nz;
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     const bool in = active && x < a.nx && z0 + k < a.nz;
@@ -272,6 +282,9 @@ __global__ __launch_bounds__(SCAN_THREADS) void scan_kernel(ScanArgs a)
                     b[e][k] = in ? a.beta[col + z0 + k] : 0.0f;
                 }
             }
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
             sb[e] = (b[e][0] + b[e][1]) + (b[e][2] + b[e][3]);
             sd[e] = (d[e][0] + d[e][1]) + (d[e][2] + d[e][3]);
             // inclusive scan over the 8 lanes (z segments) of the column's group
