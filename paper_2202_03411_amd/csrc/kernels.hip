@@ -547,20 +547,19 @@ constexpr int PW_TY_BYTES = WAVES * WAVE_PIX * 8;         // Ty of a block's wav
 constexpr int PW_SLOT = TILE_BYTES + PW_TY_BYTES;
 static_assert(PW_COPY * PW_THREADS == TILE_BYTES / 16, "a tile is copied in whole pieces");
 static_assert(2 * PW_WAVES == WAVES && PW_TY_BYTES == 64 * 16, "one wave gathers the Ty rows");
-// Slot contents for tile tn: the W tile and, from wave 0, the block's Ty rows at
-// y(tn).  Wave 0 issues PW_COPY + 1 loads, the others PW_COPY.
-__device__ __forceinline__ void pw_fill(const FwdArgs& a, int64_t wtb, int64_t tn, const u32x4* gw,
+// Slot contents for tile tn (whose y is yn): the W tile and, from wave 0, the
+// block's Ty rows at yn.  Wave 0 issues PW_COPY + 1 loads, the others PW_COPY.
+__device__ __forceinline__ void pw_fill(const FwdArgs& a, int64_t wtb, int64_t tn, int yn, const u32x4* gw,
                                         uint8_t* slot)
 {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
 #pragma unroll
     for (int c = 0; c < PW_COPY; ++c)
         lds_dma16(gw + tn * (TILE_BYTES / 16) + c * PW_THREADS + wave * 64 + lane,
                   slot + (c * PW_THREADS + wave * 64) * 16);
-    if (wave == 0) {
-        const int64_t yn = tn % a.ny;
+    if (wave == 0)
         lds_dma16(a.ty + 2 * ((wtb + (lane >> 3)) * a.ny + yn) * WAVE_PIX + (lane & 7) * 4, slot + TILE_BYTES);
-    }
 }
 
 // C0, C1 = the wave's two row tiles against one W tile; each B fragment read once.
@@ -605,11 +604,17 @@ __device__ __forceinline__ void chunk_pair(const FwdArgs& a, int64_t wt0, int64_
 #pragma unroll
         for (int q = 0; q < 16; ++q) G0[q] = G1[q] = 0.0f;
         for (int y = 0; y < a.ny; ++y, ++t) {
-            // the next slot (the last tile again at the very end: a slot nobody reads again)
-            pw_fill(a, wtb, min(t + 1, ntiles - 1), gw, lds + (size_t)((t + 1) & 1) * PW_SLOT);
+            // the next slot (the last tile again at the very end, with y = 0: a slot
+            // nobody reads again); tiles run y fastest
+            pw_fill(a, wtb, min(t + 1, ntiles - 1), y + 1 == a.ny ? 0 : y + 1, gw,
+                    lds + (size_t)((t + 1) & 1) * PW_SLOT);
             const uint8_t* cur = lds + (size_t)(t & 1) * PW_SLOT;
             f32x16 C0, C1;
+            // matrix work at raised priority: a SIMD's other wave (of the other
+            // workgroup) fills the gaps with its rotation and barrier
+            __builtin_amdgcn_s_setprio(1);
             tile_product2<PREC, FULL>(cur + (h * ZB + col) * ROW_BYTES, col, xlen, Ah0, Al0, Ah1, Al1, C0, C1);
+            __builtin_amdgcn_s_setprio(0);
             const f32x4* ty0 = (const f32x4*)(cur + TILE_BYTES + (2 * wave) * 128 + h * 64);
             const f32x4 t0[4] = {ty0[0], ty0[1], ty0[2], ty0[3]};
             rotate_add(G0, C0, t0);
@@ -650,7 +655,7 @@ __device__ __forceinline__ void fwd_pair_block(const FwdArgs& a, int64_t block, 
     const int64_t ntiles = (int64_t)a.nxc * a.nzb * a.ny;
     const u32x4* gw = (const u32x4*)a.wtiles;
 
-    pw_fill(a, wtb, 0, gw, lds);
+    pw_fill(a, wtb, 0, 0, gw, lds);
     float* accl = accs + wave * 32 * 64 + lane;
 #pragma unroll
     for (int q = 0; q < 32; ++q) accl[q * 64] = 0.0f;
