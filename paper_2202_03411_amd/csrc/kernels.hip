@@ -547,6 +547,7 @@ constexpr int PW_TY_BYTES = WAVES * WAVE_PIX * 8;         // Ty of a block's wav
 constexpr int PW_SLOT = TILE_BYTES + PW_TY_BYTES;
 static_assert(PW_COPY * PW_THREADS == TILE_BYTES / 16, "a tile is copied in whole pieces");
 static_assert(2 * PW_WAVES == WAVES && PW_TY_BYTES == 64 * 16, "one wave gathers the Ty rows");
+static_assert(ROW_BYTES == 256 && PW_SLOT % 256 == 0, "W tile rows start on 256-byte boundaries");
 // Slot contents for tile tn (whose y is yn): the W tile and, from wave 0, the
 // block's Ty rows at yn.  Wave 0 issues PW_COPY + 1 loads, the others PW_COPY.
 __device__ __forceinline__ void pw_fill(const FwdArgs& a, int64_t wtb, int64_t tn, int yn, const u32x4* gw,
@@ -563,27 +564,59 @@ __device__ __forceinline__ void pw_fill(const FwdArgs& a, int64_t wtb, int64_t t
 }
 
 // C0, C1 = the wave's two row tiles against one W tile; each B fragment read once.
+// row: the lane's row of the current slot.  A slot starts on a 256-byte boundary,
+// so the swizzled slot (s ^ sw) of the row is the row address with (sw << 4) folded
+// in, XOR (s << 4): one operation per read and no offset registers, which leaves
+// room to read the next step's fragments under the current step's products.
 template <int PREC, bool FULL>
 __device__ __forceinline__ void tile_product2(const uint8_t* row, int col, int xlen, const bf16x8* Ah0,
                                               const bf16x8* Al0, const bf16x8* Ah1, const bf16x8* Al1,
                                               f32x16& C0, f32x16& C1)
 {
-    const int sw = col & 15;
+    typedef __attribute__((address_space(3))) const uint8_t lds_u8;
+    typedef __attribute__((address_space(3))) const bf16x8 lds_b8;
+    const uint32_t a0 = (uint32_t)(uintptr_t)(lds_u8*)row + ((col & 15) << 4);   // LDS byte address
+    auto rd = [&](int slot) { return *(lds_b8*)(uintptr_t)(a0 ^ (uint32_t)(slot << 4)); };
     C0 = f32x16{};
     C1 = f32x16{};
+    bf16x8 bh = rd(0), bl = PREC == MSFT_BF16X3 ? rd(8) : bh;
 #pragma unroll
     for (int s = 0; s < XC / 8; ++s) {
+        bf16x8 nh = bh, nl = bl;
+        if (s + 1 < XC / 8 && (FULL || 8 * (s + 1) < xlen)) {
+            nh = rd(s + 1);
+            if (PREC == MSFT_BF16X3) nl = rd(8 + s + 1);
+        }
         if (FULL || 8 * s < xlen) {
-            const bf16x8 bh = *(const bf16x8*)(row + ((s ^ sw) << 4));
             C0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah0[s], bh, C0, 0, 0, 0);
             C1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah1[s], bh, C1, 0, 0, 0);
             if (PREC == MSFT_BF16X3) {
-                const bf16x8 bl = *(const bf16x8*)(row + (((8 + s) ^ sw) << 4));
                 C0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah0[s], bl, C0, 0, 0, 0);
                 C1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah1[s], bl, C1, 0, 0, 0);
                 C0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al0[s], bh, C0, 0, 0, 0);
                 C1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al1[s], bh, C1, 0, 0, 0);
             }
+        }
+        bh = nh;
+        bl = nl;
+    }
+    if (FULL && PREC == MSFT_BF16X3) {
+        // Instruction order (LDS reads: mask 0x100, MFMA: 0x008): the reads of steps
+        // 0 and 1, then per step its 6 products and the reads of step s + 2, so each
+        // read has a whole step of products to land under.
+        __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+#pragma unroll
+        for (int s = 0; s < XC / 8; ++s) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 6, 0);
+            if (s + 2 < XC / 8) __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+        }
+    } else if (FULL) {
+        // plain BF16: one read and 2 products per step, in the same order
+        __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+#pragma unroll
+        for (int s = 0; s < XC / 8; ++s) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+            if (s + 2 < XC / 8) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
         }
     }
 }
@@ -708,7 +741,7 @@ __device__ __forceinline__ void fwd_pair_block(const FwdArgs& a, int64_t block, 
 template <int PREC>
 __global__ __launch_bounds__(PW_THREADS, 2) void fwd_pair_kernel(FwdArgs a, int64_t block_begin)
 {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * PW_SLOT];
+    __shared__ __attribute__((aligned(256))) uint8_t lds[2 * PW_SLOT];
     __shared__ float accs[PW_WAVES * 32 * 64];
     fwd_pair_block<PREC>(a, block_begin + blockIdx.x, lds, accs);
 }
@@ -717,7 +750,7 @@ __global__ __launch_bounds__(PW_THREADS, 2) void fwd_pair_kernel(FwdArgs a, int6
 template <int PREC>
 __global__ __launch_bounds__(PW_THREADS, 2) void fwd_pair_batch_kernel(BatchArgs b)
 {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * PW_SLOT];
+    __shared__ __attribute__((aligned(256))) uint8_t lds[2 * PW_SLOT];
     __shared__ float accs[PW_WAVES * 32 * 64];
     const int32_t it = blockIdx.x;
     int r = 0;
