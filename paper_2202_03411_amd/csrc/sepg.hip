@@ -200,9 +200,15 @@ __global__ __launch_bounds__(SG_THREADS, 2) void sepg_stage1_kernel(SepG3Args a)
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int kk = lane >> 4, n16 = lane & 15;
-    const int64_t wt = (int64_t)blockIdx.x * SG_WAVES + wave;   // 16 columns
-    const int zb = blockIdx.z;
-    const int ybase = 4 * SG1_QUADS * blockIdx.y;
+    // workgroup b runs on XCD b % 8: consecutive L (the column blocks of one y group
+    // and z block, which read the same W tiles) share an XCD and its L2
+    const int gx = gridDim.x, gy = gridDim.y;
+    const int G = gx * gy * gridDim.z;
+    const int b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const int L = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+    const int cb = L % gx, yg = (L / gx) % gy, zb = L / (gx * gy);
+    const int64_t wt = (int64_t)cb * SG_WAVES + wave;   // 16 columns
+    const int ybase = 4 * SG1_QUADS * yg;
     const int yend = min(a.ny, ybase + 4 * SG1_QUADS);   // rows y of this workgroup: [ybase, yend)
     const f32x4* ta = (const f32x4*)a.txa1 + (size_t)wt * a.nxc3 * 6 * 64 + lane;
     // stages (quad, xc, y pair) in that order; the one after (quad q, xc, pair v)
