@@ -613,6 +613,34 @@ def test_detector_solid_angles():
         assert abs(om[j, i] - ref) <= 1e-10 * ref
 
 
+def test_ideal_mean_prefactor_by_the_optical_theorem():
+    # The Ideal detector's mean count F c I dOmega fixes |f|^2 = c |A|^2, the differential
+    # cross section of the first-Born amplitude f = sqrt(c) A.  The optical theorem ties
+    # that same amplitude to the extinction of the body: sigma_ext = (4 pi / k0) Im f(0),
+    # which for a small, weak absorber is its absorption cross section mu_a V, with mu_a
+    # the intensity attenuation per unit length.  mu_a is read off the oracle's own
+    # multi-slice transmission of a uniform column (|T|^2 per slice), and c off its
+    # detector, so a wrong power of k0 or a lost 4 pi in c fails here.
+    n, theta, F = 3, 40.0, 7.0
+    mu, _ = oracle.detect_ideal(LAM, theta, n, np.ones(n * n), F, 1)
+    om = np.array([[oracle.pixel_solid_angle(theta, n, i, j) for i in range(n)] for j in range(n)]).ravel()
+    c = mu / (F * om)
+    assert np.allclose(c, c[0], rtol=1e-13)
+    d, b = 1e-6, 2e-6
+    pitch = (1.5, 2.0, 2.5)
+    V = pitch[0] * pitch[1] * pitch[2]
+    # attenuation: the MSFT field factor of slice s of a uniform column is T^s (the strength
+    # w = dV chi T^s with chi the same in every slice), so |T|^2 = |w_1 / w_0|^2
+    col = oracle.strength(oracle.MSFT, np.full((1, 1, 4), d), np.full((1, 1, 4), b), pitch, LAM)[0, 0]
+    mu_a = -math.log(abs(col[1] / col[0]) ** 2) / pitch[2]
+    # forward amplitude of one voxel (first Born: no self-attenuation)
+    w = oracle.strength(oracle.BORN, np.full((1, 1, 1), d), np.full((1, 1, 1), b), pitch, LAM)
+    A0 = oracle.amplitude(np.zeros((1, 3)), w, pitch)[0]
+    sigma_ext = 4.0 * math.pi / K0 * math.sqrt(c[0]) * A0.imag
+    # first order in delta and beta: the two agree to O(delta)
+    assert abs(sigma_ext / (mu_a * V) - 1.0) <= 1e-5
+
+
 def test_ideal_point_scatterer_and_mean():
     # one voxel (Born): I = |dV (n^2 - 1)|^2 on every pixel, and the expected count is the
     # scalar Rayleigh-Gans cross-section k0^4 |alpha|^2 with alpha = dV (n^2 - 1) / (4 pi)
