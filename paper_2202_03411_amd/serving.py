@@ -17,6 +17,7 @@ from __future__ import annotations
 
 import collections
 import dataclasses
+import json
 import math
 import time
 from typing import Callable
@@ -37,6 +38,7 @@ class Request:
     wave_blocks: int = 1           # blocks the device runs at once: slices are multiples of it
     next_block: int = 0            # first block not launched yet
     open_items: int = 0            # launched items not finished yet
+    launches: int = 0              # launches that carried some of its blocks
     result: object = None
     state: object = None           # executor's per-request device state
 
@@ -85,10 +87,15 @@ class Scheduler:
     its first launch to its completion, each launch item's scratch while it runs; the
     total stays within hbm_budget.  With quantum None nothing is sliced and requests
     are grouped first-come first-served up to max_batch.
+
+    latency_log, a writable text stream, receives one JSON line per finished request
+    (completed or rejected), in the order they finish: its id, geometry key, arrival,
+    first launch and completion times (seconds on the scheduler's clock), latency and
+    queueing time (ms), pixel blocks and the number of launches that carried them.
     """
 
     def __init__(self, executor, hbm_budget: int, max_inflight: int = 3, max_batch: int = 24,
-                 clock: Callable[[], float] = time.perf_counter, quantum=None):
+                 clock: Callable[[], float] = time.perf_counter, quantum=None, latency_log=None):
         if max_inflight < 1 or max_batch < 1:
             raise ValueError("max_inflight and max_batch must be >= 1")
         if quantum is not None and not quantum > 0:
@@ -104,14 +111,31 @@ class Scheduler:
         self.used = 0
         self.completed: list = []
         self.rejected: list = []
+        self.log = latency_log
+
+    def _log(self, r, status):
+        if self.log is None:
+            return
+
+        def num(v):
+            return None if v is None or (isinstance(v, float) and math.isnan(v)) else v
+        done, adm = num(r.done), num(r.admitted)
+        rec = {"rid": r.rid, "status": status, "key": repr(r.key), "arrival_s": r.arrival,
+               "admitted_s": adm, "done_s": done,
+               "latency_ms": None if done is None else 1e3 * (done - r.arrival),
+               "queue_ms": None if adm is None else 1e3 * (adm - r.arrival),
+               "blocks": r.blocks, "launches": r.launches}
+        self.log.write(json.dumps(rec) + "\n")
 
     def submit(self, req: Request):
         self.ex.describe(req)
         req.next_block = 0
         req.open_items = 0
+        req.launches = 0
         if req.footprint > self.budget:
             # could never be admitted: refuse instead of blocking the queue
             self.rejected.append(req)
+            self._log(req, "rejected")
             return False
         self.queue.append(req)
         return True
@@ -130,6 +154,7 @@ class Scheduler:
                         self.ex.complete(r)
                         self.used -= r.io_bytes
                         self.completed.append(r)
+                        self._log(r, "completed")
             else:
                 still.append(b)
         self.inflight = still
@@ -141,6 +166,7 @@ class Scheduler:
         items.append((r, b0, b1))
         r.next_block = b1
         r.open_items += 1
+        r.launches += 1
         need = r.ws_bytes + (r.io_bytes if b0 == 0 else 0)
         return need
 
@@ -490,14 +516,15 @@ def make_requests(count, seed, rate=None, wavelength=45.0, theta=60.0, grids=SER
 
 
 def serve(torch, msft, plans, requests, batched=True, hbm_budget=16 << 30, slots=4, max_batch=24,
-          quantum_s=0.005, progress=None, keep_inputs=False):
+          quantum_s=0.005, progress=None, keep_inputs=False, latency_log=None):
     """Run a request list through the server; returns (summary, requests).  A batched
     launch holds at most quantum_s of the plans' measured work: expensive requests
-    are sliced into pixel-block ranges of that size (None: no slicing)."""
+    are sliced into pixel-block ranges of that size (None: no slicing).  latency_log:
+    a text stream for the per-request JSON lines (Scheduler)."""
     ex = GpuExecutor(plans, torch, nstreams=slots, batched=batched, keep_inputs=keep_inputs)
     sched = Scheduler(ex, hbm_budget, max_inflight=slots if batched else 1 << 30,
                       max_batch=max_batch if batched else 1,
-                      quantum=quantum_s if batched else None)
+                      quantum=quantum_s if batched else None, latency_log=latency_log)
     t0 = run_stream(sched, requests, progress=progress)
     torch.cuda.synchronize()
     t_end = max(r.done for r in sched.completed) if sched.completed else t0
@@ -507,13 +534,26 @@ def serve(torch, msft, plans, requests, batched=True, hbm_budget=16 << 30, slots
     return s, sched.completed
 
 
+class _TaggedLog:
+    """Adds the run's name to each JSON line written through it."""
+
+    def __init__(self, f, run):
+        self.f, self.run = f, run
+
+    def write(self, line):
+        rec = json.loads(line)
+        rec["run"] = self.run
+        self.f.write(json.dumps(rec) + "\n")
+
+
 def benchmark(count=96, precision="fp32", loads=(0.8,), seed=20220205, device=0, plain=True,
-              log=None, capacity=None):
+              log=None, capacity=None, latency_log=None):
     """The mixed-size stream served three ways: offline (all requests at t = 0),
     whose batched throughput is the measured capacity, then Poisson arrivals at
     each offered load rho * capacity.  Every stream runs batched and, if `plain`,
     as one pattern per launch on one stream.  A given capacity (patterns/s, from an
-    earlier offline run of the same stream) skips the offline runs."""
+    earlier offline run of the same stream) skips the offline runs.  latency_log: a
+    path that receives every run's per-request JSON lines, each tagged with its run."""
     import torch
 
     from . import msft
@@ -531,7 +571,12 @@ def benchmark(count=96, precision="fp32", loads=(0.8,), seed=20220205, device=0,
         reqs = make_requests(count, seed, rate)
         mode = "batched" if batched else "plain"
         prog = (lambda d, n: log(f"{name} {mode}: {d}/{n} done")) if log else None
-        s, _ = serve(torch, msft, plans, reqs, batched=batched, progress=prog)
+        if latency_log:
+            with open(latency_log, "a") as f:
+                s, _ = serve(torch, msft, plans, reqs, batched=batched, progress=prog,
+                             latency_log=_TaggedLog(f, f"{name}_{mode}"))
+        else:
+            s, _ = serve(torch, msft, plans, reqs, batched=batched, progress=prog)
         out[f"{name}_{s['mode']}"] = s
         if log:
             log(f"{name} {mode}: {s['patterns_per_s']:.2f} patterns/s, p50 {s['p50_ms']:.1f} ms, "
@@ -567,8 +612,10 @@ if __name__ == "__main__":
     ap.add_argument("--no-plain", action="store_true", help="skip the one-pattern-per-launch runs")
     ap.add_argument("--capacity", type=float, default=None,
                     help="batched capacity (patterns/s) of an earlier offline run: skip the offline runs")
+    ap.add_argument("--latency-log", default=None,
+                    help="append one JSON line per request (every run, tagged) to this file")
     args = ap.parse_args()
     res = benchmark(args.requests, args.precision, tuple(args.loads), plain=not args.no_plain,
                     log=lambda m: print(f"[serving] {m}", file=sys.stderr, flush=True),
-                    capacity=args.capacity)
+                    capacity=args.capacity, latency_log=args.latency_log)
     print(json.dumps(res))

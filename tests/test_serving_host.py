@@ -214,3 +214,31 @@ def test_slices_are_whole_device_waves():
     sched.submit(Request(1, clock.t, "m"))
     _drive(sched, clock, [])
     assert [b1 - b0 for h in ex.launches for _, b0, b1 in h["items"]] == [4, 4, 2]
+
+
+def test_latency_log_one_line_per_request():
+    import io
+    import json
+    clock = Clock()
+    spec = {"a": (10, 5, 4, 0.002), "b": (10, 5, 40, 0.002), "huge": (10 ** 6, 0, 1, 0.001)}
+    ex = FakeExecutor(clock, spec)
+    log = io.StringIO()
+    sched = Scheduler(ex, hbm_budget=100, max_inflight=2, max_batch=4, clock=clock, quantum=0.02,
+                      latency_log=log)
+    reqs = [Request(k, 0.003 * k, "a" if k % 3 else "b") for k in range(9)] + [Request(99, 0.01, "huge")]
+    _drive(sched, clock, reqs)
+    recs = [json.loads(line) for line in log.getvalue().splitlines()]
+    assert len(recs) == len(reqs)
+    by = {r["rid"]: r for r in recs}
+    assert by[99]["status"] == "rejected" and by[99]["latency_ms"] is None and by[99]["launches"] == 0
+    for r in sched.completed:
+        e = by[r.rid]
+        assert e["status"] == "completed"
+        assert math.isclose(e["latency_ms"], 1e3 * r.latency, rel_tol=1e-12)
+        assert 0.0 <= e["queue_ms"] <= e["latency_ms"]
+        assert e["blocks"] == r.blocks and e["launches"] >= 1
+    # an expensive request went out in several slices
+    assert max(by[r.rid]["launches"] for r in sched.completed if r.key == "b") > 1
+    # completed lines come in completion order
+    done = [e["done_s"] for e in recs if e["status"] == "completed"]
+    assert done == sorted(done)
