@@ -11,10 +11,12 @@
 // planes of each operand made ahead: the A operands at plan time (phases in FP64),
 // the W tiles by the column scan, H by stage 1.
 //
-// Stage 1 (v_mfma_f32_32x32x2_f32): rows are a wave's 32 columns i, columns the 32 z
-// of a W tile, K two x values (x parity = lane half), as in the flat detector's
-// Gauss kernel; a workgroup of 4 waves takes 128 columns, two consecutive y and one
-// z block, and the sums over the x chunks stay in the MFMA accumulators.
+// Stage 1 (v_mfma_f32_16x16x4_f32): rows are a wave's 16 columns i, columns 16 z of
+// a W tile, K four x values; a workgroup of 4 waves takes 64 columns, one z block and
+// two quads of 4 consecutive y in turn, the sums over the x chunks stay in the MFMA
+// accumulators, and each lane ends a quad with 4 consecutive y of its columns at 2 z:
+// whole 16-byte slots of the H tiles.  The column blocks that read the same W tiles
+// run on one XCD.
 //
 // Stage 2 (v_mfma_f32_16x16x4_f32): rows are a wave's 16 rows j, columns 16 z, K
 // four y values.  The wave keeps its A operand for every y (at most 128: 96
