@@ -153,7 +153,7 @@ struct SepDims {
     // ... and of its adjoint: chunks of 32 columns i (and of 32 rows j), K in three
     // planes [i][y][z], A tables of the two passes.
     int32_t nic3 = 0;
-    size_t kg_bytes(int ny, int nzb) const { return (size_t)3 * nic3 * 32 * ny * nzb * ZB * 4; }
+    size_t kg_bytes(int ny, int nzb) const { return (size_t)2 * nic3 * 32 * ny * nzb * ZB * 4; }
     size_t tyTg_bytes(int ny) const { return (size_t)ceil_div(ny, 64) * 4 * nic3 * SG2_A_BYTES; }
     size_t txTg_bytes(int nx) const { return (size_t)ceil_div(nx, 128) * 4 * nic3 * G3_TILE_BYTES; }
 };
@@ -190,7 +190,7 @@ struct SepG3AdjArgs {
     const float* tz;        // the plan's Tz over stage 2's pixel order (16-row tiles)
     const uint8_t* tyT;     // pass 1 A tables [16 rows y][j chunk of 32]
     const uint8_t* txT;     // pass 2 A tiles [32 rows x][i chunk of 32]
-    float* kplain;          // K in three planes Kr, Ki, Kr + Ki of [nic3 * 32][ny][nz2] floats
+    float* kplain;          // K in two planes Kr, Ki of [nic3 * 32][ny][nz2] floats
     float* rpart;           // [SEPG_ADJ_SPLIT][rows_pad][ny][nz2] complex
     int32_t n, npad, nx, ny, nzb, nz2, njc2, nic3, rows_pad;
 };

@@ -630,8 +630,8 @@ __global__ __launch_bounds__(SG_THREADS, 2) void sepg_adj_rows_kernel(SepG3AdjAr
             }
         }
     }
-    // K = (P1 - P2) + i (P3 - P1 - P2) and Kr + Ki, planes of [i][y][z2] floats: 16
-    // lanes write 16 consecutive z
+    // K = (P1 - P2) + i (P3 - P1 - P2), planes Kr, Ki of [i][y][z2] floats (pass 2
+    // forms Kr + Ki from them): 16 lanes write 16 consecutive z
     const size_t plane = (size_t)a.nic3 * 32 * a.ny * a.nz2;
 #pragma unroll
     for (int c = 0; c < SGA_COLS; ++c) {
@@ -647,7 +647,6 @@ __global__ __launch_bounds__(SG_THREADS, 2) void sepg_adj_rows_kernel(SepG3AdjAr
                     const float ki = (P[c][2][nt][r] - P[c][0][nt][r]) - P[c][1][nt][r];
                     k[16 * nt] = kr;
                     k[plane + 16 * nt] = ki;
-                    k[2 * plane + 16 * nt] = kr + ki;
                 }
             }
         }
@@ -674,20 +673,22 @@ __global__ __launch_bounds__(SG_THREADS, 2) void sepg_adj_cols_kernel(SepG3AdjAr
     const int y0 = 2 * blockIdx.y;
     const int nyh = min(2, a.ny - y0);   // >= 1
     const size_t plane = (size_t)a.nic3 * 32 * a.ny * a.nz2;
-    // the thread's slots: (plane q, h, z = col, g = wave); i = 32 kc + 8 g + 2 e + h
-    auto load_tile = [&](int kc, int y, float (&v)[3][4]) {
+    // the thread's slots: (plane q, h, z = col, g = wave); i = 32 kc + 8 g + 2 e + h;
+    // planes Kr, Ki are loaded, Kr + Ki formed here (the same FP32 sum pass 1 would store)
+    auto load_tile = [&](int kc, int y, float (&v)[2][4]) {
 #pragma unroll
-        for (int q = 0; q < 3; ++q)
+        for (int q = 0; q < 2; ++q)
 #pragma unroll
             for (int e = 0; e < 4; ++e)
                 v[q][e] = a.kplain[q * plane + ((size_t)(32 * kc + 8 * wave + 2 * e + h) * a.ny + y) * a.nz2 +
                                    zb * ZB + col];
     };
-    auto store_tile = [&](uint8_t* slot, const float (&v)[3][4]) {
-#pragma unroll
-        for (int q = 0; q < 3; ++q)
-            *(f32x4*)(slot + q * SG_PLANE_BYTES + (h * ZB + col) * G3_ROW_BYTES + ((wave ^ g3_swizzle(col)) << 4)) =
-                f32x4{v[q][0], v[q][1], v[q][2], v[q][3]};
+    auto store_tile = [&](uint8_t* slot, const float (&v)[2][4]) {
+        uint8_t* q0 = slot + (h * ZB + col) * G3_ROW_BYTES + ((wave ^ g3_swizzle(col)) << 4);
+        *(f32x4*)q0 = f32x4{v[0][0], v[0][1], v[0][2], v[0][3]};
+        *(f32x4*)(q0 + SG_PLANE_BYTES) = f32x4{v[1][0], v[1][1], v[1][2], v[1][3]};
+        *(f32x4*)(q0 + 2 * SG_PLANE_BYTES) =
+            f32x4{v[0][0] + v[1][0], v[0][1] + v[1][1], v[0][2] + v[1][2], v[0][3] + v[1][3]};
     };
     f32x16 P[2][3];
 #pragma unroll
@@ -695,7 +696,7 @@ __global__ __launch_bounds__(SG_THREADS, 2) void sepg_adj_cols_kernel(SepG3AdjAr
 #pragma unroll
         for (int q = 0; q < 3; ++q) P[u][q] = f32x16{};
     if (kc0 < kc1) {
-        float v[3][4];
+        float v[2][4];
         load_tile(kc0, y0, v);
         store_tile(lds, v);
         __syncthreads();
