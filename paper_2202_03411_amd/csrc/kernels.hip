@@ -533,8 +533,8 @@ __device__ __forceinline__ void rotate_add(float* G, const f32x16& C, const f32x
 // x chunk in registers, so each B fragment read from LDS feeds six MFMAs instead of
 // three.  Two workgroups share a CU (256 registers per lane), so that one
 // workgroup's barrier and Ty rotation run under the other's matrix work.  Each slot
-// of a two-slot LDS ring holds one W tile and the Ty rows of the block's 8 wave
-// tiles at that tile's y; the next slot is filled by direct global -> LDS loads
+// of a two-slot LDS ring holds one W tile (rows padded, below) and the Ty rows of
+// the block's 8 wave tiles at that tile's y; the next slot is filled by direct global -> LDS loads
 // issued at the start of each stage, under the stage's MFMA chain.  The per-lane
 // sums over z blocks live in LDS.  Measured against one workgroup of 8 waves with
 // one wave tile each (128³ / 512², BF16 split): 7.33 ms against 8.29; a third
@@ -542,41 +542,55 @@ __device__ __forceinline__ void rotate_add(float* G, const f32x16& C, const f32x
 // ---------------------------------------------------------------------------
 constexpr int PW_WAVES = 4;
 constexpr int PW_THREADS = 64 * PW_WAVES;
-constexpr int PW_COPY = (TILE_BYTES / 16) / PW_THREADS;   // 16-byte pieces per thread per W tile
-constexpr int PW_TY_BYTES = WAVES * WAVE_PIX * 8;         // Ty of a block's wave tiles at one y
-constexpr int PW_SLOT = TILE_BYTES + PW_TY_BYTES;
-static_assert(PW_COPY * PW_THREADS == TILE_BYTES / 16, "a tile is copied in whole pieces");
+// In LDS a W tile row is padded by one 16-byte piece (272 bytes): the 16 lanes of a
+// ds_read_b128 group (16 consecutive rows) then start 4 banks apart and meet all 64
+// banks, and a lane reads every slot of its row at an immediate offset from one row
+// address.  The pad pieces are filled with a copy of the row's first piece.
+constexpr int PW_ROW = ROW_BYTES + 16;                     // 272
+constexpr int PW_ROWS = 2 * ZB;                            // 64 rows (h, z)
+constexpr int PW_PIECES = PW_ROWS * (PW_ROW / 16);         // 1088 pieces of 16 bytes
+constexpr int PW_TILE = PW_ROWS * PW_ROW;                  // 17408 bytes
+constexpr int PW_COPY = PW_PIECES / PW_THREADS;            // 4 whole passes (wave 0: a fifth)
+constexpr int PW_TY_BYTES = WAVES * WAVE_PIX * 8;          // Ty of a block's wave tiles at one y
+constexpr int PW_SLOT = PW_TILE + PW_TY_BYTES;
+static_assert(PW_PIECES == PW_COPY * PW_THREADS + 64, "four passes plus one wave's pieces");
 static_assert(2 * PW_WAVES == WAVES && PW_TY_BYTES == 64 * 16, "one wave gathers the Ty rows");
-static_assert(ROW_BYTES == 256 && PW_SLOT % 256 == 0, "W tile rows start on 256-byte boundaries");
-// Slot contents for tile tn (whose y is yn): the W tile and, from wave 0, the
-// block's Ty rows at yn.  Wave 0 issues PW_COPY + 1 loads, the others PW_COPY.
+static_assert(ROW_BYTES == 256 && TILE_BYTES == PW_ROWS * ROW_BYTES, "a W tile is 64 rows of 16 slots");
+// Global piece of the tile for LDS piece p: row p / 17, slot p % 17 (the pad slot 16
+// takes the row's slot 0); a row's logical slot k sits at global slot k ^ (row % 16).
+__device__ __forceinline__ int pw_src_piece(int p)
+{
+    const int row = p / (PW_ROW / 16), k = p % (PW_ROW / 16);
+    return row * 16 + (k < 16 ? (k ^ (row & 15)) : (row & 15));
+}
+// Slot contents for tile tn (whose y is yn): the padded W tile (waves 0-3 four
+// passes, wave 0 the last 64 pieces) and, from wave 1, the block's Ty rows at yn.
+// src: the lane's global pieces for passes 0-4 (pw_src_piece, fixed per lane).
 __device__ __forceinline__ void pw_fill(const FwdArgs& a, int64_t wtb, int64_t tn, int yn, const u32x4* gw,
-                                        uint8_t* slot)
+                                        uint8_t* slot, const int (&src)[PW_COPY + 1])
 {
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const u32x4* tile = gw + tn * (TILE_BYTES / 16);
 #pragma unroll
     for (int c = 0; c < PW_COPY; ++c)
-        lds_dma16(gw + tn * (TILE_BYTES / 16) + c * PW_THREADS + wave * 64 + lane,
-                  slot + (c * PW_THREADS + wave * 64) * 16);
-    if (wave == 0)
-        lds_dma16(a.ty + 2 * ((wtb + (lane >> 3)) * a.ny + yn) * WAVE_PIX + (lane & 7) * 4, slot + TILE_BYTES);
+        lds_dma16(tile + src[c], slot + (c * PW_THREADS + wave * 64) * 16);
+    if (wave == 0) lds_dma16(tile + src[PW_COPY], slot + PW_COPY * PW_THREADS * 16);
+    if (wave == 1)
+        lds_dma16(a.ty + 2 * ((wtb + (lane >> 3)) * a.ny + yn) * WAVE_PIX + (lane & 7) * 4, slot + PW_TILE);
 }
 
 // C0, C1 = the wave's two row tiles against one W tile; each B fragment read once.
-// row: the lane's row of the current slot.  A slot starts on a 256-byte boundary,
-// so the swizzled slot (s ^ sw) of the row is the row address with (sw << 4) folded
-// in, XOR (s << 4): one operation per read and no offset registers, which leaves
-// room to read the next step's fragments under the current step's products.
+// row: the lane's padded row in the current slot; slot s of the tile's logical order
+// is at row + 16 s.  A fixed instruction order (LDS reads: mask 0x100, MFMA: 0x008)
+// issues the reads of steps 0 and 1 first and then, after each step's products, the
+// reads of step s + 2, so each read lands under a whole step of matrix work.
 template <int PREC, bool FULL>
-__device__ __forceinline__ void tile_product2(const uint8_t* row, int col, int xlen, const bf16x8* Ah0,
+__device__ __forceinline__ void tile_product2(const uint8_t* row, int xlen, const bf16x8* Ah0,
                                               const bf16x8* Al0, const bf16x8* Ah1, const bf16x8* Al1,
                                               f32x16& C0, f32x16& C1)
 {
-    typedef __attribute__((address_space(3))) const uint8_t lds_u8;
-    typedef __attribute__((address_space(3))) const bf16x8 lds_b8;
-    const uint32_t a0 = (uint32_t)(uintptr_t)(lds_u8*)row + ((col & 15) << 4);   // LDS byte address
-    auto rd = [&](int slot) { return *(lds_b8*)(uintptr_t)(a0 ^ (uint32_t)(slot << 4)); };
+    auto rd = [&](int slot) { return *(const bf16x8*)(row + 16 * slot); };
     C0 = f32x16{};
     C1 = f32x16{};
     bf16x8 bh = rd(0), bl = PREC == MSFT_BF16X3 ? rd(8) : bh;
@@ -601,9 +615,6 @@ __device__ __forceinline__ void tile_product2(const uint8_t* row, int col, int x
         bl = nl;
     }
     if (FULL && PREC == MSFT_BF16X3) {
-        // Instruction order (LDS reads: mask 0x100, MFMA: 0x008): the reads of steps
-        // 0 and 1, then per step its 6 products and the reads of step s + 2, so each
-        // read has a whole step of products to land under.
         __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
 #pragma unroll
         for (int s = 0; s < XC / 8; ++s) {
@@ -626,7 +637,8 @@ __device__ __forceinline__ void tile_product2(const uint8_t* row, int col, int x
 template <int PREC, bool FULL>
 __device__ __forceinline__ void chunk_pair(const FwdArgs& a, int64_t wt0, int64_t ntiles, const u32x4* gw,
                                            uint8_t* lds, int xlen, const bf16x8* Ah0, const bf16x8* Al0,
-                                           const bf16x8* Ah1, const bf16x8* Al1, int64_t& t, float* accl)
+                                           const bf16x8* Ah1, const bf16x8* Al1, int64_t& t, float* accl,
+                                           const int (&src)[PW_COPY + 1])
 {
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -640,18 +652,18 @@ __device__ __forceinline__ void chunk_pair(const FwdArgs& a, int64_t wt0, int64_
             // the next slot (the last tile again at the very end, with y = 0: a slot
             // nobody reads again); tiles run y fastest
             pw_fill(a, wtb, min(t + 1, ntiles - 1), y + 1 == a.ny ? 0 : y + 1, gw,
-                    lds + (size_t)((t + 1) & 1) * PW_SLOT);
+                    lds + (size_t)((t + 1) & 1) * PW_SLOT, src);
             const uint8_t* cur = lds + (size_t)(t & 1) * PW_SLOT;
             f32x16 C0, C1;
             // matrix work at raised priority: a SIMD's other wave (of the other
             // workgroup) fills the gaps with its rotation and barrier
             __builtin_amdgcn_s_setprio(1);
-            tile_product2<PREC, FULL>(cur + (h * ZB + col) * ROW_BYTES, col, xlen, Ah0, Al0, Ah1, Al1, C0, C1);
+            tile_product2<PREC, FULL>(cur + (h * ZB + col) * PW_ROW, xlen, Ah0, Al0, Ah1, Al1, C0, C1);
             __builtin_amdgcn_s_setprio(0);
-            const f32x4* ty0 = (const f32x4*)(cur + TILE_BYTES + (2 * wave) * 128 + h * 64);
+            const f32x4* ty0 = (const f32x4*)(cur + PW_TILE + (2 * wave) * 128 + h * 64);
             const f32x4 t0[4] = {ty0[0], ty0[1], ty0[2], ty0[3]};
             rotate_add(G0, C0, t0);
-            const f32x4* ty1 = (const f32x4*)(cur + TILE_BYTES + (2 * wave + 1) * 128 + h * 64);
+            const f32x4* ty1 = (const f32x4*)(cur + PW_TILE + (2 * wave + 1) * 128 + h * 64);
             const f32x4 t1[4] = {ty1[0], ty1[1], ty1[2], ty1[3]};
             rotate_add(G1, C1, t1);
             // the next slot's loads have landed (the compiler does not track them)
@@ -688,7 +700,12 @@ __device__ __forceinline__ void fwd_pair_block(const FwdArgs& a, int64_t block, 
     const int64_t ntiles = (int64_t)a.nxc * a.nzb * a.ny;
     const u32x4* gw = (const u32x4*)a.wtiles;
 
-    pw_fill(a, wtb, 0, 0, gw, lds);
+    // the lane's global pieces of the five fill passes (the fifth only on wave 0)
+    int src[PW_COPY + 1];
+#pragma unroll
+    for (int c = 0; c < PW_COPY; ++c) src[c] = pw_src_piece(c * PW_THREADS + tid);
+    src[PW_COPY] = pw_src_piece(PW_COPY * PW_THREADS + lane);
+    pw_fill(a, wtb, 0, 0, gw, lds, src);
     float* accl = accs + wave * 32 * 64 + lane;
 #pragma unroll
     for (int q = 0; q < 32; ++q) accl[q * 64] = 0.0f;
@@ -705,9 +722,9 @@ __device__ __forceinline__ void fwd_pair_block(const FwdArgs& a, int64_t block, 
         // one wait for the A operands per chunk (the memory counter is in order)
         __builtin_amdgcn_s_waitcnt(0);
         if (xlen == XC)
-            chunk_pair<PREC, true>(a, wt0, ntiles, gw, lds, xlen, Ah0, Al0, Ah1, Al1, t, accl);
+            chunk_pair<PREC, true>(a, wt0, ntiles, gw, lds, xlen, Ah0, Al0, Ah1, Al1, t, accl, src);
         else
-            chunk_pair<PREC, false>(a, wt0, ntiles, gw, lds, xlen, Ah0, Al0, Ah1, Al1, t, accl);
+            chunk_pair<PREC, false>(a, wt0, ntiles, gw, lds, xlen, Ah0, Al0, Ah1, Al1, t, accl, src);
     }
     const int h = lane >> 5, col = lane & 31;
     // sum over the 32 z lanes of each half (fixed butterfly order)
@@ -741,7 +758,7 @@ __device__ __forceinline__ void fwd_pair_block(const FwdArgs& a, int64_t block, 
 template <int PREC>
 __global__ __launch_bounds__(PW_THREADS, 2) void fwd_pair_kernel(FwdArgs a, int64_t block_begin)
 {
-    __shared__ __attribute__((aligned(256))) uint8_t lds[2 * PW_SLOT];
+    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * PW_SLOT];
     __shared__ float accs[PW_WAVES * 32 * 64];
     fwd_pair_block<PREC>(a, block_begin + blockIdx.x, lds, accs);
 }
@@ -750,7 +767,7 @@ __global__ __launch_bounds__(PW_THREADS, 2) void fwd_pair_kernel(FwdArgs a, int6
 template <int PREC>
 __global__ __launch_bounds__(PW_THREADS, 2) void fwd_pair_batch_kernel(BatchArgs b)
 {
-    __shared__ __attribute__((aligned(256))) uint8_t lds[2 * PW_SLOT];
+    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * PW_SLOT];
     __shared__ float accs[PW_WAVES * 32 * 64];
     const int32_t it = blockIdx.x;
     int r = 0;
