@@ -227,6 +227,41 @@ def time_uniform(msft, torch, wl, d, b, prec, steps, warmup):
             "error_vs_fp64_oracle": {"rel_l2_intensity": err, "pixels": int(ok.sum())}}
 
 
+def time_peaks(msft, torch):
+    """What this device sustains: pure matrix-core loops (four accumulator chains per
+    wave, four waves per workgroup, four workgroups per CU, no memory traffic) in FP32
+    and BF16, and the HBM rate of a 1 GiB device copy (bytes read plus written)."""
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    nblocks = 4 * cus
+    sink = torch.empty(nblocks * 256, dtype=torch.float32, device="cuda")
+    out = {}
+    for prec, name, iters in (("fp32", "fp32_mfma_tflops", 20000), ("bf16x3", "bf16_mfma_tflops", 40000)):
+        msft.msft_peak_mfma(prec, 100, nblocks, sink)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fl = sum(msft.msft_peak_mfma(prec, iters, nblocks, sink) for _ in range(3))
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = fl / (e0.elapsed_time(e1) * 1e-3) / 1e12
+    n = 1 << 28
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    msft.msft_copy(src, dst)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        msft.msft_copy(src, dst)
+    e1.record()
+    torch.cuda.synchronize()
+    out["hbm_copy_gbs"] = 2 * 4 * n * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    out["copy_bytes"] = 2 * 4 * n
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
 def time_render(msft, torch, steps):
     """The fit's star-body renderer on 128^3 (l <= 8, soft edge of one pitch), its
     coefficient gradient, and a 96^3 volume map resampled onto the same grid."""
@@ -536,6 +571,18 @@ def main():
         line["render"] = time_render(msft, torch, args.steps)
         print(f"[bench] render l<=8 soft star 128^3: {line['render']['render_ms'] * 1e3:.1f} us, "
               f"gradient {line['render']['gradient_ms'] * 1e3:.1f} us", file=sys.stderr, flush=True)
+    if not args.only:
+        pk = time_peaks(msft, torch)
+        # the headline kernels against what the device sustains (roofline.peak stays the
+        # published figure)
+        pk["fwd_g3_frac_of_sustained"] = line["roofline"]["achieved"] / pk["fp32_mfma_tflops"]
+        v3 = line["variants"].get("bf16x3")
+        if v3:
+            pk["fwd_pair_bf16x3_frac_of_sustained"] = 3.0 * v3["contract_tflops"] / pk["bf16_mfma_tflops"]
+        line["peaks"] = pk
+        print(f"[bench] sustained: FP32 MFMA {pk['fp32_mfma_tflops']:.1f} TF/s, BF16 MFMA "
+              f"{pk['bf16_mfma_tflops']:.1f} TF/s, HBM copy {pk['hbm_copy_gbs']:.0f} GB/s",
+              file=sys.stderr, flush=True)
     if args.fit > 0 and not args.only:
         dets = ["flat", "uniform_q"] if args.fit_detector == "both" else [args.fit_detector]
         line["fit"] = {}

@@ -344,6 +344,28 @@ msft_status msft_render_volume(const msft_shape_grid* g, int32_t sx, int32_t sy,
                                double sdx, double sdy, double sdz, const float* src_delta,
                                const float* src_beta, float* delta, float* beta, void* stream);
 
+/*
+ * Machine peaks for the roofline fractions of the measured contractions (the
+ * performance figures of Sec. 6): what this device sustains on pure matrix-core
+ * work and on a streaming copy, beside the vendor's published peaks.
+ *
+ * msft_peak_mfma: nblocks workgroups of 256 threads; every wave runs `iters`
+ *   rounds of four independent accumulator chains of v_mfma_f32_32x32x2_f32
+ *   (precision MSFT_FP32) or v_mfma_f32_32x32x16_bf16 (MSFT_BF16X3) on register
+ *   operands, then stores one float per thread into sink (device, nblocks * 256
+ *   floats, written) so that no work is elided.  *flops (host) receives the real
+ *   flops of the launch.  Errors: MSFT_ERR_INVALID for another precision,
+ *   iters < 1, nblocks < 1, NULL sink or flops.
+ * msft_copy: dst[i] = src[i] over `bytes` bytes in 16-byte pieces (device
+ *   pointers, 16-byte aligned; bytes a multiple of 16); the buffers must not
+ *   overlap.  Errors: MSFT_ERR_INVALID for NULL pointers, misalignment or a byte
+ *   count that is not a multiple of 16.
+ * Both run asynchronously on stream on the current device.
+ */
+msft_status msft_peak_mfma(int32_t precision, int32_t iters, int32_t nblocks, float* sink, double* flops,
+                           void* stream);
+msft_status msft_copy(const void* src, void* dst, size_t bytes, void* stream);
+
 /* Static description of a status code. */
 const char* msft_status_str(msft_status s);
 

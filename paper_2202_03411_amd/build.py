@@ -22,7 +22,7 @@ HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wextra", "-Wno-unused-par
 
 SOURCES_HOST = ["geometry.cpp", "abi.cpp"]
 SOURCES_HIP = ["kernels.hip", "gauss.hip", "backward.hip", "render.hip", "detector.hip",
-               "noalloc.hip", "sepg.hip"]
+               "noalloc.hip", "sepg.hip", "peaks.hip"]
 
 
 def _run(cmd, verbose):

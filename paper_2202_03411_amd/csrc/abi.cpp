@@ -617,6 +617,28 @@ msft_status msft_detect_ideal(msft_plan_t plan, const float* intensity, double p
     return ok();
 }
 
+msft_status msft_peak_mfma(int32_t precision, int32_t iters, int32_t nblocks, float* sink, double* flops,
+                           void* stream)
+{
+    if (precision != MSFT_FP32 && precision != MSFT_BF16X3)
+        return fail(MSFT_ERR_INVALID, "precision must be MSFT_FP32 or MSFT_BF16X3");
+    if (iters < 1 || nblocks < 1 || !sink || !flops)
+        return fail(MSFT_ERR_INVALID, "iters and nblocks must be >= 1, sink and flops non-NULL");
+    int e = launch_peak_mfma(precision, iters, nblocks, sink, flops, stream);
+    if (e) return hip_fail((hipError_t)e, "peak launch");
+    return ok();
+}
+
+msft_status msft_copy(const void* src, void* dst, size_t bytes, void* stream)
+{
+    if (!src || !dst || bytes % 16 || (uintptr_t)src % 16 || (uintptr_t)dst % 16)
+        return fail(MSFT_ERR_INVALID, "src and dst must be 16-byte aligned and bytes a multiple of 16");
+    if (bytes == 0) return ok();
+    int e = launch_copy(src, dst, (int64_t)(bytes / 16), stream);
+    if (e) return hip_fail((hipError_t)e, "copy launch");
+    return ok();
+}
+
 msft_status msft_plan(const msft_geometry* g, int device, msft_plan_t* out)
 {
     return make_plan(g, nullptr, 0, device, out);

@@ -343,6 +343,9 @@ int launch_render_sh(const ShArgs& s, const float* coeffs, float* delta, float* 
 int launch_render_sh_grad(const ShArgs& s, const float* coeffs, const float* gd, const float* gb,
                           float* grad, double* partial, int nblocks, void* stream);
 int launch_render_ellipsoid(const EllArgs& e, float* delta, float* beta, void* stream);
+// Machine-peak probes (peaks.hip).  flops: the real flops of the launch.
+int launch_peak_mfma(int precision, int iters, int nblocks, float* sink, double* flops, void* stream);
+int launch_copy(const void* src, void* dst, int64_t pieces, void* stream);
 int launch_detect_ideal(const IdealArgs& a, const float* intensity, float* counts, float* expected,
                         void* stream);
 int launch_render_volume(const VolArgs& a, const float* sd, const float* sb, float* delta,

@@ -107,6 +107,8 @@ def _load():
     lib.msft_render_ellipsoid.argtypes = [P(msft_shape_grid), VP, VP, VP, VP, VP]
     lib.msft_detect_ideal.argtypes = [VP, VP, D, ctypes.c_uint64, VP, VP, VP]
     lib.msft_render_volume.argtypes = [P(msft_shape_grid), I32, I32, I32, D, D, D, VP, VP, VP, VP, VP]
+    lib.msft_peak_mfma.argtypes = [I32, I32, I32, VP, P(D), VP]
+    lib.msft_copy.argtypes = [VP, VP, S, VP]
     lib.msft_status_str.argtypes = [ctypes.c_int]
     lib.msft_status_str.restype = ctypes.c_char_p
     lib.msft_last_error.argtypes = []
@@ -115,7 +117,8 @@ def _load():
                  "msft_plan_qmap", "msft_plan_grid", "msft_simulate", "msft_simulate_scan",
                  "msft_simulate_contract", "msft_simulate_noalloc", "msft_pixel_block", "msft_batch_query", "msft_simulate_batch",
                  "msft_backward", "msft_render_sh", "msft_render_sh_query", "msft_render_sh_backward",
-                 "msft_render_ellipsoid", "msft_render_volume", "msft_detect_ideal"):
+                 "msft_render_ellipsoid", "msft_render_volume", "msft_detect_ideal", "msft_peak_mfma",
+                 "msft_copy"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -130,7 +133,7 @@ EXPORTS = ("msft_plan", "msft_plan_qlist", "msft_plan_destroy", "msft_plan_query
            "msft_batch_query",
            "msft_simulate_batch", "msft_backward", "msft_render_sh", "msft_render_sh_query",
            "msft_render_sh_backward", "msft_render_ellipsoid", "msft_render_volume",
-           "msft_detect_ideal", "msft_status_str",
+           "msft_detect_ideal", "msft_peak_mfma", "msft_copy", "msft_status_str",
            "msft_last_error")
 
 
@@ -484,6 +487,26 @@ def msft_render_volume(shape_grid, src_delta, src_beta, src_pitch, delta, beta, 
     _check(_lib.msft_render_volume(ctypes.byref(shape_grid), sx, sy, sz, sdx, sdy, sdz,
                                    _ptr(src_delta), _ptr(src_beta), _ptr(delta), _ptr(beta),
                                    _stream(stream)), "msft_render_volume")
+
+
+def msft_peak_mfma(precision, iters, nblocks, sink, stream=None) -> float:
+    """Launch the matrix-core peak probe; sink: float32 device tensor of nblocks * 256.
+    Returns the real flops of the launch."""
+    prec = {"fp32": MSFT_FP32, "bf16x3": MSFT_BF16X3}[precision]
+    _check_tensor(sink, "sink", int(nblocks) * 256, sink.device.index if sink.is_cuda else 0)
+    flops = ctypes.c_double(0.0)
+    _check(_lib.msft_peak_mfma(prec, int(iters), int(nblocks), _ptr(sink), ctypes.byref(flops), _stream(stream)),
+           "msft_peak_mfma")
+    return flops.value
+
+
+def msft_copy(src, dst, stream=None) -> None:
+    """dst = src for two contiguous device tensors of the same byte size."""
+    nbytes = src.numel() * src.element_size()
+    if not (src.is_cuda and dst.is_cuda and src.is_contiguous() and dst.is_contiguous()
+            and dst.numel() * dst.element_size() == nbytes and src.device == dst.device):
+        raise ValueError("msft_copy: contiguous device tensors of one size on one device")
+    _check(_lib.msft_copy(_ptr(src), _ptr(dst), nbytes, _stream(stream)), "msft_copy")
 
 
 def msft_detect_ideal(plan_handle, intensity, photon_density, seed, counts, expected=None,

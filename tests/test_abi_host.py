@@ -221,3 +221,18 @@ def test_noalloc_refuses_plans_beyond_its_fixed_scratch():
         assert "host-only" in msft.msft_last_error()
     finally:
         msft.msft_plan_destroy(h)
+
+
+def test_peak_probe_argument_errors():
+    # refused before anything is launched, so no device is needed
+    flops = ctypes.c_double(0.0)
+    lib = msft._lib
+    assert lib.msft_peak_mfma(7, 10, 1, ctypes.c_void_p(256), ctypes.byref(flops), None) == msft.MSFT_ERR_INVALID
+    assert lib.msft_peak_mfma(msft.MSFT_FP32, 0, 1, ctypes.c_void_p(256), ctypes.byref(flops), None) == \
+        msft.MSFT_ERR_INVALID
+    assert lib.msft_peak_mfma(msft.MSFT_FP32, 10, 1, None, ctypes.byref(flops), None) == msft.MSFT_ERR_INVALID
+    assert lib.msft_copy(ctypes.c_void_p(8), ctypes.c_void_p(256), 32, None) == msft.MSFT_ERR_INVALID
+    assert lib.msft_copy(ctypes.c_void_p(256), ctypes.c_void_p(512), 24, None) == msft.MSFT_ERR_INVALID
+    assert lib.msft_copy(None, ctypes.c_void_p(512), 32, None) == msft.MSFT_ERR_INVALID
+    # nothing to copy: nothing launched
+    assert lib.msft_copy(ctypes.c_void_p(256), ctypes.c_void_p(512), 0, None) == msft.MSFT_OK
