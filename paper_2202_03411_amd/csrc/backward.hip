@@ -222,9 +222,11 @@ __device__ __forceinline__ double suffix_sum(double v, int lane)
 // face back to the entrance.  S_s = sum_{s'<s} (beta + i delta) is the column total
 // minus the inclusive suffix, T = exp(-k0 dz S), and the propagation term needs the
 // exclusive suffix sum_{s'>s} R_s' w_s'; both suffixes come from wave scans plus
-// the carry of the segments already done.  FP64 throughout.
+// the carry of the segments already done.  Sums in FP64; T itself in FP32 from the
+// FP64 prefix (phase reduced to [-pi, pi] in FP64), as the forward scan forms it.
 __global__ __launch_bounds__(256) void adj_finalize(FinArgs a)
 {
+    constexpr double kTwoPi = 6.283185307179586476925286766559;
     const int lane = threadIdx.x & 63;
     const int64_t col = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (col >= (int64_t)a.nx * a.ny) return;   // wave-uniform
@@ -262,12 +264,16 @@ __global__ __launch_bounds__(256) void adj_finalize(FinArgs a)
         } else {
             double tr = 1.0, ti = 0.0;
             if (a.strength == MSFT_STRENGTH_MSFT) {
+                // T = exp(-k0 dz S) in FP32, as the forward scan forms it: the prefix
+                // sums stay FP64 and the phase is reduced to [-pi, pi] in FP64 first
                 const double sb = tot_b - (carry_b + sufb), sd = tot_d - (carry_d + sufd);
-                const double mag = exp(-k0dz * sb);
-                double sn, cs;
-                sincos(-k0dz * sd, &sn, &cs);
-                tr = mag * cs;
-                ti = mag * sn;
+                const double ph = -k0dz * sd;
+                const double phr = ph - kTwoPi * rint(ph * (1.0 / kTwoPi));
+                const float mag = expf((float)(-k0dz * sb));
+                float sn, cs;
+                sincosf((float)phr, &sn, &cs);
+                tr = (double)mag * (double)cs;
+                ti = (double)mag * (double)sn;
             }
             const double nr = 1.0 - d, ni = bt;
             // dw/d delta = dV T (-2 n), dw/d beta = dV T (2 i n)
