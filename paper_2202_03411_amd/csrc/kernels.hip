@@ -556,28 +556,28 @@ constexpr int PW_SLOT = PW_TILE + PW_TY_BYTES;
 static_assert(PW_PIECES == PW_COPY * PW_THREADS + 64, "four passes plus one wave's pieces");
 static_assert(2 * PW_WAVES == WAVES && PW_TY_BYTES == 64 * 16, "one wave gathers the Ty rows");
 static_assert(ROW_BYTES == 256 && TILE_BYTES == PW_ROWS * ROW_BYTES, "a W tile is 64 rows of 16 slots");
-// Global piece of the tile for LDS piece p: row p / 17, slot p % 17 (the pad slot 16
-// takes the row's slot 0); a row's logical slot k sits at global slot k ^ (row % 16).
-__device__ __forceinline__ int pw_src_piece(int p)
+// Byte offset in the tile of the global piece for LDS piece p: row p / 17, slot
+// p % 17 (the pad slot 16 takes the row's slot 0); a row's logical slot k sits at
+// global slot k ^ (row % 16).
+__device__ __forceinline__ uint32_t pw_src_bytes(int p)
 {
     const int row = p / (PW_ROW / 16), k = p % (PW_ROW / 16);
-    return row * 16 + (k < 16 ? (k ^ (row & 15)) : (row & 15));
+    return 16u * (uint32_t)(row * 16 + (k < 16 ? (k ^ (row & 15)) : (row & 15)));
 }
 // Slot contents for tile tn (whose y is yn): the padded W tile (waves 0-3 four
 // passes, wave 0 the last 64 pieces) and, from wave 1, the block's Ty rows at yn.
-// src: the lane's global pieces for passes 0-4 (pw_src_piece, fixed per lane).
-__device__ __forceinline__ void pw_fill(const FwdArgs& a, int64_t wtb, int64_t tn, int yn, const u32x4* gw,
-                                        uint8_t* slot, const int (&src)[PW_COPY + 1])
+// src: the lane's byte offsets in the tile for passes 0-4, and (last) its byte offset
+// in the block's Ty rows at one y.  Bases are wave-uniform, offsets 32-bit.
+__device__ __forceinline__ void pw_fill(const FwdArgs& a, int64_t wtb, int tn, int yn, const u32x4* gw,
+                                        uint8_t* slot, const uint32_t (&src)[PW_COPY + 2])
 {
-    const int tid = threadIdx.x, lane = tid & 63;
+    const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const u32x4* tile = gw + tn * (TILE_BYTES / 16);
+    const u32x4* tile = gw + (size_t)tn * (TILE_BYTES / 16);
 #pragma unroll
-    for (int c = 0; c < PW_COPY; ++c)
-        lds_dma16(tile + src[c], slot + (c * PW_THREADS + wave * 64) * 16);
-    if (wave == 0) lds_dma16(tile + src[PW_COPY], slot + PW_COPY * PW_THREADS * 16);
-    if (wave == 1)
-        lds_dma16(a.ty + 2 * ((wtb + (lane >> 3)) * a.ny + yn) * WAVE_PIX + (lane & 7) * 4, slot + PW_TILE);
+    for (int c = 0; c < PW_COPY; ++c) lds_dma16_s(tile, src[c], slot + (c * PW_THREADS + wave * 64) * 16);
+    if (wave == 0) lds_dma16_s(tile, src[PW_COPY], slot + PW_COPY * PW_THREADS * 16);
+    if (wave == 1) lds_dma16_s(a.ty + 2 * (wtb * a.ny + yn) * WAVE_PIX, src[PW_COPY + 1], slot + PW_TILE);
 }
 
 // C0, C1 = the wave's two row tiles against one W tile; each B fragment read once.
@@ -635,10 +635,10 @@ __device__ __forceinline__ void tile_product2(const uint8_t* row, int xlen, cons
 // All z blocks of one x chunk; tile t sits in slot t & 1.  accl: the lane's 32 sums
 // in LDS, stride 64 floats ([row tile][16]).
 template <int PREC, bool FULL>
-__device__ __forceinline__ void chunk_pair(const FwdArgs& a, int64_t wt0, int64_t ntiles, const u32x4* gw,
+__device__ __forceinline__ void chunk_pair(const FwdArgs& a, int64_t wt0, int ntiles, const u32x4* gw,
                                            uint8_t* lds, int xlen, const bf16x8* Ah0, const bf16x8* Al0,
-                                           const bf16x8* Ah1, const bf16x8* Al1, int64_t& t, float* accl,
-                                           const int (&src)[PW_COPY + 1])
+                                           const bf16x8* Ah1, const bf16x8* Al1, int& t, float* accl,
+                                           const uint32_t (&src)[PW_COPY + 2])
 {
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -697,14 +697,16 @@ __device__ __forceinline__ void fwd_pair_block(const FwdArgs& a, int64_t block, 
     const int lane = tid & 63, wave = tid >> 6;
     const int64_t wtb = block * WAVES;
     const int64_t wt0 = wtb + 2 * wave;
-    const int64_t ntiles = (int64_t)a.nxc * a.nzb * a.ny;
+    const int ntiles = a.nxc * a.nzb * a.ny;   // tiles of W (at most a few million)
     const u32x4* gw = (const u32x4*)a.wtiles;
 
-    // the lane's global pieces of the five fill passes (the fifth only on wave 0)
-    int src[PW_COPY + 1];
+    // the lane's byte offsets for the five tile passes (the fifth only on wave 0) and
+    // for the Ty rows (wave 1): wave tile wtb + lane / 8, piece lane % 8, at one y
+    uint32_t src[PW_COPY + 2];
 #pragma unroll
-    for (int c = 0; c < PW_COPY; ++c) src[c] = pw_src_piece(c * PW_THREADS + tid);
-    src[PW_COPY] = pw_src_piece(PW_COPY * PW_THREADS + lane);
+    for (int c = 0; c < PW_COPY; ++c) src[c] = pw_src_bytes(c * PW_THREADS + tid);
+    src[PW_COPY] = pw_src_bytes(PW_COPY * PW_THREADS + lane);
+    src[PW_COPY + 1] = (uint32_t)(((lane >> 3) * a.ny * 2 * WAVE_PIX + (lane & 7) * 4) * sizeof(float));
     pw_fill(a, wtb, 0, 0, gw, lds, src);
     float* accl = accs + wave * 32 * 64 + lane;
 #pragma unroll
@@ -712,7 +714,7 @@ __device__ __forceinline__ void fwd_pair_block(const FwdArgs& a, int64_t block, 
     __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
     __syncthreads();
 
-    int64_t t = 0;
+    int t = 0;
     for (int xc = 0; xc < a.nxc; ++xc) {
         const int xlen = min(XC, a.x_pad - xc * XC);
         f32x4 Af[16];

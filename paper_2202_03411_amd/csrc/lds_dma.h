@@ -32,6 +32,23 @@ __device__ __forceinline__ void lds_dma16(const void* src, uint8_t* dst_wave)
                  : "v"(src), "s"(m0)
                  : "memory", "m0");
 }
+// The same from a wave-uniform base (scalar registers) plus a 32-bit per-lane byte
+// offset, so that no 64-bit address is formed per lane.
+__device__ __forceinline__ void lds_dma16_s(const void* sbase, uint32_t voff, uint8_t* dst_wave)
+{
+    const uint32_t m0 = __builtin_amdgcn_readfirstlane(
+        (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t*)dst_wave);
+    // (readfirstlane returns a signed int: widen through uint32_t, or a low word with
+    // bit 31 set would be sign-extended into the high word)
+    const uint64_t p = (uint64_t)(uintptr_t)sbase;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)p);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(p >> 32));
+    const uint64_t base = ((uint64_t)hi << 32) | (uint64_t)lo;
+    asm volatile("s_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, %1"
+                 :
+                 : "v"(voff), "s"(base), "s"(m0)
+                 : "memory", "m0");
+}
 #pragma clang diagnostic pop
 
 }  // namespace msft
