@@ -469,13 +469,13 @@ __global__ __launch_bounds__(SG_THREADS, 2) void sepg_stage2_kernel(SepG3Args a)
 //   K(i, y, z) = sum_j exp(-i q_y(j) y) [h(i, j) exp(-i q_z(i, j) z)]   (pass 1)
 //   R(x, y, z) = sum_i exp(-i q_x(i) x) K(i, y, z)                      (pass 2)
 // Pass 1 (v_mfma_f32_16x16x4_f32): rows are a wave's 16 y, columns 16 z, K four
-// rows j; a workgroup takes 64 y, SGA_COLS columns i and one z block, loads the
-// next chunk's Tz (direct global -> LDS loads) and h under the current chunk's
-// MFMAs, then forms its B tiles h Tz (three planes) in LDS, and writes K as three
-// planes of [i][y][z] floats (16 lanes store
-// 16 consecutive z).  Pass 2 (sepg_adj_cols_kernel) has the shape of stage 1 with
-// rows x and K over the columns i, split in two halves whose partial sums the
-// column walk adds.
+// rows j; a workgroup takes 64 y, SGA_COLS columns i and one z block.  Each thread
+// loads its own Tz and h for the chunk after next into registers, and forms the
+// next chunk's B tiles h Tz (three planes) into the other LDS buffer between the
+// current chunk's MFMAs, one barrier per chunk; K goes out as two planes Kr, Ki of
+// [i][y][z] floats (16 lanes store 16 consecutive z).  Pass 2 (sepg_adj_cols_kernel)
+// has the shape of stage 1 with rows x and K over the columns i, split in two
+// halves whose partial sums the column walk adds.
 // ---------------------------------------------------------------------------
 constexpr int SGA_COLS = 2;
 
@@ -483,12 +483,16 @@ constexpr int SGA_COLS = 2;
 // layout, j in place of y; column c at tiles + c G3_TILE_BYTES) with the wave's A
 // operand for that chunk: Af[2 plane + g], step 4 g + e.  Groups (column, g, plane)
 // of eight MFMAs; the next group's B fragments are read from LDS before the current
-// group's MFMAs are issued.
-template <int NC>
+// group's MFMAs are issued.  form(c) (the next chunk's B tiles of column c, into the
+// other LDS buffer: VALU work and three LDS stores) is spread between the MFMAs of
+// the groups FORM0 and FORM1 - 1.
+template <int NC, bool FORM, class Form>
 __device__ __forceinline__ void sga_tiles(const uint8_t* tiles, int kk, int n16, const f32x4 (&Af)[6],
-                                          f32x4 (&P)[SGA_COLS][3][2])
+                                          f32x4 (&P)[SGA_COLS][3][2], Form&& form)
 {
     constexpr int NG = NC * 6;
+    constexpr int FORM0 = 2, FORM1 = 8;
+    static_assert(NG > FORM1, "two groups to hide the forming under");
     const uint8_t* base = tiles + kk * 1024 + n16 * 16;
     // group k: column k / 6, g = (k / 3) % 2, plane k % 3
     auto frag = [&](int k, int nt) {
@@ -503,6 +507,19 @@ __device__ __forceinline__ void sga_tiles(const uint8_t* tiles, int kk, int n16,
         if (k + 1 < NG) {
             b[(k + 1) & 1][0] = frag(k + 1, 0);
             b[(k + 1) & 1][1] = frag(k + 1, 1);
+        }
+        if (FORM && (k == FORM0 || k == FORM1)) {
+            // this region holds group k - 1's MFMAs, group k + 1's reads and one
+            // column's forming: reads first, then one MFMA per three VALU operations,
+            // the stores last
+            form(k == FORM0 ? 0 : 1);
+            __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);
+            }
+            __builtin_amdgcn_sched_group_barrier(0x200, 3, 0);
         }
         // keep the next group's reads ahead of this group's MFMAs
         __builtin_amdgcn_sched_barrier(0);
@@ -523,8 +540,6 @@ __device__ __forceinline__ void sga_tiles(const uint8_t* tiles, int kk, int n16,
 __global__ __launch_bounds__(SG_THREADS, 2) void sepg_adj_rows_kernel(SepG3AdjArgs a)
 {
     __shared__ __attribute__((aligned(16))) uint8_t lds[2 * SGA_COLS * G3_TILE_BYTES];
-    __shared__ __attribute__((aligned(16))) uint8_t tzs[SGA_COLS * 2 * 4096];   // Tz of the next chunk
-    __shared__ __attribute__((aligned(16))) uint8_t hs[32 * 16];                // h of the next chunk
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -544,90 +559,90 @@ __global__ __launch_bounds__(SG_THREADS, 2) void sepg_adj_rows_kernel(SepG3AdjAr
 #pragma unroll
         for (int p = 0; p < 3; ++p) P[c][p][0] = P[c][p][1] = f32x4{};
     if (ncol > 0) {
-        // Tz of chunk jc into LDS by direct loads: per column c the 16-row tiles
-        // w16 = i (npad / 16) + 2 jc + w (w = 0, 1), each a contiguous block (hp, z, m)
-        // of 4 KiB holding row 4 (m / 2) + 2 hp + m % 2 at z; four pieces per thread
-        // (a column beyond the detector loads the last one, and gets zero tiles)
-        auto fill_tz = [&](int jc) {
-#pragma unroll
-            for (int p = 0; p < 2 * SGA_COLS; ++p) {
-                const int c = p >> 1, w = p & 1;
-                const int64_t i = min(i0 + c, a.n - 1);
-                const int64_t w16 = i * (a.npad / SG2_ROWS) + 2 * jc + w;
-                lds_dma16((const u32x4*)(a.tz + 2 * (w16 * a.nzb + zb) * (2 * ZB * 8)) + wave * 64 + lane,
-                          tzs + p * 4096 + wave * 1024);
-            }
-        };
-        // h of chunk jc for the columns i0, i0 + 1: row j = 32 jc + t as one 16-byte
-        // piece, loaded by thread t < 32 (row clamped into the detector; form_b zeroes
-        // the rows and columns beyond it)
-        auto load_h = [&](int jc, u32x4& v) {
-            if (tid < 32) v = *(const u32x4*)((const float2*)a.h + (int64_t)min(32 * jc + tid, a.n - 1) * a.n + i0);
-        };
-        // B = h Tz of chunk jc in three planes, rows j = 8 fk + 4 fg + e of the tile at
-        // z = fz: Tz row 8 fk + 4 fg + e sits in block w = fk / 2 at hp = e / 2,
-        // m = 4 (fk % 2) + 2 fg + e % 2
-        auto form_b = [&](int jc, uint8_t* slot) {
+        // the thread's Tz of chunk jc, straight into registers: per column c the
+        // 16-row tile w16 = i (npad / 16) + 2 jc + fk / 2 is a contiguous block
+        // (hp, z, m) of 4 KiB holding row 4 (m / 2) + 2 hp + m % 2 at z, so rows
+        // 8 fk + 4 fg + e sit at hp = e / 2, m = 4 (fk % 2) + 2 fg + e % 2: one 16-byte
+        // piece per hp (a column beyond the detector loads the last one; its h is
+        // taken as zero)
+        auto load_tz = [&](int jc, f32x4 (&tz)[SGA_COLS][2]) {
 #pragma unroll
             for (int c = 0; c < SGA_COLS; ++c) {
-                f32x4 tz[2];
+                const int64_t w16 = (int64_t)min(i0 + c, a.n - 1) * (a.npad / SG2_ROWS) + 2 * jc + (fk >> 1);
+                const float* blk = a.tz + (w16 * a.nzb + zb) * (2 * 2 * ZB * 8);
 #pragma unroll
                 for (int hp = 0; hp < 2; ++hp)
-                    tz[hp] = *(const f32x4*)(tzs + (c * 2 + (fk >> 1)) * 4096 +
-                                             ((hp * ZB + fz) * 8 + 4 * (fk & 1) + 2 * fg) * 8);
-                f32x4 br, bi, bs;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const bool in = 32 * jc + 8 * fk + 4 * fg + e < a.n && c < ncol;
-                    const float2 hv = *(const float2*)(hs + (8 * fk + 4 * fg + e) * 16 + c * 8);
-                    const float hr = in ? hv.x : 0.0f, hi = in ? hv.y : 0.0f;
-                    const float tr = tz[e >> 1][2 * (e & 1)], ti = tz[e >> 1][2 * (e & 1) + 1];
-                    br[e] = hr * tr - hi * ti;
-                    bi[e] = hr * ti + hi * tr;
-                    bs[e] = br[e] + bi[e];
-                }
-                uint8_t* q = slot + c * G3_TILE_BYTES + ((fk * 2 + fg) * 32 + fz) * 16;
-                *(f32x4*)q = br;
-                *(f32x4*)(q + SG_PLANE_BYTES) = bi;
-                *(f32x4*)(q + 2 * SG_PLANE_BYTES) = bs;
+                    tz[c][hp] = *(const f32x4*)(blk + ((hp * ZB + fz) * 8 + 4 * (fk & 1) + 2 * fg) * 2);
             }
         };
+        // h of the thread's rows j = 32 jc + 8 fk + 4 fg + e for the columns i0, i0 + 1,
+        // one 16-byte piece per row (the row clamped into the detector; form_b zeroes
+        // the rows and columns beyond it)
+        auto load_h = [&](int jc, u32x4 (&hv)[4]) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                hv[e] = *(const u32x4*)((const float2*)a.h + (int64_t)min(32 * jc + 8 * fk + 4 * fg + e, a.n - 1) * a.n + i0);
+        };
+        // column c of B = h Tz for chunk jc in three planes, rows j = 8 fk + 4 fg + e of
+        // the tile at z = fz
+        auto form_b = [&](int jc, int c, const f32x4 (&tz)[SGA_COLS][2], const u32x4 (&hv)[4], uint8_t* slot) {
+            f32x4 br, bi, bs;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const bool in = 32 * jc + 8 * fk + 4 * fg + e < a.n && c < ncol;
+                const float hr = in ? __uint_as_float(hv[e][2 * c]) : 0.0f;
+                const float hi = in ? __uint_as_float(hv[e][2 * c + 1]) : 0.0f;
+                const float tr = tz[c][e >> 1][2 * (e & 1)], ti = tz[c][e >> 1][2 * (e & 1) + 1];
+                br[e] = hr * tr - hi * ti;
+                bi[e] = hr * ti + hi * tr;
+                bs[e] = br[e] + bi[e];
+            }
+            uint8_t* q = slot + c * G3_TILE_BYTES + ((fk * 2 + fg) * 32 + fz) * 16;
+            *(f32x4*)q = br;
+            *(f32x4*)(q + SG_PLANE_BYTES) = bi;
+            *(f32x4*)(q + 2 * SG_PLANE_BYTES) = bs;
+        };
+        auto buf = [&](int jc) { return lds + (jc & 1) * SGA_COLS * G3_TILE_BYTES; };
         const f32x4* ta = (const f32x4*)a.tyT + (size_t)yt * a.njc2 * 6 * 64 + lane;
-        f32x4 Ac[6];
+        // two register sets, taking turns: A operand of the chunk in flight, and Tz
+        // and h of the chunk after it
+        f32x4 AcA[6], AcB[6], tzA[SGA_COLS][2], tzB[SGA_COLS][2];
+        u32x4 hA[4], hB[4];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) Ac[q] = ta[q * 64];
-        u32x4 hv = {};
-        fill_tz(0);
-        load_h(0, hv);
-        __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
-        if (tid < 32) *(u32x4*)(hs + tid * 16) = hv;
+        for (int q = 0; q < 6; ++q) AcA[q] = ta[q * 64];
+        load_tz(0, tzA);
+        load_h(0, hA);
+#pragma unroll
+        for (int c = 0; c < SGA_COLS; ++c) form_b(0, c, tzA, hA, buf(0));
+        load_tz(min(1, a.njc2 - 1), tzA);
+        load_h(min(1, a.njc2 - 1), hA);
         __syncthreads();
-        form_b(0, lds);
-        __syncthreads();
-        // step jc: Tz and h of chunk jc + 1 are loaded under chunk jc's MFMAs, then
-        // chunk jc + 1's tiles are formed into the other LDS buffer
-        for (int jc = 0; jc < a.njc2; ++jc) {
-            const bool more = jc + 1 < a.njc2;
-            f32x4 An[6];
-            if (more) {
-                fill_tz(jc + 1);
-                load_h(jc + 1, hv);
+        // chunk jc's MFMAs (A operand Acur), chunk jc + 1's tiles formed under them from
+        // tzc, hc into the other buffer (last read before the previous barrier); the
+        // loads for the next step go out first: chunk jc + 1's A operand into Anext,
+        // chunk jc + 2's Tz and h (clamped to the last chunk, so every path issues the
+        // same loads) into tzn, hn
+        auto step = [&](int jc, const f32x4 (&Acur)[6], f32x4 (&Anext)[6], const f32x4 (&tzc)[SGA_COLS][2],
+                        const u32x4 (&hc)[4], f32x4 (&tzn)[SGA_COLS][2], u32x4 (&hn)[4]) {
 #pragma unroll
-                for (int q = 0; q < 6; ++q) An[q] = ta[((jc + 1) * 6 + q) * 64];
-            }
-            sga_tiles<SGA_COLS>(lds + (jc & 1) * SGA_COLS * G3_TILE_BYTES, kk, n16, Ac, P);
-            if (more) {
-                // Tz landed (the compiler does not track it); h goes to LDS, read by
-                // every wave after the barrier
-                __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
-                if (tid < 32) *(u32x4*)(hs + tid * 16) = hv;
-                __syncthreads();
-                // the other B buffer was last read before the previous barrier
-                form_b(jc + 1, lds + ((jc + 1) & 1) * SGA_COLS * G3_TILE_BYTES);
-                __syncthreads();
-#pragma unroll
-                for (int q = 0; q < 6; ++q) Ac[q] = An[q];
-            }
+            for (int q = 0; q < 6; ++q) Anext[q] = ta[((jc + 1) * 6 + q) * 64];
+            const int jn = min(jc + 2, a.njc2 - 1);
+            load_tz(jn, tzn);
+            load_h(jn, hn);
+            sga_tiles<SGA_COLS, true>(buf(jc), kk, n16, Acur, P,
+                                      [&](int c) { form_b(jc + 1, c, tzc, hc, buf(jc + 1)); });
+            __syncthreads();
+        };
+        int jc = 0;
+        for (; jc + 2 < a.njc2; jc += 2) {
+            step(jc, AcA, AcB, tzA, hA, tzB, hB);
+            step(jc + 1, AcB, AcA, tzB, hB, tzA, hA);
+        }
+        if (jc + 1 < a.njc2) {
+            step(jc, AcA, AcB, tzA, hA, tzB, hB);
+            sga_tiles<SGA_COLS, false>(buf(jc + 1), kk, n16, AcB, P, [&](int) {});
+        } else {
+            sga_tiles<SGA_COLS, false>(buf(jc), kk, n16, AcA, P, [&](int) {});
         }
     }
     // K = (P1 - P2) + i (P3 - P1 - P2), planes Kr, Ki of [i][y][z2] floats (pass 2

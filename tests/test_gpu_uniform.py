@@ -152,12 +152,14 @@ def test_uniform_repeatable(env):
 
 
 @pytest.mark.parametrize("grid,det,pitch", [((30, 26, 35), 24, (9.0, 8.0, 7.0)),
+                                             ((22, 30, 18), 37, (7.0, 6.0, 8.0)),
                                              ((10, 140, 20), 37, (6.0, 5.0, 7.0))],
-                         ids=["three_product", "tall_y"])
+                         ids=["three_product", "three_product_odd_side", "tall_y"])
 def test_uniform_backward_matches_oracle(env, grid, det, pitch):
     # the separable adjoint on ragged uniform-q plans (pixels beyond the rim carry
-    # A = 0, N not a multiple of the column chunk); more than 128 rows y take FP32
-    # out of the three-product form
+    # A = 0, N not a multiple of the column chunk, an odd N whose last column pair
+    # holds one column, two row chunks); more than 128 rows y take FP32 out of the
+    # three-product form
     torch, msft = env
     d, b = _field(grid, 58)
     g = np.random.default_rng(59).normal(size=det * det)
