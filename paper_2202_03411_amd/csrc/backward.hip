@@ -10,7 +10,7 @@
 //                pixel chunk into LDS from FP64 phases, not read from the plan.
 //  adj_finalize  sums the pixel groups in a fixed order and applies the chain
 //                rule through w = dV (n^2 - 1) T and the column scan (Eqs. (7)-(9)),
-//                one wave per column.
+//                one wave per column (adj_finalize_k: up to 4 slices per lane).
 #include <hip/hip_runtime.h>
 
 #include "msft_internal.h"
@@ -307,6 +307,115 @@ __global__ __launch_bounds__(256) void adj_finalize(FinArgs a)
     }
 }
 
+// The same chain rule for columns of at most 64 K slices: lane l holds slices
+// K l .. K l + K - 1 of one column, so a single FP64 wave scan per quantity (the
+// lanes' own sums of beta, delta, then of R w) and the lane's running sums over its
+// slices give every prefix and suffix; loads and stores stay contiguous over the
+// wave.
+template <int K>
+__global__ __launch_bounds__(256) void adj_finalize_k(FinArgs a)
+{
+    constexpr double kTwoPi = 6.283185307179586476925286766559;
+    const int lane = threadIdx.x & 63;
+    const int64_t col = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (col >= (int64_t)a.nx * a.ny) return;   // wave-uniform
+    const int x = (int)(col / a.ny), y = (int)(col % a.ny);
+    const float* dcol = a.delta + col * a.nz;
+    const float* bcol = a.beta + col * a.nz;
+    const int64_t X2 = (int64_t)a.nxc * XC, NZ2 = (int64_t)a.nzb * ZB;
+    const int64_t part_stride = X2 * a.ny * NZ2;
+    const float2* rp = (const float2*)a.rpart + ((int64_t)x * a.ny + y) * NZ2;
+    const double dV = a.dV, k0dz = a.k0dz;
+    double d[K], bt[K], rr[K], ri[K];
+    double lb = 0.0, ld = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int c = K * lane + k;
+        const bool in = c < a.nz;
+        d[k] = in ? (double)dcol[c] : 0.0;
+        bt[k] = in ? (double)bcol[c] : 0.0;
+        rr[k] = ri[k] = 0.0;
+        if (in)
+            for (int s = 0; s < a.nsplit; ++s) {
+                const float2 v = rp[s * part_stride + c];
+                rr[k] += v.x;
+                ri[k] += v.y;
+            }
+        lb += bt[k];
+        ld += d[k];
+    }
+    const double SB = suffix_sum(lb, lane), SD = suffix_sum(ld, lane);
+    const double tot_b = __shfl(SB, 0, 64), tot_d = __shfl(SD, 0, 64);
+    double gd[K], gb[K], rwr[K], rwi[K];
+    // inclusive suffix of beta, delta at the lane's slice k: the later lanes, then
+    // the lane's slices from its last down to k
+    double ub = SB - lb, ud = SD - ld;
+#pragma unroll
+    for (int k = K - 1; k >= 0; --k) {
+        ub += bt[k];
+        ud += d[k];
+        gd[k] = gb[k] = rwr[k] = rwi[k] = 0.0;
+        if (a.strength == MSFT_STRENGTH_DENSITY) {
+            gd[k] = 2.0 * dV * rr[k];
+            gb[k] = -2.0 * dV * ri[k];
+        } else {
+            double tr = 1.0, ti = 0.0;
+            if (a.strength == MSFT_STRENGTH_MSFT) {
+                // T = exp(-k0 dz S) in FP32, as the forward scan forms it: the prefix
+                // sums stay FP64 and the phase is reduced to [-pi, pi] in FP64 first
+                const double sb = tot_b - ub, sd = tot_d - ud;
+                const double ph = -k0dz * sd;
+                const double phr = ph - kTwoPi * rint(ph * (1.0 / kTwoPi));
+                const float mag = expf((float)(-k0dz * sb));
+                float sn, cs;
+                sincosf((float)phr, &sn, &cs);
+                tr = (double)mag * (double)cs;
+                ti = (double)mag * (double)sn;
+            }
+            const double nr = 1.0 - d[k], ni = bt[k];
+            // dw/d delta = dV T (-2 n), dw/d beta = dV T (2 i n)
+            const double dd_r = dV * (-2.0) * (tr * nr - ti * ni);
+            const double dd_i = dV * (-2.0) * (tr * ni + ti * nr);
+            const double db_r = dV * 2.0 * (-(tr * ni + ti * nr));
+            const double db_i = dV * 2.0 * (tr * nr - ti * ni);
+            gd[k] = 2.0 * (rr[k] * dd_r - ri[k] * dd_i);
+            gb[k] = 2.0 * (rr[k] * db_r - ri[k] * db_i);
+            if (a.strength == MSFT_STRENGTH_MSFT) {
+                const double chr = d[k] * (d[k] - 2.0) - bt[k] * bt[k], chi = 2.0 * bt[k] * (1.0 - d[k]);
+                const double wr = dV * (chr * tr - chi * ti), wi = dV * (chr * ti + chi * tr);
+                rwr[k] = rr[k] * wr - ri[k] * wi;
+                rwi[k] = rr[k] * wi + ri[k] * wr;
+            }
+        }
+    }
+    if (a.strength == MSFT_STRENGTH_MSFT) {
+        double lr = 0.0, li = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            lr += rwr[k];
+            li += rwi[k];
+        }
+        const double SR = suffix_sum(lr, lane), SI = suffix_sum(li, lane);
+        // sum over s' > s: the later lanes, then the lane's slices after k
+        double er = SR - lr, ei = SI - li;
+#pragma unroll
+        for (int k = K - 1; k >= 0; --k) {
+            gd[k] += 2.0 * k0dz * ei;
+            gb[k] -= 2.0 * k0dz * er;
+            er += rwr[k];
+            ei += rwi[k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int c = K * lane + k;
+        if (c < a.nz) {
+            a.grad_delta[col * a.nz + c] = (float)gd[k];
+            a.grad_beta[col * a.nz + c] = (float)gb[k];
+        }
+    }
+}
+
 int launch_adj_prep(const float* amplitude, const float* grad_intensity, float* h, int64_t npix,
                     int64_t npix_pad, void* stream)
 {
@@ -319,8 +428,12 @@ int launch_adj_prep(const float* amplitude, const float* grad_intensity, float* 
 int launch_adj_finalize(const FinArgs& fin, void* stream)
 {
     const int64_t ncol = (int64_t)fin.nx * fin.ny;
-    hipLaunchKernelGGL(adj_finalize, dim3((unsigned)ceil_div(ncol, 4)), dim3(256), 0,
-                       (hipStream_t)stream, fin);
+    const dim3 grid((unsigned)ceil_div(ncol, 4));
+    hipStream_t s = (hipStream_t)stream;
+    if (fin.nz <= 64) hipLaunchKernelGGL(adj_finalize_k<1>, grid, dim3(256), 0, s, fin);
+    else if (fin.nz <= 128) hipLaunchKernelGGL(adj_finalize_k<2>, grid, dim3(256), 0, s, fin);
+    else if (fin.nz <= 256) hipLaunchKernelGGL(adj_finalize_k<4>, grid, dim3(256), 0, s, fin);
+    else hipLaunchKernelGGL(adj_finalize, grid, dim3(256), 0, s, fin);
     return (int)hipGetLastError();
 }
 
@@ -333,9 +446,8 @@ int launch_backward(const AdjArgs& adj, const FinArgs& fin, const float* amplitu
                        (const float2*)amplitude, grad_intensity, (float2*)adj.h, adj.npix, np);
     const int64_t nblocks = (int64_t)adj.nsplit * adj.nxc * adj.nzb * adj.nyb;
     hipLaunchKernelGGL(adj_contract, dim3((unsigned)nblocks), dim3(512), 0, s, adj);
-    const int64_t ncol = (int64_t)fin.nx * fin.ny;
-    hipLaunchKernelGGL(adj_finalize, dim3((unsigned)ceil_div(ncol, 4)), dim3(256), 0, s, fin);
-    return (int)hipGetLastError();
+    const int e = (int)hipGetLastError();
+    return e ? e : launch_adj_finalize(fin, stream);
 }
 
 }  // namespace msft

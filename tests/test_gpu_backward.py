@@ -45,6 +45,12 @@ CASES = [
     ("xchunks_born", (150, 5, 33), 20, (3.0, 9.0, 8.0), "born", inputs.MODE_BORN, 2),
     ("density", (20, 17, 40), 30, (8.0, 8.0, 8.0), "density", inputs.MODE_DENSITY, 3),
     ("tiny", (1, 1, 1), 1, (10.0, 10.0, 10.0), "msft", inputs.MODE_MSFT, 4),
+    # columns of 65-128, 129-256 and more than 256 slices: two and four slices per
+    # lane of the column walk, and its segmented form
+    ("deep100_msft", (8, 7, 100), 16, (9.0, 8.0, 7.0), "msft", inputs.MODE_MSFT, 5),
+    ("deep200_msft", (6, 5, 200), 16, (9.0, 8.0, 7.0), "msft", inputs.MODE_MSFT, 6),
+    ("deep130_density", (5, 4, 130), 12, (8.0, 8.0, 8.0), "density", inputs.MODE_DENSITY, 7),
+    ("deep300_msft", (4, 3, 300), 12, (9.0, 8.0, 7.0), "msft", inputs.MODE_MSFT, 8),
 ]
 
 
