@@ -307,11 +307,44 @@ __global__ __launch_bounds__(256) void adj_finalize(FinArgs a)
     }
 }
 
+// One DPP step on an FP64 value (both 32-bit halves moved by the same lane pattern;
+// lanes outside the row mask, or whose source lies outside their row, read 0).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, ROW_MASK, 0xF, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, ROW_MASK, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | (unsigned long long)lo));
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave in FP64, in registers: doubling
+// steps inside each row of 16 lanes (row_shr 1, 2, 4, 8), then the row totals carried
+// up (lane 15 of rows 0 and 2 into rows 1 and 3, then lane 31 into rows 2 and 3).
+__device__ __forceinline__ double wave_prefix_f64(double v)
+{
+    v += dpp_f64<0x111, 0xF>(v);
+    v += dpp_f64<0x112, 0xF>(v);
+    v += dpp_f64<0x114, 0xF>(v);
+    v += dpp_f64<0x118, 0xF>(v);
+    v += dpp_f64<0x142, 0xA>(v);
+    v += dpp_f64<0x143, 0xC>(v);
+    return v;
+}
+
+// Lane 63's value, in every lane.
+__device__ __forceinline__ double last_lane_f64(double v)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, 63);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), 63);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | (unsigned long long)lo));
+}
+
 // The same chain rule for columns of at most 64 K slices: lane l holds slices
-// K l .. K l + K - 1 of one column, so a single FP64 wave scan per quantity (the
-// lanes' own sums of beta, delta, then of R w) and the lane's running sums over its
-// slices give every prefix and suffix; loads and stores stay contiguous over the
-// wave.
+// K l .. K l + K - 1 of one column, so one FP64 wave prefix per quantity (the lanes'
+// own sums of beta, delta, then of R w) and the lane's running sums over its slices
+// give every prefix and suffix; loads and stores stay contiguous over the wave.
 template <int K>
 __global__ __launch_bounds__(256) void adj_finalize_k(FinArgs a)
 {
@@ -344,16 +377,12 @@ __global__ __launch_bounds__(256) void adj_finalize_k(FinArgs a)
         lb += bt[k];
         ld += d[k];
     }
-    const double SB = suffix_sum(lb, lane), SD = suffix_sum(ld, lane);
-    const double tot_b = __shfl(SB, 0, 64), tot_d = __shfl(SD, 0, 64);
+    // exclusive prefix S = sum_{s'<s} (beta + i delta): the earlier lanes, then the
+    // lane's slices before k
+    double sb = wave_prefix_f64(lb) - lb, sd = wave_prefix_f64(ld) - ld;
     double gd[K], gb[K], rwr[K], rwi[K];
-    // inclusive suffix of beta, delta at the lane's slice k: the later lanes, then
-    // the lane's slices from its last down to k
-    double ub = SB - lb, ud = SD - ld;
 #pragma unroll
-    for (int k = K - 1; k >= 0; --k) {
-        ub += bt[k];
-        ud += d[k];
+    for (int k = 0; k < K; ++k) {
         gd[k] = gb[k] = rwr[k] = rwi[k] = 0.0;
         if (a.strength == MSFT_STRENGTH_DENSITY) {
             gd[k] = 2.0 * dV * rr[k];
@@ -363,7 +392,6 @@ __global__ __launch_bounds__(256) void adj_finalize_k(FinArgs a)
             if (a.strength == MSFT_STRENGTH_MSFT) {
                 // T = exp(-k0 dz S) in FP32, as the forward scan forms it: the prefix
                 // sums stay FP64 and the phase is reduced to [-pi, pi] in FP64 first
-                const double sb = tot_b - ub, sd = tot_d - ud;
                 const double ph = -k0dz * sd;
                 const double phr = ph - kTwoPi * rint(ph * (1.0 / kTwoPi));
                 const float mag = expf((float)(-k0dz * sb));
@@ -387,6 +415,8 @@ __global__ __launch_bounds__(256) void adj_finalize_k(FinArgs a)
                 rwi[k] = rr[k] * wi + ri[k] * wr;
             }
         }
+        sb += bt[k];
+        sd += d[k];
     }
     if (a.strength == MSFT_STRENGTH_MSFT) {
         double lr = 0.0, li = 0.0;
@@ -395,9 +425,10 @@ __global__ __launch_bounds__(256) void adj_finalize_k(FinArgs a)
             lr += rwr[k];
             li += rwi[k];
         }
-        const double SR = suffix_sum(lr, lane), SI = suffix_sum(li, lane);
-        // sum over s' > s: the later lanes, then the lane's slices after k
-        double er = SR - lr, ei = SI - li;
+        const double pr = wave_prefix_f64(lr), pi = wave_prefix_f64(li);
+        // sum over s' > s: the later lanes (column total minus the inclusive prefix),
+        // then the lane's slices after k
+        double er = last_lane_f64(pr) - pr, ei = last_lane_f64(pi) - pi;
 #pragma unroll
         for (int k = K - 1; k >= 0; --k) {
             gd[k] += 2.0 * k0dz * ei;
