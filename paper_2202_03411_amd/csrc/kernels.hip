@@ -937,6 +937,7 @@ constexpr int SP_THREADS = 64 * SP_WAVES;
 constexpr int SP_ROWS = SP_WAVES * WAVE_PIX;                  // 64 rows j per workgroup
 constexpr int SP_STAGE = 2 * TILE_BYTES;                      // both y chunks
 constexpr int SP_COPY = SP_STAGE / 16 / SP_THREADS;           // 8 pieces per thread, 4 per tile
+constexpr int SP_TZ_READ = 4;                                 // stage 2: Tz table read every 4 z blocks
 static_assert(SP_COPY * SP_THREADS * 16 == SP_STAGE && (TILE_BYTES / 16) % 64 == 0, "whole wave pieces");
 
 // ---------------------------------------------------------------------------
@@ -1230,6 +1231,7 @@ template <int PREC, int CPW>
 __global__ __launch_bounds__(SP_THREADS, 2) void sep_stage2p_kernel(FwdArgs a)
 {
     __shared__ __attribute__((aligned(16))) uint8_t lds[2 * SP_STAGE];
+    __shared__ f32x4 rzs[SP_THREADS * 4];   // per thread: exp(-i q_z 32 dz) of its 8 rows
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1259,11 +1261,44 @@ __global__ __launch_bounds__(SP_THREADS, 2) void sep_stage2p_kernel(FwdArgs a)
         float acc[16];
 #pragma unroll
         for (int q = 0; q < 16; ++q) acc[q] = 0.0f;
-        for (int zb = 0; zb < nzb; ++zb) {
-            const f32x4* tzp = (const f32x4*)(a.tz + 2 * ((((wt * nzb + zb) * 2 + h) * ZB + col) * 8));
-            f32x4 tzv[4];
+        // Tz of the lane's 8 rows at its z: read from the plan's table every SP_TZ_READ z
+        // blocks and rotated by rz = exp(-i q_z 32 dz) = Tz(block 1) conj(Tz(block 0))
+        // in between (a quarter of the table's traffic; at most SP_TZ_READ - 1 FP32
+        // rotations from a table value)
+        const float* tzc = a.tz + 2 * (((wt * nzb * 2 + h) * ZB + col) * 8);
+        const int64_t tz_block = 2 * 2 * ZB * 8;   // floats per z block
+        // (the thread's rz lives in its own LDS slot: registers are full)
+        f32x4* rzt = rzs + tid * 4;
+        if (nzb > 1) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) tzv[q] = tzp[q];
+            for (int q = 0; q < 4; ++q) {
+                const f32x4 t0 = ((const f32x4*)tzc)[q], t1 = ((const f32x4*)(tzc + tz_block))[q];
+                f32x4 r;
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    r[2 * u] = t1[2 * u] * t0[2 * u] + t1[2 * u + 1] * t0[2 * u + 1];
+                    r[2 * u + 1] = t1[2 * u + 1] * t0[2 * u] - t1[2 * u] * t0[2 * u + 1];
+                }
+                rzt[q] = r;
+            }
+        }
+        f32x4 tzv[4];
+        for (int zb = 0; zb < nzb; ++zb) {
+            if (zb % SP_TZ_READ == 0) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) tzv[q] = ((const f32x4*)(tzc + zb * tz_block))[q];
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const f32x4 r = rzt[q];
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        const float tr = tzv[q][2 * u], ti = tzv[q][2 * u + 1];
+                        tzv[q][2 * u] = tr * r[2 * u] - ti * r[2 * u + 1];
+                        tzv[q][2 * u + 1] = tr * r[2 * u + 1] + ti * r[2 * u];
+                    }
+                }
+            }
             if (zb + 1 < nzb) sp_fill(a, i, zb + 1, wave, lds + ((s + 1) & 1) * SP_STAGE);
             else if (c + 1 < ncol) sp_fill(a, i + 1, 0, wave, lds + ((s + 1) & 1) * SP_STAGE);
             const uint8_t* cur = lds + (s & 1) * SP_STAGE + (h * ZB + col) * ROW_BYTES;
