@@ -69,6 +69,8 @@ SMALL = [
     ("two_blocks", (24, 24, 24), 150, (10.0, 10.0, 10.0), inputs.MODE_BORN, 53, 30.0),
     ("tiny", (1, 1, 1), 1, (10.0, 10.0, 10.0), inputs.MODE_MSFT, 54, 60.0),
     ("thin_z", (9, 70, 3), 31, (6.0, 5.0, 12.0), inputs.MODE_DENSITY, 55, 80.0),
+    # six z blocks: BF16 stage 2 reads the Tz table at blocks 0 and 4 and rotates between
+    ("deep_z", (12, 10, 170), 20, (8.0, 8.0, 6.0), inputs.MODE_MSFT, 57, 60.0),
     # more than 128 rows y: FP32 leaves the three-product form for the four-product one
     ("tall_y", (10, 140, 20), 24, (6.0, 5.0, 7.0), inputs.MODE_MSFT, 56, 60.0),
 ]
