@@ -236,6 +236,19 @@ constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_ZROUND = 4;   // z blocks per round, one wave each
 constexpr int SCAN_XB = 32;      // columns per workgroup
 
+// One step of the 8-lane inclusive scans: lane l takes lane l - OFF of its 16-lane row
+// (a DPP row shift, no LDS traffic) and adds it when that lane is in its group.
+template <int OFF>
+__device__ __forceinline__ void scan8_step(float& b, float& d, int zs)
+{
+    const float tb = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(b), 0x110 + OFF, 0xF, 0xF, false));
+    const float td = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(d), 0x110 + OFF, 0xF, 0xF, false));
+    if (zs >= OFF) {
+        b += tb;
+        d += td;
+    }
+}
+
 template <int PREC, bool G3>
 __global__ __launch_bounds__(SCAN_THREADS) void scan_kernel(ScanArgs a)
 {
@@ -287,17 +300,14 @@ __global__ __launch_bounds__(SCAN_THREADS) void scan_kernel(ScanArgs a)
         for (int e = 0; e < 4; ++e) {
             sb[e] = (b[e][0] + b[e][1]) + (b[e][2] + b[e][3]);
             sd[e] = (d[e][0] + d[e][1]) + (d[e][2] + d[e][3]);
-            // inclusive scan over the 8 lanes (z segments) of the column's group
+            // inclusive scan over the 8 lanes (z segments) of the column's group: DPP
+            // shifts inside the 16-lane row; a lane adds only when the source lies in
+            // its own group (zs >= off)
             ib[e] = sb[e];
             id[e] = sd[e];
-#pragma unroll
-            for (int off = 1; off < 8; off <<= 1) {
-                const float tb = __shfl_up(ib[e], off, 8), td = __shfl_up(id[e], off, 8);
-                if (zs >= off) {
-                    ib[e] += tb;
-                    id[e] += td;
-                }
-            }
+            scan8_step<1>(ib[e], id[e], zs);
+            scan8_step<2>(ib[e], id[e], zs);
+            scan8_step<4>(ib[e], id[e], zs);
             if (zs == 7) {
                 tot[0][zr][col_of(e)] = ib[e];
                 tot[1][zr][col_of(e)] = id[e];
